@@ -1,0 +1,211 @@
+/*
+ * hbm.h -- C ABI of the MI355X (gfx950) Metropolis-within-Gibbs sampler for
+ * single-plate hierarchical Bayesian models.
+ *
+ * Method (Szalai-Gindl, Loredo, Kelly, Csabai, Budavari, Dobos -- CUDAHM):
+ * alternate (Sec. 2.1, eqs 2.4/2.5)
+ *   (a) a robust adaptive Metropolis (RAM) update of every object's latent
+ *       vector chi_i given the population parameters theta (Sec. 2.2,
+ *       eq 2.6), the objects being conditionally independent, and
+ *   (b) a Metropolis-Hastings step on theta that consumes the N-term
+ *       population log-likelihood sum_i log f(chi_i; theta) (Sec. 2.2), less
+ *       N ln Z(theta) for flux-selected catalogs (eqs 4.3/4.4, 5.10).
+ *
+ * Every step runs in the library's HIP kernels.  The caller owns the latent
+ * state and the data (device buffers it allocates, e.g. torch tensors); the
+ * library owns only its scratch (per-object derived constants, reduction
+ * partials, quadrature tables, the theta state and its trace), allocated by
+ * init_chains and freed by destroy_chains.
+ *
+ * Conventions for every function below.
+ *   - Return value: HBM_OK (0) or a negative hbm_status.  No exception or
+ *     abort crosses the ABI.  last_error() gives a message for the last
+ *     failure on a context.
+ *   - A validation failure (HBM_EINVAL, HBM_ENOSPACE) leaves the context
+ *     unchanged.  A HIP failure (HBM_EHIP) poisons the context: every later
+ *     call except last_error and destroy_chains returns HBM_ESTATE.
+ *   - Work is enqueued on the hip stream given to init_chains.  Calls that
+ *     return host values synchronise that stream; the others are
+ *     asynchronous.  A context is not thread-safe; distinct contexts on
+ *     distinct streams may run concurrently.
+ *   - Layouts are structure-of-arrays: component j of object i of an array
+ *     with N objects sits at [j * N + i].  Real arrays hold float for
+ *     HBM_FP32 and double for HBM_FP64 (the per-object precision).
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed
+ *     and counter = (object, sweep, tag, block); tag 0 = latent RAM step,
+ *     1 = theta proposal, 2 = theta accept.  A chain is a pure function of
+ *     (data, configuration, seed), independent of launch shape.
+ */
+#ifndef HBM_H
+#define HBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define HBM_API __attribute__((visibility("default")))
+#else
+#define HBM_API
+#endif
+
+typedef struct hbm_ctx hbm_ctx;
+typedef int32_t hbm_status;
+
+#define HBM_OK        0
+#define HBM_EINVAL   -1  /* bad argument, shape or NULL pointer */
+#define HBM_ENOMEM   -2  /* device allocation failed */
+#define HBM_EHIP     -3  /* HIP runtime error; the context is poisoned */
+#define HBM_EDOMAIN  -4  /* non-finite log density, or theta outside the prior support */
+#define HBM_ESTATE   -5  /* poisoned context, or calls in the wrong order */
+#define HBM_ENOSPACE -6  /* sample store full */
+
+/* Models.  Latent coordinates, data columns and theta:
+ *  HBM_NORMAL_NORMAL_1D (Sec. 3 with one heteroscedastic component):
+ *      chi = latent value; data (y_i, sigma_i); theta = (mu, ln tau);
+ *      prior flat in mu, uniform in tau > 0.  Per-object precision FP64.
+ *  HBM_GAMMA_LF_1D (Sec. 4-5, gamma = BB1 with l -> 0, Appendix B):
+ *      chi = ln L; data (Fhat_i, k_i = ln 4 pi r_i^2); theta = (beta, ln L*),
+ *      L ~ Gamma(beta + 1, L*); prior 1/(1+beta^2) on -1 < beta < 0, flat
+ *      in ln L*; selection by Fhat > F_th with noise sigma_F.  FP32.
+ *  HBM_GAMMA_LF_COLOR_3D: chi = (ln L, ln r, c); data (Fhat_i, rhat_i, chat_i);
+ *      theta = (beta, ln L*, a, b, s); c ~ N(a + b ln L, s^2), r with density
+ *      3 r^2 / rmax^3 on (0, rmax]; rhat ~ N(r, (f_r rhat)^2),
+ *      chat ~ N(c, sigma_c^2); prior as 1-D plus flat a, b and uniform s > 0.  FP32.
+ *  HBM_NORMAL_NORMAL_3D (the paper's Sec. 3 instance): chi in R^3,
+ *      chi ~ MVN(mu, C_pop), y_ij ~ N(chi_ij, sigma_j^2), C_pop and sigma
+ *      known; theta = mu, flat prior.  FP64.
+ * model_consts: LF models [0] F_th, [1] sigma_F, [2] rmax, [3] centre ln L0
+ * of the ln L quadrature interval [ln L0 - 30, ln L0 + ln 40], [4] f_r,
+ * [5] sigma_c.  NN3D: [0..5] lower triangle of C_pop (row-major),
+ * [6..8] sigma_j.  NN1D: unused. */
+#define HBM_NORMAL_NORMAL_1D  1
+#define HBM_GAMMA_LF_1D       2
+#define HBM_GAMMA_LF_COLOR_3D 3
+#define HBM_NORMAL_NORMAL_3D  4
+
+#define HBM_FP64 1
+#define HBM_FP32 2
+
+typedef struct hbm_config {
+    int32_t model;               /* HBM_* model id */
+    int32_t precision;           /* HBM_FP64 or HBM_FP32; must match the model */
+    int64_t n_objects;           /* N >= 1 */
+    uint64_t seed;               /* Philox key */
+    double target_accept;        /* alpha* of the latent RAM (paper default 0.4) */
+    double eta_exponent;         /* gamma in eta_n = n^-gamma, 0.5 < gamma <= 1 (paper 2/3) */
+    double s0;                   /* initial latent factor S_1 = s0 I (paper: I) */
+    double theta_target_accept;  /* alpha* of the theta random walk's RAM */
+    int32_t adapt_theta;         /* 1: RAM-adapt the theta proposal factor; 0: keep it */
+    int32_t n_quad;              /* Gauss-Legendre nodes of the selection normaliser (LF: 16..4096) */
+    int32_t thin_chi;            /* latent snapshot after every sweep k with k % thin_chi == 0; 0: none */
+    int32_t reserved;
+    int64_t max_cycles;          /* capacity of the theta trace (and bound on snapshots) */
+    double theta_chol0[25];      /* initial theta proposal factor, p x p lower, row-major */
+    double model_consts[16];
+} hbm_config;
+
+typedef struct hbm_buffers {
+    const void *data;   /* [m][N] model data (device), read only */
+    void *chi;          /* [d][N] latents (device), read/write */
+    void *chol;         /* [d(d+1)/2][N] packed lower RAM factors, row-major (0,0),(1,0),(1,1),... */
+    uint32_t *acc;      /* [N] per-object accepted-move counters (device) */
+    void *chi_samples;  /* [max_cycles / thin_chi][d][N] latent snapshots (device), or NULL */
+} hbm_buffers;
+
+/* Create a sampler (Sec. 2.2: "X_1 with pi(X_1) > 0, S_1 = I").
+ * chi0_host: [d][N] starting latents (copied into buffers->chi), or NULL to
+ * keep what buffers->chi already holds.  theta0: [p] starting theta (host).
+ * Sets chol = s0 I and acc = 0, builds the selection tables, evaluates
+ * Z(theta0), and checks that every log pi_i(chi0_i) is finite
+ * (HBM_EDOMAIN otherwise, first bad index in last_error) and theta0 is in
+ * the prior support (HBM_EDOMAIN).  hip_stream: a hipStream_t or NULL for
+ * the default stream.  On success *out owns library scratch. */
+HBM_API hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, const double *chi0_host,
+                       const double *theta0, void *hip_stream, hbm_ctx **out);
+
+/* n_sweeps RAM sweeps of all latents at the current theta (eq 2.4, eq 2.6).
+ * Sweep k (1-based, counted over the context's life) draws block
+ * (i, k, 0, 0) for object i, proposes Y = X + S U with U ~ N(0, I_d),
+ * accepts when ln u < log pi(Y) - log pi(X), and adapts S with
+ * eta = (k+1)^-gamma.  Each sweep also reduces, in FP64 and in a fixed
+ * order, sum_i log f(chi_i; theta) and sum_i [log f(chi_i; theta') -
+ * log f(chi_i; theta)] for the pending proposal theta', plus Z(theta'),
+ * for the next theta_step.  out_accept_rate (nullable): mean acceptance
+ * of the last sweep; non-NULL makes the call synchronous. */
+HBM_API hbm_status ram_sweep(hbm_ctx *ctx, int32_t n_sweeps, double *out_accept_rate);
+
+/* sum_i log f(chi_i; theta) - N ln Z(theta) at the current latents, FP64
+ * accumulation (the N-term sum a theta MH step consumes).  theta: [p] host.
+ * Synchronous. */
+HBM_API hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out);
+
+/* One Metropolis-Hastings step on theta for the sweep just done: the
+ * pending proposal theta' = theta + S_theta z (z from block (0, k, 1, b)) is
+ * accepted when ln u < Delta (u from block (0, k, 2, 0)),
+ * Delta = sum_i [log f(chi_i; theta') - log f(chi_i; theta)]
+ *         - N [ln Z(theta') - ln Z(theta)] + ln p(theta') - ln p(theta),
+ * Delta = -inf outside the prior support; then S_theta is RAM-adapted and
+ * theta is appended to the trace.  Runs on the device.  Requires a
+ * ram_sweep since the last theta_step (HBM_ESTATE otherwise); HBM_ENOSPACE
+ * when the trace is full.  out_accepted (nullable): 1 if accepted.
+ * Synchronous. */
+HBM_API hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted);
+
+/* n_cycles full cycles (sweep then theta step), with the theta step fused
+ * into the sweep kernel's last workgroup, so no host round trip happens
+ * between cycles; the sequence is replayed from a captured hipGraph when
+ * use_graph != 0.  Results are identical to alternating ram_sweep(1) and
+ * theta_step.  Asynchronous. */
+HBM_API hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph);
+
+/* Copy recorded samples to host.  theta_out: [count][p] rows first..first+count-1
+ * of the theta trace (or NULL).  chi_out: [count][d][N] latent snapshots
+ * first..first+count-1 in the per-object precision (or NULL).  With both NULL
+ * *n_written receives the number of theta rows recorded.  Synchronous. */
+HBM_API hbm_status get_samples(hbm_ctx *ctx, int64_t first, int64_t count, double *theta_out,
+                       void *chi_out, int64_t *n_written);
+
+/* Current theta [p], theta factor [p][p] (either nullable) and sweeps done. */
+HBM_API hbm_status get_theta(hbm_ctx *ctx, double *theta, double *chol_theta, int64_t *k);
+
+/* Overwrite theta, its factor and the sweep counter k (lockstep replay and
+ * resume).  The caller's latent buffers are taken as they are.  Recomputes
+ * Z(theta) and the pending proposal for sweep k + 1.  HBM_EDOMAIN when theta
+ * is outside the prior support. */
+HBM_API hbm_status set_theta(hbm_ctx *ctx, const double *theta, const double *chol_theta, int64_t k);
+
+/* One sweep like ram_sweep that also writes, per object, trace[0][i] =
+ * log pi_i(X), trace[1][i] = log pi_i(Y) (up to model constants shared with
+ * the oracle's definition), trace[2][i] = 1 if accepted else 0, in the
+ * per-object precision; trace is a device buffer [3][N].  Synchronous. */
+HBM_API hbm_status ram_sweep_trace(hbm_ctx *ctx, void *trace);
+
+/* Statistics of the last sweep and theta step: out[0] sum log f(chi; theta),
+ * out[1] sum of per-object log f differences at theta', out[2] ln Z(theta),
+ * out[3] ln Z(theta'), out[4] Delta of the last theta step, out[5] its
+ * acceptance probability, out[6] accepted latent moves of the last sweep,
+ * out[7] theta accepted (0/1).  Synchronous. */
+HBM_API hbm_status get_stats(hbm_ctx *ctx, double out[8]);
+
+/* Per-launch duration bookkeeping of the sweep kernel: when enabled, every
+ * sweep-kernel launch is bracketed by hipEvents on the context's stream;
+ * read returns the launches timed and their mean duration in ms and
+ * resets the counters.  Synchronous read. */
+HBM_API hbm_status kernel_timing(hbm_ctx *ctx, int32_t enable);
+HBM_API hbm_status read_kernel_timing(hbm_ctx *ctx, int64_t *n_launches, double *mean_ms);
+
+/* Message of the last failure on ctx (or of the last failed init when ctx
+ * is NULL); library-owned, valid until the next call on the context. */
+HBM_API const char *last_error(const hbm_ctx *ctx);
+
+/* Release the library's scratch; the caller's buffers are untouched. */
+HBM_API void destroy_chains(hbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HBM_H */

@@ -57,6 +57,9 @@ def lib():
         L.orc_eps.restype = d
         L.orc_pop_sum.argtypes = [P, P, P]
         L.orc_pop_sum.restype = d
+        L.orc_pop_terms.argtypes = [P, P, P, P]
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = i32
         L.orc_sweep.argtypes = [P, i64, P, P, P, P, P]
         L.orc_theta_proposal.argtypes = [P, i64, P, P, P]
         L.orc_theta_step.argtypes = [P, i64, P, P, P, P]
@@ -85,6 +88,10 @@ def variates(seed: int, ctr):
     z = np.zeros(4)
     lib().orc_variates(ctypes.c_uint64(seed), _ptr(c), _ptr(u), _ptr(z))
     return u, z
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def gauss_legendre(n: int, a: float, b: float):
@@ -167,6 +174,13 @@ class Oracle:
         th = np.ascontiguousarray(theta, dtype=np.float64)
         c = np.ascontiguousarray(chi, dtype=np.float64)
         return lib().orc_pop_sum(self._h, _ptr(th), _ptr(c))
+
+    def pop_terms(self, theta, chi) -> np.ndarray:
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        c = np.ascontiguousarray(chi, dtype=np.float64)
+        out = np.zeros(self.n)
+        lib().orc_pop_terms(self._h, _ptr(th), _ptr(c), _ptr(out))
+        return out
 
     def pop_loglik(self, theta, chi) -> float:
         """sum_i log f(chi_i; theta) - N log Z(theta)."""

@@ -12,6 +12,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -264,6 +267,16 @@ double orc_pop_sum(const orc_ctx *c, const double *theta, const double *chi)
     return sum;
 }
 
+void orc_pop_terms(const orc_ctx *c, const double *theta, const double *chi, double *out)
+{
+    double x[3], lm;
+    for (int64_t i = 0; i < c->n; i++) {
+        for (int j = 0; j < c->d; j++)
+            x[j] = chi[j * c->n + i];
+        orc_log_terms(c, i, x, theta, &lm, &out[i]);
+    }
+}
+
 /* ===================================================================== */
 /* Construction                                                           */
 /* ===================================================================== */
@@ -336,6 +349,15 @@ void orc_free(orc_ctx *c)
     free(c->qt);
     free(c->qv);
     free(c);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 int orc_dims(const orc_ctx *c, int *d, int *p, int *m)

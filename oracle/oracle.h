@@ -53,6 +53,7 @@ orc_ctx *orc_new(int model, int64_t n, const double *data, const double *consts,
                  double alpha_star_theta, int adapt_theta, int nq);
 void orc_free(orc_ctx *c);
 int orc_dims(const orc_ctx *c, int *d, int *p, int *m);
+int orc_num_threads(void);   /* threads the latent sweep uses */
 
 /* log member likelihood and log population density of object i at x[d]. */
 void orc_log_terms(const orc_ctx *c, int64_t i, const double *x, const double *theta,
@@ -62,6 +63,8 @@ double orc_log_Z(const orc_ctx *c, const double *theta);
 double orc_eps(const orc_ctx *c, double x);   /* detection efficiency of ln L = x */
 /* sum_i log f(chi_i; theta), serial in object order.  chi: [d][n]. */
 double orc_pop_sum(const orc_ctx *c, const double *theta, const double *chi);
+/* out[i] = log f(chi_i; theta). */
+void orc_pop_terms(const orc_ctx *c, const double *theta, const double *chi, double *out);
 
 /* One RAM sweep k (1-based) of every object at fixed theta.
  * chi [d][n], chol [d(d+1)/2][n] (packed lower, row-major), acc [n].

@@ -1,0 +1,459 @@
+// Kernels of the sampler.
+//
+//  sweep_kernel   one RAM sweep of every object (Sec. 2.2) fused with the
+//                 FP64 reductions the theta step consumes, the selection
+//                 quadrature for the pending theta' (workgroup 0), and an
+//                 epilogue in the last workgroup to finish that reduces the
+//                 tile partials in fixed order and advances the theta chain.
+//  theta_kernel   the theta Metropolis-Hastings step on its own (plain cycle).
+//  poplik_kernel  sum_i log f(chi_i; theta) - N ln Z(theta) for a given theta.
+//  init kernels   derived per-object data, factors, quadrature tables.
+#pragma once
+
+#include "models.h"
+
+namespace hbm {
+
+template <typename T>
+struct SweepArgs {
+    T *chi;
+    T *chol;
+    uint32_t *acc;
+    const T *dd;               // derived per-object data [MD][N]
+    T *snaps;                  // latent snapshots or nullptr
+    T *trace;                  // [3][N] or nullptr
+    double *partials;          // [n_tiles][2]
+    uint32_t *pacc;            // [n_tiles]
+    uint32_t *counter;         // workgroups finished in this launch
+    CycleState *cs;
+    const Statics *st;
+    const double *qx, *qw, *qeps;
+    double *theta_trace;       // [trace_cap][p]
+    int64_t n;
+    int32_t n_tiles;
+};
+
+// ---------------------------------------------------------------------------
+// Theta-chain arithmetic (FP64, one lane).
+// ---------------------------------------------------------------------------
+template <class M>
+__device__ void prepare_next(CycleState *c, const Statics &s)
+{
+    using T = typename M::T;
+    constexpr int P = M::P;
+    const int64_t kn = c->k + 1;
+    double z[4 * ((P + 3) / 4)];
+#pragma unroll
+    for (int b = 0; b < (P + 3) / 4; ++b) {
+        const Block4 blk = philox(0u, static_cast<uint32_t>(kn), 1u, static_cast<uint32_t>(b), s.key0, s.key1);
+        normals<double, 4>(blk, z + 4 * b);
+    }
+    for (int r = 0; r < P; ++r) {
+        double v = c->theta[r];
+        for (int q = 0; q <= r; ++q) v += c->chol_theta[r * P + q] * z[q];
+        c->prop[r] = v;
+        c->zprop[r] = z[r];
+    }
+    c->lprior_prop = M::log_prior(c->prop);
+    c->prop_valid = c->lprior_prop > -HUGE_VAL;
+    const double *tp = c->prop_valid ? c->prop : c->theta;
+    M::derive_kc(c->theta, tp, s, kc_of<T>(c));
+    M::z_consts(tp, c->zc_prop);
+    c->eta_next = pow(static_cast<double>(kn + 1), -s.gamma);
+}
+
+template <class M>
+__device__ void theta_mh(CycleState *c, const Statics &s, double *theta_trace)
+{
+    constexpr int P = M::P;
+    if (!c->sums_ready) {
+        c->flags |= kFlagNoSums;
+        return;
+    }
+    double delta = -HUGE_VAL;
+    if (c->used_valid) {
+        delta = c->sum_dlf - static_cast<double>(s.n) * (c->logZ_used - c->logZ_cur) + (c->lprior_used - c->lprior_cur);
+        if (delta != delta) delta = -HUGE_VAL;
+    }
+    const double alpha = delta >= 0.0 ? 1.0 : exp(delta);
+    const Block4 ub = philox(0u, static_cast<uint32_t>(c->k), 2u, 0u, s.key0, s.key1);
+    const bool accepted = log(uniform24<double>(ub, 4)) < delta;
+    if (accepted) {
+        for (int r = 0; r < P; ++r) c->theta[r] = c->used_prop[r];
+        c->logZ_cur = c->logZ_used;
+        c->lprior_cur = c->lprior_used;
+    }
+    if (s.adapt_theta) {
+        double L[P * (P + 1) / 2], zz[P];
+        for (int r = 0, e = 0; r < P; ++r)
+            for (int q = 0; q <= r; ++q, ++e) L[e] = c->chol_theta[r * P + q];
+        for (int r = 0; r < P; ++r) zz[r] = c->used_z[r];
+        const double eta = pow(static_cast<double>(c->k + 1), -s.gamma);
+        ram_adapt<double, P>(L, zz, eta * (alpha - s.alpha_star_theta));
+        for (int r = 0, e = 0; r < P; ++r)
+            for (int q = 0; q <= r; ++q, ++e) c->chol_theta[r * P + q] = L[e];
+    }
+    if (c->n_theta < s.trace_cap) {
+        for (int r = 0; r < P; ++r) theta_trace[c->n_theta * P + r] = c->theta[r];
+        c->n_theta += 1;
+    } else {
+        c->flags |= kFlagTraceFull;
+    }
+    c->sums_ready = 0;
+    c->delta_last = delta;
+    c->alpha_last = alpha;
+    c->accepted_last = accepted;
+}
+
+// ln Z(theta) = ln sum_j w_j f_x(x_j; theta) eps_j over the fixed ln L rule;
+// every lane of one workgroup takes nodes tid, tid + 256, ...  Valid in thread 0.
+__device__ __forceinline__ double block_log_z(const double *zc, const double *qx, const double *qw,
+                                              const double *qeps, int nq, double (*red)[kWavesPerBlock])
+{
+    double v[1] = {0.0};
+    for (int j = threadIdx.x; j < nq; j += kBlock) {
+        const double t = qx[j] - zc[1];
+        v[0] += qw[j] * exp(zc[0] * t - exp(t) - zc[2]) * qeps[j];
+    }
+    block_sum<1>(v, red);
+    return log(v[0]);
+}
+
+// ---------------------------------------------------------------------------
+// The sweep.
+// ---------------------------------------------------------------------------
+template <class M, bool kFull, bool kTrace>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> a)
+{
+    using T = typename M::T;
+    constexpr int D = M::D, NC = M::NC;
+    __shared__ double red[3][kWavesPerBlock];
+    __shared__ int is_last;
+    CycleState *cs = a.cs;
+    const Statics &st = *a.st;
+
+    if (blockIdx.x == 0) {
+        if (M::kSelection) {
+            const int valid = cs->prop_valid;
+            double zc[3] = {cs->zc_prop[0], cs->zc_prop[1], cs->zc_prop[2]};
+            if (valid) {
+                const double lz = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
+                if (threadIdx.x == 0) {
+                    cs->logZ_pending = lz;
+                    if (!(lz > -HUGE_VAL && lz < HUGE_VAL)) atomicOr(&cs->flags, kFlagBadZ);
+                }
+            }
+        }
+    } else {
+        const int tile = blockIdx.x - 1;
+        const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;
+        const int64_t n = a.n;
+        const int64_t k = cs->k + 1;
+        const T *kc = kc_of<T>(cs);
+        const T eta = static_cast<T>(cs->eta_next);
+        const T astar = static_cast<T>(st.alpha_star);
+        double v[3] = {0.0, 0.0, 0.0};
+        if (i < n) {
+            T x[D], S[NC], U[D], y[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) x[j] = a.chi[j * n + i];
+#pragma unroll
+            for (int e = 0; e < NC; ++e) S[e] = a.chol[e * n + i];
+            uint32_t nacc = a.acc[i];
+            const typename M::Obj o = M::load(a.dd, i, n);
+            const Block4 b = philox(static_cast<uint32_t>(i), static_cast<uint32_t>(k), 0u, 0u, st.key0, st.key1);
+            normals<T, D>(b, U);
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                T acc_r = x[r];
+#pragma unroll
+                for (int q = 0; q <= r; ++q) acc_r += S[r * (r + 1) / 2 + q] * U[q];
+                y[r] = acc_r;
+            }
+            const Eval<T> ex = M::eval(o, x, kc, st);
+            const Eval<T> ey = M::eval(o, y, kc, st);
+            const T neg_inf = -static_cast<T>(HUGE_VAL);
+            const T delta = (ey.lpv > neg_inf) ? ey.lpv - ex.lpv : neg_inf;
+            const bool accept = log(uniform24<T>(b, 4)) < delta;
+            const T alpha = delta >= static_cast<T>(0) ? static_cast<T>(1) : exp(delta);
+            if (accept) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) x[j] = y[j];
+                nacc += 1u;
+            }
+            const Eval<T> en = accept ? ey : ex;
+            ram_adapt<T, D>(S, U, eta * (alpha - astar));
+#pragma unroll
+            for (int j = 0; j < D; ++j) a.chi[j * n + i] = x[j];
+#pragma unroll
+            for (int e = 0; e < NC; ++e) a.chol[e * n + i] = S[e];
+            a.acc[i] = nacc;
+            v[0] = static_cast<double>(en.lf);
+            v[1] = static_cast<double>(M::dlf(o, x, en, kc, st));
+            v[2] = accept ? 1.0 : 0.0;
+            if (!(ex.lpv > neg_inf)) atomicOr(&cs->flags, kFlagNonFiniteState);
+            if (kTrace) {
+                a.trace[i] = ex.lp;
+                a.trace[n + i] = ey.lp;
+                a.trace[2 * n + i] = accept ? static_cast<T>(1) : static_cast<T>(0);
+            }
+            if (a.snaps != nullptr && st.thin > 0 && k % st.thin == 0) {
+                const int64_t snap = k / st.thin - 1;
+                if (snap < st.snap_cap) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) a.snaps[(snap * D + j) * n + i] = x[j];
+                }
+            }
+        }
+        block_sum<3>(v, red);
+        if (threadIdx.x == 0) {
+            a.partials[2 * tile] = v[0];
+            a.partials[2 * tile + 1] = v[1];
+            a.pacc[tile] = static_cast<uint32_t>(v[2]);
+        }
+    }
+
+    // Last workgroup to finish runs the epilogue.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        is_last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < a.n_tiles; t += kBlock) {
+        v[0] += a.partials[2 * t];
+        v[1] += a.partials[2 * t + 1];
+        v[2] += static_cast<double>(a.pacc[t]);
+    }
+    block_sum<3>(v, red);
+    if (threadIdx.x == 0) {
+        cs->k += 1;
+        cs->sum_lf = v[0];
+        cs->sum_dlf = v[1];
+        cs->n_acc_last = v[2];
+        for (int r = 0; r < M::P; ++r) {
+            cs->used_prop[r] = cs->prop[r];
+            cs->used_z[r] = cs->zprop[r];
+        }
+        cs->logZ_used = cs->logZ_pending;
+        cs->lprior_used = cs->lprior_prop;
+        cs->used_valid = cs->prop_valid;
+        cs->sums_ready = 1;
+        if (kFull) theta_mh<M>(cs, st, a.theta_trace);
+        prepare_next<M>(cs, st);
+        *a.counter = 0u;
+    }
+}
+
+template <class M>
+__global__ void theta_kernel(CycleState *cs, const Statics *st, double *theta_trace)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (!cs->sums_ready) {
+            cs->flags |= kFlagNoSums;
+            return;
+        }
+        theta_mh<M>(cs, *st, theta_trace);
+        prepare_next<M>(cs, *st);
+    }
+}
+
+// Recompute everything that depends on theta after it is set from the host.
+template <class M>
+__global__ __launch_bounds__(kBlock) void set_theta_kernel(CycleState *cs, const Statics *st, const double *qx,
+                                                           const double *qw, const double *qeps)
+{
+    __shared__ double red[1][kWavesPerBlock];
+    double zc[3];
+    M::z_consts(cs->theta, zc);
+    const double lp = M::log_prior(cs->theta);
+    double lz = 0.0;
+    if (M::kSelection && lp > -HUGE_VAL) lz = block_log_z(zc, qx, qw, qeps, st->nq, red);
+    if (threadIdx.x == 0) {
+        cs->lprior_cur = lp;
+        cs->logZ_cur = lz;
+        if (M::kSelection && lp > -HUGE_VAL && !(lz > -HUGE_VAL && lz < HUGE_VAL)) cs->flags |= kFlagBadZ;
+        cs->sums_ready = 0;
+        prepare_next<M>(cs, *st);
+    }
+}
+
+template <class M>
+__global__ void statics_kernel(Statics *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) M::derive_statics(*st);
+}
+
+template <class M>
+__global__ __launch_bounds__(kBlock) void derive_data_kernel(const typename M::T *data, typename M::T *dd,
+                                                             const Statics *st)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < st->n) M::derive_obj(data, dd, i, st->n, *st);
+}
+
+template <class M>
+__global__ __launch_bounds__(kBlock) void init_chain_kernel(typename M::T *chol, uint32_t *acc, double s0,
+                                                            const Statics *st)
+{
+    using T = typename M::T;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t n = st->n;
+    if (i >= n) return;
+    for (int r = 0, e = 0; r < M::D; ++r)
+        for (int q = 0; q <= r; ++q, ++e) chol[e * n + i] = (r == q) ? static_cast<T>(s0) : static_cast<T>(0);
+    acc[i] = 0u;
+}
+
+// Flags objects whose starting log density is not finite (pi(X_1) > 0 is required).
+template <class M>
+__global__ __launch_bounds__(kBlock) void check_init_kernel(const typename M::T *chi, const typename M::T *dd,
+                                                            CycleState *cs, const Statics *st)
+{
+    using T = typename M::T;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t n = st->n;
+    if (i >= n) return;
+    T x[M::D];
+    for (int j = 0; j < M::D; ++j) x[j] = chi[j * n + i];
+    const Eval<T> e = M::eval(M::load(dd, i, n), x, kc_of<T>(cs), *st);
+    if (!(e.lpv > -static_cast<T>(HUGE_VAL) && e.lpv < static_cast<T>(HUGE_VAL))) {
+        atomicMin(&cs->first_bad, static_cast<int32_t>(i));
+        atomicOr(&cs->flags, kFlagNonFiniteState);
+    }
+}
+
+template <typename T>
+struct PopArgs {
+    const T *chi;
+    const T *dd;
+    double *partials;
+    uint32_t *counter;
+    CycleState *cs;
+    const Statics *st;
+    const double *qx, *qw, *qeps;
+    int64_t n;
+    int32_t n_tiles;
+    double theta[kMaxP];
+};
+
+template <class M>
+__global__ __launch_bounds__(kBlock) void poplik_kernel(PopArgs<typename M::T> a)
+{
+    using T = typename M::T;
+    __shared__ double red[1][kWavesPerBlock];
+    __shared__ T kc[32];
+    __shared__ double logz;
+    __shared__ int is_last;
+    const Statics &st = *a.st;
+    if (blockIdx.x == 0) {
+        if (M::kSelection) {
+            double zc[3];
+            M::z_consts(a.theta, zc);
+            const double lz = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
+            if (threadIdx.x == 0) a.cs->poplik_logz = lz;
+        } else if (threadIdx.x == 0) {
+            a.cs->poplik_logz = 0.0;
+        }
+    } else {
+        if (threadIdx.x == 0) M::derive_kc(a.theta, a.theta, st, kc);
+        __syncthreads();
+        const int tile = blockIdx.x - 1;
+        const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;
+        double v[1] = {0.0};
+        if (i < a.n) {
+            T x[M::D];
+            for (int j = 0; j < M::D; ++j) x[j] = a.chi[j * a.n + i];
+            v[0] = static_cast<double>(M::eval(M::load(a.dd, i, a.n), x, kc, st).lf);
+        }
+        block_sum<1>(v, red);
+        if (threadIdx.x == 0) a.partials[tile] = v[0];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        is_last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < a.n_tiles; t += kBlock) v[0] += a.partials[t];
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) {
+        logz = a.cs->poplik_logz;
+        a.cs->poplik_out = v[0] - static_cast<double>(a.n) * logz;
+        *a.counter = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Selection tables.  Gauss-Legendre nodes on [-1, 1]: node j is the root of
+// P_n near cos(pi (4j + 3) / (4n + 2)) (Tricomi's first term), polished by
+// Newton steps on the three-term recurrence; weight 2 / ((1 - t^2) P_n'(t)^2).
+// ---------------------------------------------------------------------------
+__global__ void gauss_legendre_kernel(double *t_out, double *w_out, int nq)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nq) return;
+    const double pi = 3.14159265358979323846;
+    const double theta = pi * (4.0 * j + 3.0) / (4.0 * nq + 2.0);
+    double t = cos(theta) * (1.0 - (nq - 1.0) / (8.0 * nq * nq * nq));
+    double dp = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        double pm1 = 1.0, p = t;
+        for (int l = 1; l < nq; ++l) {
+            const double pn = ((2.0 * l + 1.0) * t * p - l * pm1) / (l + 1.0);
+            pm1 = p;
+            p = pn;
+        }
+        dp = nq * (pm1 - t * p) / (1.0 - t * t);
+        const double step = p / dp;
+        t -= step;
+        if (fabs(step) <= 1e-17) break;
+    }
+    {
+        double pm1 = 1.0, p = t;
+        for (int l = 1; l < nq; ++l) {
+            const double pn = ((2.0 * l + 1.0) * t * p - l * pm1) / (l + 1.0);
+            pm1 = p;
+            p = pn;
+        }
+        dp = nq * (pm1 - t * p) / (1.0 - t * t);
+    }
+    t_out[j] = t;
+    w_out[j] = 2.0 / ((1.0 - t * t) * dp * dp);
+}
+
+// Outer rule in x = ln L on [ln L0 - 30, ln L0 + ln 40] and, per node, the
+// detection efficiency eps(x) = int_0^rmax dr h(r) eta(L / 4 pi r^2) with
+// h(r) = 3 r^2 / rmax^3 and eta(F) = Phi((F - F_th) / sigma_F) (eq 5.10),
+// written in s = ln u, u = (r / rmax)^3, so that h dr = e^s ds, over
+// s in [-60, 0] with the same n-point rule (the part below e^-60 is dropped).
+__global__ void eps_table_kernel(const double *t, const double *w, double *qx, double *qw, double *qeps,
+                                 const Statics *st)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nq = st->nq;
+    if (j >= nq) return;
+    const double fth = st->mc[0], sigf = st->mc[1], rmax = st->mc[2], lnl0 = st->mc[3];
+    const double lo = lnl0 - 30.0, hi = lnl0 + log(40.0);
+    // nodes ascend in x: t descends with the node index
+    const double x = 0.5 * (lo + hi) - 0.5 * (hi - lo) * t[j];
+    qx[j] = x;
+    qw[j] = 0.5 * (hi - lo) * w[j];
+    const double lum_scaled = exp(x) / (4.0 * 3.14159265358979323846 * rmax * rmax);
+    double acc = 0.0;
+    for (int l = 0; l < nq; ++l) {
+        const double s = -30.0 - 30.0 * t[l];
+        const double flux = lum_scaled * exp(-2.0 * s / 3.0);
+        const double eta = 0.5 * erfc(-(flux - fth) / (sigf * 1.4142135623730950488));
+        acc += 30.0 * w[l] * exp(s) * eta;
+    }
+    qeps[j] = acc;
+}
+
+}  // namespace hbm

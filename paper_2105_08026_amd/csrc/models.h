@@ -1,0 +1,345 @@
+// Per-model arithmetic of the sampler: the member likelihood l_i (Sec. 2.1)
+// and the population density f(chi; theta) in latent coordinates, the prior
+// on theta, and the constants each sweep derives from (theta, theta').
+//
+// Single-precision models are written around per-object centres so that the
+// float arithmetic keeps ~1e-7 relative accuracy in the log densities even
+// for bright objects whose likelihood is a thousandth wide in ln L:
+//   * the data are re-expressed once (in FP64) as a centre c_i in float plus
+//     its rounding residual e_i, so ln(F / Fhat) = (chi - c_i) - e_i is formed
+//     from an exact float difference and a tiny correction, and the flux
+//     residual is -(Fhat / sigma) expm1(...);
+//   * ln L* is split into a float head and tail, so chi - ln L* is accurate;
+//   * the change of log f between theta and theta' is formed from parameter
+//     differences (computed in FP64), never as a difference of two sums.
+#pragma once
+
+#include "device.h"
+
+namespace hbm {
+
+constexpr double kLn2Pi = 1.8378770664093454836;
+constexpr double kLn4Pi = 2.5310242469692907930;
+
+template <typename T> __device__ __forceinline__ T stat(const Statics &s, int j);
+template <> __device__ __forceinline__ float stat<float>(const Statics &s, int j) { return s.mf[j]; }
+template <> __device__ __forceinline__ double stat<double>(const Statics &s, int j) { return s.md[j]; }
+
+template <typename T> __device__ __forceinline__ T *kc_of(CycleState *c);
+template <> __device__ __forceinline__ float *kc_of<float>(CycleState *c) { return c->kc_f; }
+template <> __device__ __forceinline__ double *kc_of<double>(CycleState *c) { return c->kc_d; }
+
+template <typename T>
+struct Eval {
+    T lpv;   // log pi up to terms shared by X and Y (used for the accept ratio)
+    T lp;    // log l_i + log f with the constants of the documented densities
+    T lf;    // log f(chi; theta)
+    T q;     // model scratch reused by dlf
+    T eq;
+    T res;
+    T u;
+};
+
+// ===========================================================================
+// Heteroscedastic 1-D normal-normal (Sec. 3), FP64.
+//   log l_i(x) = -((y_i - x) / sigma_i)^2 / 2
+//   log f(x)   = -((x - mu) / tau)^2 / 2 - ln tau - ln(2 pi) / 2
+//   theta = (mu, ln tau); prior density in (mu, ln tau) is tau.
+// ===========================================================================
+struct NN1D {
+    using T = double;
+    static constexpr int D = 1, NC = 1, M = 2, MD = 2, P = 2, MODEL = 1;
+    static constexpr bool kSelection = false;
+    struct Obj {
+        double y, is;
+    };
+
+    __device__ static void derive_statics(Statics &) {}
+    __device__ static void derive_obj(const T *data, T *dd, int64_t i, int64_t n, const Statics &)
+    {
+        dd[i] = data[i];
+        dd[n + i] = 1.0 / data[n + i];
+    }
+    __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{dd[i], dd[n + i]}; }
+    __device__ static double log_prior(const double *th) { return th[1]; }
+    __device__ static void z_consts(const double *, double *zc) { zc[0] = zc[1] = zc[2] = 0.0; }
+    __device__ static void derive_kc(const double *th, const double *tp, const Statics &, T *kc)
+    {
+        kc[0] = th[0];
+        kc[1] = exp(-th[1]);
+        kc[2] = th[1] + 0.5 * kLn2Pi;
+        kc[3] = tp[0];
+        kc[4] = exp(-tp[1]);
+        kc[5] = tp[1] + 0.5 * kLn2Pi;
+    }
+    __device__ static Eval<T> eval(const Obj &o, const T *x, const T *kc, const Statics &)
+    {
+        Eval<T> e;
+        const T rm = (o.y - x[0]) * o.is;
+        const T dv = (x[0] - kc[0]) * kc[1];
+        e.lf = -0.5 * dv * dv - kc[2];
+        e.lp = -0.5 * rm * rm + e.lf;
+        e.lpv = e.lp;
+        e.q = e.eq = e.res = e.u = 0;
+        return e;
+    }
+    __device__ static T dlf(const Obj &, const T *x, const Eval<T> &e, const T *kc, const Statics &)
+    {
+        const T dv = (x[0] - kc[3]) * kc[4];
+        return (-0.5 * dv * dv - kc[5]) - e.lf;
+    }
+};
+
+// ===========================================================================
+// The paper's correlated 3-D normal-normal (Sec. 3), FP64.
+//   log l_i(x) = -sum_j ((y_ij - x_j) / sigma_j)^2 / 2
+//   log f(x)   = log MVN(x; mu, C_pop);  theta = mu, flat prior.
+// Statics md: [0..5] packed C_pop^-1, [6] log normaliser, [7..9] 1/sigma_j.
+// ===========================================================================
+struct NN3D {
+    using T = double;
+    static constexpr int D = 3, NC = 6, M = 3, MD = 3, P = 3, MODEL = 4;
+    static constexpr bool kSelection = false;
+    struct Obj {
+        double y[3];
+    };
+
+    __device__ static void derive_statics(Statics &s)
+    {
+        // Cholesky C = G G^T of the packed covariance, then C^-1 = G^-T G^-1.
+        const double *c = s.mc;
+        double g00 = sqrt(c[0]);
+        double g10 = c[1] / g00, g11 = sqrt(c[2] - g10 * g10);
+        double g20 = c[3] / g00, g21 = (c[4] - g20 * g10) / g11;
+        double g22 = sqrt(c[5] - g20 * g20 - g21 * g21);
+        // H = G^-1 (lower)
+        double h00 = 1.0 / g00, h11 = 1.0 / g11, h22 = 1.0 / g22;
+        double h10 = -g10 * h00 * h11;
+        double h21 = -g21 * h11 * h22;
+        double h20 = -(g20 * h00 + g21 * h10) * h22;
+        // C^-1 = H^T H, packed lower
+        s.md[0] = h00 * h00 + h10 * h10 + h20 * h20;
+        s.md[1] = h11 * h10 + h21 * h20;
+        s.md[2] = h11 * h11 + h21 * h21;
+        s.md[3] = h22 * h20;
+        s.md[4] = h22 * h21;
+        s.md[5] = h22 * h22;
+        s.md[6] = 1.5 * kLn2Pi + log(g00) + log(g11) + log(g22);
+        for (int j = 0; j < 3; ++j) s.md[7 + j] = 1.0 / c[6 + j];
+    }
+    __device__ static void derive_obj(const T *data, T *dd, int64_t i, int64_t n, const Statics &)
+    {
+        for (int j = 0; j < 3; ++j) dd[j * n + i] = data[j * n + i];
+    }
+    __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{{dd[i], dd[n + i], dd[2 * n + i]}}; }
+    __device__ static double log_prior(const double *) { return 0.0; }
+    __device__ static void z_consts(const double *, double *zc) { zc[0] = zc[1] = zc[2] = 0.0; }
+    __device__ static void derive_kc(const double *th, const double *tp, const Statics &, T *kc)
+    {
+        for (int j = 0; j < 3; ++j) {
+            kc[j] = th[j];
+            kc[3 + j] = tp[j];
+        }
+    }
+    __device__ static double quad(const Statics &s, double d0, double d1, double d2)
+    {
+        const double *w = s.md;
+        return w[0] * d0 * d0 + w[2] * d1 * d1 + w[5] * d2 * d2 + 2.0 * (w[1] * d1 * d0 + w[3] * d2 * d0 + w[4] * d2 * d1);
+    }
+    __device__ static Eval<T> eval(const Obj &o, const T *x, const T *kc, const Statics &s)
+    {
+        Eval<T> e;
+        double lm = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double r = (o.y[j] - x[j]) * s.md[7 + j];
+            lm += -0.5 * r * r;
+        }
+        e.lf = -0.5 * quad(s, x[0] - kc[0], x[1] - kc[1], x[2] - kc[2]) - s.md[6];
+        e.lp = lm + e.lf;
+        e.lpv = e.lp;
+        e.q = e.eq = e.res = e.u = 0;
+        return e;
+    }
+    __device__ static T dlf(const Obj &, const T *x, const Eval<T> &e, const T *kc, const Statics &s)
+    {
+        return (-0.5 * quad(s, x[0] - kc[3], x[1] - kc[4], x[2] - kc[5]) - s.md[6]) - e.lf;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Shared pieces of the luminosity-function models (Sec. 4-5, Appendix B).
+// The luminosity PDF is the gamma law of shape beta + 1 and scale L* (the
+// BB1 model as l -> 0); in chi = ln L it reads
+//   log f(chi) = (beta + 1)(chi - ln L*) - exp(chi - ln L*) - lnGamma(beta + 1).
+// kc: [0] beta + 1, [1] float head of ln L*, [2] its tail, [3] lnGamma(beta+1),
+//     [4] beta' - beta, [5] expm1(ln L* - ln L*'),
+//     [6] (beta' + 1)(ln L*' - ln L*) + lnGamma(beta'+1) - lnGamma(beta+1).
+// With q = chi - ln L*:  log f' - log f = (beta' - beta) q - e^q [5] - [6].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void gamma_kc(const double *th, const double *tp, float *kc)
+{
+    const double lg = lgamma(th[0] + 1.0), lgp = lgamma(tp[0] + 1.0);
+    const float head = static_cast<float>(th[1]);
+    kc[0] = static_cast<float>(th[0] + 1.0);
+    kc[1] = head;
+    kc[2] = static_cast<float>(th[1] - static_cast<double>(head));
+    kc[3] = static_cast<float>(lg);
+    kc[4] = static_cast<float>(tp[0] - th[0]);
+    const double dl = tp[1] - th[1];
+    kc[5] = static_cast<float>(expm1(-dl));
+    kc[6] = static_cast<float>((tp[0] + 1.0) * dl + (lgp - lg));
+}
+
+__device__ __forceinline__ double lf_beta_prior(double beta)
+{
+    return (beta > -1.0 && beta < 0.0) ? -log1p(beta * beta) : -HUGE_VAL;
+}
+
+// ===========================================================================
+// Gamma luminosity function, flux-limited, known distances; chi = ln L.
+//   log l_i(chi) = -((Fhat_i - exp(chi - k_i)) / sigma_F)^2 / 2,  k_i = ln 4 pi r_i^2.
+// Derived data per object: a = Fhat / sigma_F, centre c = ln(4 pi r^2 Fhat)
+// rounded to float, and e = (exact centre) - c.
+// ===========================================================================
+struct LF1D {
+    using T = float;
+    static constexpr int D = 1, NC = 1, M = 2, MD = 3, P = 2, MODEL = 2;
+    static constexpr bool kSelection = true;
+    struct Obj {
+        float a, c, e;
+    };
+
+    __device__ static void derive_statics(Statics &) {}
+    __device__ static void derive_obj(const T *data, T *dd, int64_t i, int64_t n, const Statics &s)
+    {
+        const double fhat = data[i], k = data[n + i];
+        const double centre = k + log(fhat);
+        const float c = static_cast<float>(centre);
+        dd[i] = static_cast<float>(fhat / s.mc[1]);
+        dd[n + i] = c;
+        dd[2 * n + i] = static_cast<float>(centre - static_cast<double>(c));
+    }
+    __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{dd[i], dd[n + i], dd[2 * n + i]}; }
+    __device__ static double log_prior(const double *th) { return lf_beta_prior(th[0]); }
+    __device__ static void z_consts(const double *th, double *zc)
+    {
+        zc[0] = th[0] + 1.0;
+        zc[1] = th[1];
+        zc[2] = lgamma(th[0] + 1.0);
+    }
+    __device__ static void derive_kc(const double *th, const double *tp, const Statics &, T *kc) { gamma_kc(th, tp, kc); }
+    __device__ static Eval<T> eval(const Obj &o, const T *x, const T *kc, const Statics &)
+    {
+        Eval<T> e;
+        e.q = (x[0] - kc[1]) - kc[2];
+        e.eq = expf(e.q);
+        const float z = -o.a * expm1f((x[0] - o.c) - o.e);
+        const float lm = -0.5f * z * z;
+        const float g = kc[0] * e.q - e.eq;
+        e.lpv = lm + g;
+        e.lf = g - kc[3];
+        e.lp = lm + e.lf;
+        e.res = e.u = 0.0f;
+        return e;
+    }
+    __device__ static T dlf(const Obj &, const T *, const Eval<T> &e, const T *kc, const Statics &)
+    {
+        return kc[4] * e.q - e.eq * kc[5] - kc[6];
+    }
+};
+
+// ===========================================================================
+// Gamma luminosity function with measured distance and colour; chi = (ln L, ln r, c).
+//   log l_i = -(zF^2 + zr^2 + zc^2) / 2 with
+//     zF = (Fhat - L / 4 pi r^2) / sigma_F, zr = (rhat - r) / (f_r rhat), zc = (chat - c) / sigma_c
+//   log f = gamma term + ln(3 r^3 / rmax^3) [ln r <= ln rmax, else -inf]
+//           - ((c - a - b ln L) / s)^2 / 2 - ln s - ln(2 pi) / 2
+// Derived data: a = Fhat / sigma_F, c1 = centre of ln L, e1 its residual
+// against ln 4 pi + 2 c2 + ln Fhat, c2 = ln rhat in float, e2 its residual, chat.
+// Statics mf: [0] 1/f_r, [1] 1/sigma_c, [2] ln rmax, [3] ln 3 - 3 ln rmax.
+// kc beyond the gamma part: [7] a, [8] b, [9] 1/s, [10] ln s + ln(2 pi)/2,
+//   [11] a' - a, [12] b' - b, [13] 1/s' - 1/s, [14] 1/s', [15] ln(s'/s).
+// ===========================================================================
+struct LF3D {
+    using T = float;
+    static constexpr int D = 3, NC = 6, M = 3, MD = 6, P = 5, MODEL = 3;
+    static constexpr bool kSelection = true;
+    struct Obj {
+        float a, c1, e1, c2, e2, ch;
+    };
+
+    __device__ static void derive_statics(Statics &s)
+    {
+        s.mf[0] = static_cast<float>(1.0 / s.mc[4]);
+        s.mf[1] = static_cast<float>(1.0 / s.mc[5]);
+        s.mf[2] = static_cast<float>(log(s.mc[2]));
+        s.mf[3] = static_cast<float>(log(3.0) - 3.0 * log(s.mc[2]));
+    }
+    __device__ static void derive_obj(const T *data, T *dd, int64_t i, int64_t n, const Statics &s)
+    {
+        const double fhat = data[i], rhat = data[n + i], chat = data[2 * n + i];
+        const double lr = log(rhat);
+        const float c2 = static_cast<float>(lr);
+        const double centre = kLn4Pi + 2.0 * lr + log(fhat);
+        const float c1 = static_cast<float>(centre);
+        dd[i] = static_cast<float>(fhat / s.mc[1]);
+        dd[n + i] = c1;
+        dd[2 * n + i] = static_cast<float>(kLn4Pi + 2.0 * static_cast<double>(c2) + log(fhat) - static_cast<double>(c1));
+        dd[3 * n + i] = c2;
+        dd[4 * n + i] = static_cast<float>(lr - static_cast<double>(c2));
+        dd[5 * n + i] = static_cast<float>(chat);
+    }
+    __device__ static Obj load(const T *dd, int64_t i, int64_t n)
+    {
+        return Obj{dd[i], dd[n + i], dd[2 * n + i], dd[3 * n + i], dd[4 * n + i], dd[5 * n + i]};
+    }
+    __device__ static double log_prior(const double *th)
+    {
+        return th[4] > 0.0 ? lf_beta_prior(th[0]) : -HUGE_VAL;
+    }
+    __device__ static void z_consts(const double *th, double *zc) { LF1D::z_consts(th, zc); }
+    __device__ static void derive_kc(const double *th, const double *tp, const Statics &, T *kc)
+    {
+        gamma_kc(th, tp, kc);
+        kc[7] = static_cast<float>(th[2]);
+        kc[8] = static_cast<float>(th[3]);
+        kc[9] = static_cast<float>(1.0 / th[4]);
+        kc[10] = static_cast<float>(log(th[4]) + 0.5 * kLn2Pi);
+        kc[11] = static_cast<float>(tp[2] - th[2]);
+        kc[12] = static_cast<float>(tp[3] - th[3]);
+        kc[13] = static_cast<float>(1.0 / tp[4] - 1.0 / th[4]);
+        kc[14] = static_cast<float>(1.0 / tp[4]);
+        kc[15] = static_cast<float>(log(tp[4] / th[4]));
+    }
+    __device__ static Eval<T> eval(const Obj &o, const T *x, const T *kc, const Statics &s)
+    {
+        Eval<T> e;
+        e.q = (x[0] - kc[1]) - kc[2];
+        e.eq = expf(e.q);
+        const float d0 = x[0] - o.c1, d1 = x[1] - o.c2;
+        const float zF = -o.a * expm1f((d0 - 2.0f * d1) - o.e1);
+        const float zr = -s.mf[0] * expm1f(d1 - o.e2);
+        const float zc = (x[2] - o.ch) * s.mf[1];
+        const float lm = -0.5f * (zF * zF + zr * zr + zc * zc);
+        // colour residual c - a - b ln L around the object's centre: the
+        // rounding of the per-object constant is shared by X and Y.
+        const float kres = (o.ch - kc[7]) - kc[8] * o.c1;
+        e.res = ((x[2] - o.ch) + kres) - kc[8] * d0;
+        e.u = e.res * kc[9];
+        const float g = kc[0] * e.q - e.eq;
+        const float col = -0.5f * e.u * e.u;
+        const bool inside = x[1] <= s.mf[2];
+        e.lpv = inside ? lm + g + 3.0f * d1 + col : -HUGE_VALF;
+        e.lf = inside ? g - kc[3] + (3.0f * x[1] + s.mf[3]) + col - kc[10] : -HUGE_VALF;
+        e.lp = lm + e.lf;
+        return e;
+    }
+    __device__ static T dlf(const Obj &, const T *x, const Eval<T> &e, const T *kc, const Statics &)
+    {
+        const float dg = kc[4] * e.q - e.eq * kc[5] - kc[6];
+        const float du = e.res * kc[13] - (kc[11] + kc[12] * x[0]) * kc[14];
+        return dg - 0.5f * du * (2.0f * e.u + du) - kc[15];
+    }
+};
+
+}  // namespace hbm

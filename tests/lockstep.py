@@ -1,0 +1,129 @@
+"""Lockstep comparison of the GPU sampler with the FP64 oracle.
+
+From one state (latents, RAM factors, theta, its factor, sweep count) both
+sides take one RAM sweep with the same Philox streams; the oracle then
+adopts the GPU's post-sweep latents and both take the theta step.  What is
+compared, per object and per step:
+  * log pi(X) and log pi(Y): |gpu - orc| <= rel * max(1, |orc|)  (rel = 1e-5
+    for FP32 per-object arithmetic, 1e-12 for FP64);
+  * accept/reject decisions: identical, except logged near-ties, where a
+    mismatch is a near-tie only when the observed numeric error straddles
+    the threshold, |ln u - Delta_orc| <= |Delta_gpu - Delta_orc|, and that
+    error itself is within the tolerance above;
+  * the new latent (rejected: unchanged bit for bit; accepted: the
+    proposal, equal up to the per-object precision) and the new RAM factor;
+  * the theta step's log acceptance ratio, its decision (same near-tie
+    rule) and the new theta and factor.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+import oracle
+
+
+@dataclasses.dataclass
+class StepReport:
+    n: int
+    max_rel_lpx: float
+    max_rel_lpy: float
+    near_ties: int
+    decision_mismatch: int
+    max_chi_err: float
+    max_chol_rel: float
+    theta_delta_gpu: float
+    theta_delta_orc: float
+    theta_tol: float
+    theta_near_tie: bool
+
+
+def tolerances(precision: str):
+    if precision == "f32":
+        return dict(lp=1e-5, chi_ulps=8.0, chol=2e-5, theta_rel=1e-6)
+    return dict(lp=1e-12, chi_ulps=64.0, chol=1e-11, theta_rel=1e-12)
+
+
+def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
+    tol = tolerances(prec)
+    chi0, chol0, acc0 = sampler.state()
+    theta0, cth0, k0 = sampler.theta()
+    tr = sampler.trace_sweep()                      # GPU sweep k0 + 1
+    chi1, chol1, acc1 = sampler.state()
+
+    st = oracle.State(chi0.copy(), chol0.copy(), acc0.copy(), theta0.copy(), cth0.copy(), k0)
+    otr = orc.sweep(st, trace=True)                 # oracle sweep from the same state
+
+    lpx_o, lpy_o, lnu_o, acc_o = otr[:, 0], otr[:, 1], otr[:, 2], otr[:, 3] > 0
+    lpx_g, lpy_g, acc_g = tr[0], tr[1], tr[2] > 0
+    scale_x = np.maximum(1.0, np.abs(lpx_o))
+    rel_x = np.abs(lpx_g - lpx_o) / scale_x
+    fin_y = np.isfinite(lpy_o)
+    rel_y = np.zeros_like(lpy_o)
+    rel_y[fin_y] = np.abs(lpy_g[fin_y] - lpy_o[fin_y]) / np.maximum(1.0, np.abs(lpy_o[fin_y]))
+    assert np.all(rel_x <= tol["lp"]), ("log pi(X)", rel_x.max(), int(np.argmax(rel_x)))
+    assert np.all(rel_y <= tol["lp"]), ("log pi(Y)", rel_y.max(), int(np.argmax(rel_y)))
+    # where the oracle's proposal has zero density the GPU's must too (or be rejected)
+    assert not np.any(acc_g & ~fin_y)
+
+    mism = np.nonzero(acc_g != acc_o)[0]
+    near = 0
+    for i in mism:
+        d_o = lpy_o[i] - lpx_o[i]
+        d_g = lpy_g[i] - lpx_g[i]
+        err = abs(d_g - d_o)
+        ok = abs(lnu_o[i] - d_o) <= err and err <= tol["lp"] * max(1.0, abs(lpx_o[i]), abs(lpy_o[i]))
+        assert ok, ("decision mismatch that is not a near-tie", int(i), d_o, d_g, lnu_o[i])
+        near += 1
+
+    same = acc_g == acc_o
+    d = chi0.shape[0]
+    # rejected moves keep the latent bit for bit
+    rej = same & ~acc_o
+    assert np.array_equal(chi1[:, rej], chi0[:, rej])
+    # accepted moves land on the proposal
+    accd = same & acc_o
+    ulp = np.spacing(np.abs(st.chi[:, accd]).astype(np.float32 if prec == "f32" else np.float64)).astype(np.float64)
+    err = np.abs(chi1[:, accd] - st.chi[:, accd])
+    chi_err = float((err / np.maximum(ulp, 1e-300)).max()) if err.size else 0.0
+    assert chi_err <= tol["chi_ulps"], ("latent", chi_err)
+    crel = np.abs(chol1[:, same] - st.chol[:, same]) / np.maximum(np.abs(st.chol[:, same]), 1e-30)
+    # off-diagonal factor entries can be tiny; compare them relative to the diagonal scale
+    if d > 1:
+        diag_idx = [r * (r + 1) // 2 + r for r in range(d)]
+        dscale = np.max(np.abs(st.chol[diag_idx][:, same]), axis=0)
+        crel = np.abs(chol1[:, same] - st.chol[:, same]) / np.maximum(dscale, 1e-30)
+    chol_rel = float(crel.max()) if crel.size else 0.0
+    assert chol_rel <= tol["chol"], ("RAM factor", chol_rel)
+    assert np.array_equal(acc1[same], st.acc[same])
+
+    # theta step: the oracle takes the GPU's latents (lockstep)
+    st.chi = chi1.copy()
+    st.chol = chol1.copy()
+    st.acc = acc1.copy()
+    prop = orc.theta_proposal(st, k=k0 + 1)
+    scale = float(np.sum(np.abs(orc.pop_terms(prop, chi1) - orc.pop_terms(theta0, chi1)))) \
+        if np.isfinite(orc.log_prior(prop)) else 0.0
+    info = orc.theta_step(st)
+    acc_th_g = sampler.theta_step()
+    stats = sampler.stats()
+    theta1, cth1, _ = sampler.theta()
+    d_g, d_o = stats["delta"], info["delta"]
+    # FP64 selection normalisers of the two sides agree to ~1e-13 relative
+    has_sel = orc.wl.model in (2, 3)
+    theta_tol = tol["theta_rel"] * max(1.0, scale) + (1e-12 * sampler.n if has_sel else 0.0)
+    near_theta = False
+    if np.isfinite(d_o):
+        assert abs(d_g - d_o) <= theta_tol, ("theta delta", d_g, d_o, theta_tol)
+    else:
+        assert not np.isfinite(d_g)
+    if acc_th_g != info["accepted"]:
+        assert abs(info["ln_u"] - d_o) <= abs(d_g - d_o) <= theta_tol, ("theta decision", d_g, d_o, info["ln_u"])
+        near_theta = True
+    else:
+        np.testing.assert_allclose(theta1, st.theta, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(cth1, st.chol_theta, rtol=1e-9, atol=1e-14)
+    return StepReport(sampler.n, float(rel_x.max()), float(rel_y.max()), near, len(mism), chi_err, chol_rel,
+                      d_g, d_o, theta_tol, near_theta)

@@ -1,0 +1,65 @@
+"""The C ABI library loads and exports every function include/hbm.h declares,
+and the Python binding's struct layouts match the header's (checked with a
+tiny C program compiled against hbm.h).  No compute call is made."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return re.findall(r"^HBM_API\s+[\w\s\*]+?\b(\w+)\s*\(", text, flags=re.M)
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for core in ("init_chains", "ram_sweep", "pop_loglik", "theta_step", "get_samples", "destroy_chains",
+                 "last_error"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2105_08026_amd as hbm
+    if not os.path.exists(hbm.LIB_PATH):
+        pytest.skip("library not built")
+    L = ctypes.CDLL(hbm.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) == set(hbm.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", hbm.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert exported == set(declared_functions())
+
+
+def test_struct_layout_matches_header(tmp_path):
+    import paper_2105_08026_amd as hbm
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in hbm.Config._fields_]
+    bfields = [f for f, _ in hbm.Buffers._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hbm.h"', "int main(void){",
+             'printf("%zu %zu\\n", sizeof(hbm_config), sizeof(hbm_buffers));']
+    lines += [f'printf("%zu\\n", offsetof(hbm_config, {f}));' for f in fields]
+    lines += [f'printf("%zu\\n", offsetof(hbm_buffers, {f}));' for f in bfields]
+    lines += ["return 0;}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(hbm.Config) and vals[1] == ctypes.sizeof(hbm.Buffers)
+    offs = vals[2:]
+    assert offs[: len(fields)] == [getattr(hbm.Config, f).offset for f in fields]
+    assert offs[len(fields):] == [getattr(hbm.Buffers, f).offset for f in bfields]
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_2105_08026_amd as hbm
+    monkeypatch.setattr(hbm, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(hbm, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        hbm.lib()

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+FP64 models (normal-normal, 1-D and the paper's 3-D instance): whole chains
+must coincide with the oracle's (identical decisions; values to ~1e-12).
+FP32 models (luminosity function, 1-D and 3-D): lockstep, one sweep and
+one theta step at a time from a shared state (tests/lockstep.py), at sizes
+that span several 256-object tiles and a ragged tail, and at the full
+300,000-object catalog in the launch configuration the bench uses.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import batch_means
+from lockstep import lockstep_step
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_08026_amd as h
+    h.lib()
+    return h
+
+
+def test_nn1d_chain_identical_to_oracle(hbm):
+    _say("nn1d chain: N=1000, 2000 cycles, plain ram_sweep + theta_step")
+    wl = synth.normal_normal_1d(n=1000, seed=0)
+    s = hbm.Sampler(wl, max_cycles=2000)
+    for _ in range(2000):
+        s.ram_sweep(1)
+        s.theta_step()
+    tg = s.theta_trace()
+    chi_g, chol_g, acc_g = s.state()
+    o = oracle.Oracle(wl)
+    st = o.initial_state()
+    to, _ = o.run(st, 2000)
+    np.testing.assert_allclose(tg, to, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(chi_g, st.chi, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(chol_g, st.chol, rtol=1e-10)
+    assert np.array_equal(acc_g, st.acc)
+
+
+def test_nn1d_fused_graph_equals_plain(hbm):
+    _say("nn1d: run_cycles (graph, fused theta step) vs ram_sweep + theta_step, bitwise")
+    wl = synth.normal_normal_1d(n=1000, seed=0)
+    a = hbm.Sampler(wl, max_cycles=300)
+    for _ in range(300):
+        a.ram_sweep(1)
+        a.theta_step()
+    b = hbm.Sampler(wl, max_cycles=300)
+    b.run_cycles(300, use_graph=True)
+    c = hbm.Sampler(wl, max_cycles=300)
+    c.run_cycles(300, use_graph=False)
+    for other in (b, c):
+        assert np.array_equal(a.theta_trace(), other.theta_trace())
+        sa, so = a.state(), other.state()
+        for x, y in zip(sa, so):
+            assert np.array_equal(x, y)
+
+
+def test_nn3d_papers_instance_chain_identical(hbm):
+    _say("nn3d (paper Sec. 3 instance): N=777, 400 cycles")
+    wl = synth.normal_normal_3d(n=777, seed=5)
+    s = hbm.Sampler(wl, max_cycles=400)
+    s.run_cycles(400, use_graph=True)
+    o = oracle.Oracle(wl)
+    st = o.initial_state()
+    to, _ = o.run(st, 400)
+    np.testing.assert_allclose(s.theta_trace(), to, rtol=1e-9, atol=1e-9)
+    chi_g, chol_g, acc_g = s.state()
+    np.testing.assert_allclose(chi_g, st.chi, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(chol_g, st.chol, rtol=1e-8, atol=1e-10)
+    assert np.array_equal(acc_g, st.acc)
+
+
+@pytest.mark.parametrize("n", [3001, 257])
+def test_lf1d_lockstep(hbm, n):
+    _say(f"lf1d lockstep: N={n}")
+    wl = synth.gamma_lf_1d(n=n, seed=51, fth=389.75)
+    s = hbm.Sampler(wl, max_cycles=200)
+    o = oracle.Oracle(wl)
+    worst = 0.0
+    for step in range(40):
+        r = lockstep_step(s, o, "f32")
+        worst = max(worst, r.max_rel_lpx, r.max_rel_lpy)
+        if step % 10 == 0:
+            _say(f"  step {step}: max rel lp err {worst:.2e} near-ties {r.near_ties} dtheta {r.theta_delta_gpu - r.theta_delta_orc:.2e}")
+
+
+def test_lf3d_lockstep(hbm):
+    _say("lf3d lockstep: N=3001")
+    wl = synth.gamma_lf_3d(n=3001, seed=52, fth=389.75)
+    s = hbm.Sampler(wl, max_cycles=200)
+    o = oracle.Oracle(wl)
+    for step in range(30):
+        r = lockstep_step(s, o, "f32")
+        if step % 10 == 0:
+            _say(f"  step {step}: lp err {max(r.max_rel_lpx, r.max_rel_lpy):.2e} chol {r.max_chol_rel:.2e}")
+
+
+def test_lf1d_full_catalog_lockstep_after_graph_cycles(hbm):
+    _say("lf1d full catalog N=300000: 200 graph cycles, then 3 lockstep steps")
+    wl = synth.gamma_lf_1d()
+    s = hbm.Sampler(wl, max_cycles=400)
+    s.run_cycles(200, use_graph=True)
+    o = oracle.Oracle(wl)
+    for _ in range(3):
+        r = lockstep_step(s, o, "f32")
+        _say(f"  lp err {max(r.max_rel_lpx, r.max_rel_lpy):.2e} near-ties {r.near_ties}")
+    th = s.theta_trace()
+    assert np.all(np.isfinite(th))
+
+
+@pytest.mark.parametrize("make", [lambda: synth.normal_normal_1d(n=1000),
+                                  lambda: synth.gamma_lf_1d(n=5000, seed=53, fth=389.75),
+                                  lambda: synth.gamma_lf_3d(n=2000, seed=54, fth=389.75),
+                                  lambda: synth.normal_normal_3d(n=500)])
+def test_pop_loglik_matches_oracle(hbm, make):
+    wl = make()
+    _say(f"pop_loglik {wl.name} N={wl.n}")
+    s = hbm.Sampler(wl, max_cycles=50)
+    s.run_cycles(20)
+    chi, _, _ = s.state()
+    o = oracle.Oracle(wl)
+    rng = np.random.default_rng(9)
+    for _ in range(4):
+        th = wl.theta_true + 0.02 * rng.standard_normal(wl.p) * np.abs(np.diag(wl.theta_chol0)) / 0.05
+        if not np.isfinite(o.log_prior(th)):
+            continue
+        got = s.pop_loglik(th)
+        ref = o.pop_loglik(th, chi)
+        scale = np.sum(np.abs(o.pop_terms(th, chi)))
+        rel = 1e-6 if wl.precision == "f32" else 1e-13
+        assert abs(got - ref) <= rel * scale + 1e-12 * wl.n, (got, ref, scale)
+
+
+def test_determinism_and_stats(hbm):
+    _say("determinism: two contexts, same seed, fused graph path")
+    wl = synth.gamma_lf_1d(n=20000, seed=55, fth=389.75)
+    a = hbm.Sampler(wl, max_cycles=100)
+    b = hbm.Sampler(wl, max_cycles=100)
+    a.run_cycles(100)
+    b.run_cycles(100)
+    assert np.array_equal(a.theta_trace(), b.theta_trace())
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    st = a.stats()
+    assert 0 <= st["n_acc"] <= wl.n and np.isfinite(st["sum_lf"])
+
+
+def test_error_paths(hbm):
+    wl = synth.gamma_lf_1d(n=1000, seed=56, fth=389.75)
+    bad = synth.gamma_lf_1d(n=1000, seed=56, fth=389.75)
+    bad.theta0 = np.array([0.5, bad.theta0[1]])          # beta outside (-1, 0)
+    with pytest.raises(hbm.HbmError) as e:
+        hbm.Sampler(bad)
+    assert e.value.status == hbm.HBM_EDOMAIN
+    s = hbm.Sampler(wl, max_cycles=2)
+    with pytest.raises(hbm.HbmError) as e:
+        s.theta_step()                                     # no sweep yet
+    assert e.value.status == hbm.HBM_ESTATE
+    s.run_cycles(2)
+    with pytest.raises(hbm.HbmError) as e:
+        s.run_cycles(1)                                    # trace full
+    assert e.value.status == hbm.HBM_ENOSPACE
+    # the context still works after validation errors
+    assert np.isfinite(s.pop_loglik(wl.theta0))
+
+
+def test_snapshots(hbm):
+    wl = synth.normal_normal_1d(n=600)
+    s = hbm.Sampler(wl, max_cycles=100, thin=10)
+    s.run_cycles(100)
+    snaps = s.chi_snapshots(0, 10)
+    o = oracle.Oracle(wl)
+    st = o.initial_state()
+    _, ct = o.run(st, 100, thin=10, chi_trace=True)
+    np.testing.assert_allclose(snaps, ct, rtol=1e-10, atol=1e-10)
+
+
+def test_lf1d_free_run_posterior_moments(hbm):
+    _say("lf1d free run: posterior theta moments vs oracle within MCSE")
+    wl = synth.gamma_lf_1d(n=400, seed=57, fth=389.75)
+    m = 30000
+    s = hbm.Sampler(wl, max_cycles=m)
+    s.run_cycles(m)
+    tg = s.theta_trace()[m // 5:]
+    o = oracle.Oracle(wl)
+    st = o.initial_state()
+    to, _ = o.run(st, m)
+    to = to[m // 5:]
+    for j in range(2):
+        mg, sg = batch_means(tg[:, j])
+        mo, so = batch_means(to[:, j])
+        z = abs(mg - mo) / math.hypot(sg, so)
+        _say(f"  theta[{j}] gpu {mg:.5f}±{sg:.5f} oracle {mo:.5f}±{so:.5f} z={z:.2f}")
+        assert z < 3.0
+        vg, svg = batch_means((tg[:, j] - mg) ** 2)
+        vo, svo = batch_means((to[:, j] - mo) ** 2)
+        assert abs(vg - vo) < 3.0 * math.hypot(svg, svo)
