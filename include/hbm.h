@@ -178,10 +178,12 @@ HBM_API hbm_status get_theta(hbm_ctx *ctx, double *theta, double *chol_theta, in
  * is outside the prior support. */
 HBM_API hbm_status set_theta(hbm_ctx *ctx, const double *theta, const double *chol_theta, int64_t k);
 
-/* One sweep like ram_sweep that also writes, per object, trace[0][i] =
- * log pi_i(X), trace[1][i] = log pi_i(Y) (up to model constants shared with
- * the oracle's definition), trace[2][i] = 1 if accepted else 0, in the
- * per-object precision; trace is a device buffer [3][N].  Synchronous. */
+/* One sweep like ram_sweep that also writes, per object, in the per-object
+ * precision: trace[0][i] = log pi_i(X), trace[1][i] = log pi_i(Y) (member
+ * log likelihood plus log population density, with the constants of the
+ * densities documented above), trace[2][i] = 1 if accepted else 0, and
+ * trace[3 + j][i] = component j of the proposal Y; trace is a device buffer
+ * [3 + d][N].  Synchronous. */
 HBM_API hbm_status ram_sweep_trace(hbm_ctx *ctx, void *trace);
 
 /* Statistics of the last sweep and theta step: out[0] sum log f(chi; theta),

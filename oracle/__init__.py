@@ -58,6 +58,7 @@ def lib():
         L.orc_pop_sum.argtypes = [P, P, P]
         L.orc_pop_sum.restype = d
         L.orc_pop_terms.argtypes = [P, P, P, P]
+        L.orc_log_post.argtypes = [P, P, P, P]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
         L.orc_sweep.argtypes = [P, i64, P, P, P, P, P]
@@ -180,6 +181,14 @@ class Oracle:
         c = np.ascontiguousarray(chi, dtype=np.float64)
         out = np.zeros(self.n)
         lib().orc_pop_terms(self._h, _ptr(th), _ptr(c), _ptr(out))
+        return out
+
+    def log_post(self, theta, pts) -> np.ndarray:
+        """log l_i(x_i) + log f(x_i; theta) for every object at points pts [d][n]."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        x = np.ascontiguousarray(pts, dtype=np.float64)
+        out = np.zeros(self.n)
+        lib().orc_log_post(self._h, _ptr(th), _ptr(x), _ptr(out))
         return out
 
     def pop_loglik(self, theta, chi) -> float:

@@ -267,6 +267,17 @@ double orc_pop_sum(const orc_ctx *c, const double *theta, const double *chi)
     return sum;
 }
 
+void orc_log_post(const orc_ctx *c, const double *theta, const double *pts, double *out)
+{
+    double x[3], lm, lp;
+    for (int64_t i = 0; i < c->n; i++) {
+        for (int j = 0; j < c->d; j++)
+            x[j] = pts[j * c->n + i];
+        orc_log_terms(c, i, x, theta, &lm, &lp);
+        out[i] = lm + lp;
+    }
+}
+
 void orc_pop_terms(const orc_ctx *c, const double *theta, const double *chi, double *out)
 {
     double x[3], lm;

@@ -63,6 +63,8 @@ double orc_log_Z(const orc_ctx *c, const double *theta);
 double orc_eps(const orc_ctx *c, double x);   /* detection efficiency of ln L = x */
 /* sum_i log f(chi_i; theta), serial in object order.  chi: [d][n]. */
 double orc_pop_sum(const orc_ctx *c, const double *theta, const double *chi);
+/* out[i] = log l_i(pts_i) + log f(pts_i; theta), pts [d][n]. */
+void orc_log_post(const orc_ctx *c, const double *theta, const double *pts, double *out);
 /* out[i] = log f(chi_i; theta). */
 void orc_pop_terms(const orc_ctx *c, const double *theta, const double *chi, double *out);
 

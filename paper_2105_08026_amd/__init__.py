@@ -290,8 +290,8 @@ class Sampler:
         return out
 
     def trace_sweep(self) -> np.ndarray:
-        """One sweep returning per-object (log pi(X), log pi(Y), accepted) as float64 [3][N]."""
-        tr = torch.empty((3, self.n), dtype=self.dtype, device=self.device)
+        """One sweep returning per-object (log pi(X), log pi(Y), accepted, Y[0..d-1]) as float64 [3 + d][N]."""
+        tr = torch.empty((3 + self.d, self.n), dtype=self.dtype, device=self.device)
         ram_sweep_trace(self.ctx, tr.data_ptr())
         return tr.double().cpu().numpy()
 

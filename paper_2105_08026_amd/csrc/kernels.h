@@ -21,7 +21,7 @@ struct SweepArgs {
     uint32_t *acc;
     const T *dd;               // derived per-object data [MD][N]
     T *snaps;                  // latent snapshots or nullptr
-    T *trace;                  // [3][N] or nullptr
+    T *trace;                  // [3 + D][N] or nullptr
     double *partials;          // [n_tiles][2]
     uint32_t *pacc;            // [n_tiles]
     uint32_t *counter;         // workgroups finished in this launch
@@ -196,6 +196,8 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
                 a.trace[i] = ex.lp;
                 a.trace[n + i] = ey.lp;
                 a.trace[2 * n + i] = accept ? static_cast<T>(1) : static_cast<T>(0);
+#pragma unroll
+                for (int j = 0; j < D; ++j) a.trace[(3 + j) * n + i] = y[j];
             }
             if (a.snaps != nullptr && st.thin > 0 && k % st.thin == 0) {
                 const int64_t snap = k / st.thin - 1;
