@@ -197,6 +197,8 @@ struct CycleState {
     double logZ_used;              // ln Z(used_prop)
     double lprior_cur, lprior_prop, lprior_used;
     double eta_next;               // eta of sweep k + 1
+    double eta_used;               // eta of the sweep just done (also the theta step's)
+    double aux_cur, aux_prop, aux_used;   // per-theta model scalar (lnGamma(beta + 1) for LF models)
     double sum_lf;                 // sum_i log f(chi_i; theta) after the last sweep
     double sum_dlf;                // sum_i [log f(chi_i; used_prop) - log f(chi_i; theta)]
     double n_acc_last;             // accepted latent moves in the last sweep
@@ -214,6 +216,7 @@ struct CycleState {
     float kc_f[32];                // per-sweep kernel constants, FP32 models
     double kc_d[32];               // per-sweep kernel constants, FP64 models
 };
+static_assert(sizeof(CycleState) % 8 == 0, "CycleState is staged through LDS in 8-byte words");
 
 // Per-context constants that never change after init.
 struct Statics {

@@ -43,9 +43,8 @@ struct CtxImpl {
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
     void *dd = nullptr;
-    double *partials = nullptr;
-    uint32_t *pacc = nullptr;
-    uint32_t *counter = nullptr;
+    double *partials = nullptr;     // [n_tiles][3]
+    double *zout = nullptr;         // [2]: ln Z at the pending proposal, ln Z of pop_loglik
     double *ref_t = nullptr, *ref_w = nullptr, *qx = nullptr, *qw = nullptr, *qeps = nullptr;
     CycleState *cs = nullptr;
     Statics *st = nullptr;
@@ -127,14 +126,12 @@ struct Ops {
         a.snaps = static_cast<T *>(c->buf.chi_samples);
         a.trace = static_cast<T *>(trace);
         a.partials = c->partials;
-        a.pacc = c->pacc;
-        a.counter = c->counter;
+        a.zout = c->zout;
         a.cs = c->cs;
         a.st = c->st;
         a.qx = c->qx;
         a.qw = c->qw;
         a.qeps = c->qeps;
-        a.theta_trace = c->theta_trace;
         a.n = c->n;
         a.n_tiles = c->n_tiles;
         return a;
@@ -151,23 +148,28 @@ struct Ops {
             if (e0) HIPCHK(c, hipEventRecord(e0, c->stream));
         }
         if (trace)
-            hipLaunchKernelGGL((sweep_kernel<M, false, true>), grid, dim3(kBlock), 0, c->stream, a);
-        else if (full)
-            hipLaunchKernelGGL((sweep_kernel<M, true, false>), grid, dim3(kBlock), 0, c->stream, a);
+            hipLaunchKernelGGL((sweep_kernel<M, true>), grid, dim3(kBlock), 0, c->stream, a);
         else
-            hipLaunchKernelGGL((sweep_kernel<M, false, false>), grid, dim3(kBlock), 0, c->stream, a);
+            hipLaunchKernelGGL((sweep_kernel<M, false>), grid, dim3(kBlock), 0, c->stream, a);
         LAUNCHCHK(c, "sweep_kernel");
         if (c->timing && e0 && e1) {
             HIPCHK(c, hipEventRecord(e1, c->stream));
             c->ev_pending.push_back(e0);
             c->ev_pending.push_back(e1);
         }
+        if (full)
+            hipLaunchKernelGGL((epilogue_kernel<M, true>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st,
+                               c->partials, c->zout, c->theta_trace, c->n_tiles);
+        else
+            hipLaunchKernelGGL((epilogue_kernel<M, false>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st,
+                               c->partials, c->zout, c->theta_trace, c->n_tiles);
+        LAUNCHCHK(c, "epilogue_kernel");
         return HBM_OK;
     }
 
     static hbm_status theta(CtxImpl *c)
     {
-        hipLaunchKernelGGL((theta_kernel<M>), dim3(1), dim3(1), 0, c->stream, c->cs, c->st, c->theta_trace);
+        hipLaunchKernelGGL((theta_kernel<M>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st, c->theta_trace);
         LAUNCHCHK(c, "theta_kernel");
         return HBM_OK;
     }
@@ -186,17 +188,18 @@ struct Ops {
         a.chi = static_cast<const T *>(c->buf.chi);
         a.dd = static_cast<const T *>(c->dd);
         a.partials = c->partials;
-        a.counter = c->counter;
-        a.cs = c->cs;
+        a.zout = c->zout;
         a.st = c->st;
         a.qx = c->qx;
         a.qw = c->qw;
         a.qeps = c->qeps;
         a.n = c->n;
-        a.n_tiles = c->n_tiles;
         for (int r = 0; r < kMaxP; ++r) a.theta[r] = r < M::P ? theta[r] : 0.0;
         hipLaunchKernelGGL((poplik_kernel<M>), dim3(c->n_tiles + 1), dim3(kBlock), 0, c->stream, a);
         LAUNCHCHK(c, "poplik_kernel");
+        hipLaunchKernelGGL(poplik_finish_kernel, dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->partials, c->zout,
+                           c->n, c->n_tiles);
+        LAUNCHCHK(c, "poplik_finish_kernel");
         return HBM_OK;
     }
 
@@ -303,7 +306,7 @@ void release(CtxImpl *c)
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
-    void *ptrs[] = {c->dd, c->partials, c->pacc, c->counter, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
+    void *ptrs[] = {c->dd, c->partials, c->zout, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
                     c->cs, c->st, c->theta_trace};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -422,9 +425,8 @@ hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, con
     const bool sel = has_selection(config->model);
     const int nq = sel ? config->n_quad : 1;
     if ((s = alloc(&c->dd, c->esize * c->md * c->n)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->partials), sizeof(double) * 2 * c->n_tiles)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->pacc), sizeof(uint32_t) * c->n_tiles)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->counter), sizeof(uint32_t))) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->partials), sizeof(double) * 3 * c->n_tiles)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->zout), sizeof(double) * 2)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->ref_t), sizeof(double) * nq)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->ref_w), sizeof(double) * nq)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->qx), sizeof(double) * nq)) != HBM_OK ||
@@ -461,8 +463,7 @@ hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, con
 
     hipError_t e;
     if ((e = hipMemcpyAsync(c->st, &hs, sizeof(hs), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(c->cs, &hc, sizeof(hc), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
-        (e = hipMemsetAsync(c->counter, 0, sizeof(uint32_t), c->stream)) != hipSuccess) {
+        (e = hipMemcpyAsync(c->cs, &hc, sizeof(hc), hipMemcpyHostToDevice, c->stream)) != hipSuccess) {
         hip_fail(c, e, "init copies");
         return bail(HBM_EHIP);
     }

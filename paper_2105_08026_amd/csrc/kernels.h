@@ -1,12 +1,16 @@
 // Kernels of the sampler.
 //
-//  sweep_kernel   one RAM sweep of every object (Sec. 2.2) fused with the
-//                 FP64 reductions the theta step consumes, the selection
-//                 quadrature for the pending theta' (workgroup 0), and an
-//                 epilogue in the last workgroup to finish that reduces the
-//                 tile partials in fixed order and advances the theta chain.
-//  theta_kernel   the theta Metropolis-Hastings step on its own (plain cycle).
-//  poplik_kernel  sum_i log f(chi_i; theta) - N ln Z(theta) for a given theta.
+//  sweep_kernel     one RAM sweep of every object (Sec. 2.2) fused with the
+//                   per-tile FP64 partial sums the theta step consumes, and
+//                   the selection quadrature for the pending theta'
+//                   (workgroup 0).
+//  epilogue_kernel  one workgroup: fixed-order reduction of the partials,
+//                   then the theta Metropolis-Hastings step (fused cycles)
+//                   and the next proposal.  Kept out of the sweep kernel:
+//                   a cross-workgroup release inside it would write back
+//                   the XCD's L2 once per workgroup.
+//  theta_kernel     the theta step on its own (plain cycle).
+//  poplik_kernel    sum_i log f(chi_i; theta) - N ln Z(theta) for a given theta.
 //  init kernels   derived per-object data, factors, quadrature tables.
 #pragma once
 
@@ -22,87 +26,135 @@ struct SweepArgs {
     const T *dd;               // derived per-object data [MD][N]
     T *snaps;                  // latent snapshots or nullptr
     T *trace;                  // [3 + D][N] or nullptr
-    double *partials;          // [n_tiles][2]
-    uint32_t *pacc;            // [n_tiles]
-    uint32_t *counter;         // workgroups finished in this launch
+    double *partials;          // [3][n_tiles]: sum log f, sum of log f changes, accepted moves
+    double *zout;              // ln Z at the pending proposal, written by workgroup 0
     CycleState *cs;
     const Statics *st;
     const double *qx, *qw, *qeps;
-    double *theta_trace;       // [trace_cap][p]
     int64_t n;
     int32_t n_tiles;
 };
 
 // ---------------------------------------------------------------------------
-// Theta-chain arithmetic (FP64, one lane).
+// Theta-chain arithmetic (FP64).  The state is staged in LDS by one
+// workgroup; lane 0 runs the sequential parts on that copy.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void stage_in(CycleState &dst, const CycleState *src)
+{
+    const uint64_t *s = reinterpret_cast<const uint64_t *>(src);
+    uint64_t *d = reinterpret_cast<uint64_t *>(&dst);
+    for (int j = threadIdx.x; j < static_cast<int>(sizeof(CycleState) / 8); j += blockDim.x) d[j] = s[j];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void stage_out(CycleState *dst, const CycleState &src)
+{
+    __syncthreads();
+    const uint64_t *s = reinterpret_cast<const uint64_t *>(&src);
+    uint64_t *d = reinterpret_cast<uint64_t *>(dst);
+    for (int j = threadIdx.x; j < static_cast<int>(sizeof(CycleState) / 8); j += blockDim.x) d[j] = s[j];
+}
+
+// Values of the epilogue that do not depend on the reduction, computed on
+// separate wavefronts while it is in flight: the standard normals of the
+// next proposal (Philox blocks (0, k + 1, 1, b)), ln u of the theta accept
+// test (block (0, k, 2, 0)) and eta of the next sweep.
+struct Precomp {
+    double z[kMaxP];
+    double ln_u;
+    double eta_next;
+};
+
+// k: the sweep whose theta step this epilogue runs (or 0 for none).
 template <class M>
-__device__ void prepare_next(CycleState *c, const Statics &s)
+__device__ __forceinline__ void precompute(Precomp &pc, int64_t k, const Statics &s)
+{
+    constexpr int NB = (M::P + 3) / 4;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    if (wave == 1 && lane < NB) {
+        const Block4 blk = philox(0u, static_cast<uint32_t>(k + 1), 1u, static_cast<uint32_t>(lane), s.key0, s.key1);
+        double z4[4];
+        normals<double, 4>(blk, z4);
+        for (int j = 0; j < 4; ++j)
+            if (4 * lane + j < kMaxP) pc.z[4 * lane + j] = z4[j];
+    }
+    if (wave == 2 && lane == 0) {
+        const Block4 ub = philox(0u, static_cast<uint32_t>(k), 2u, 0u, s.key0, s.key1);
+        pc.ln_u = log(uniform24<double>(ub, 4));
+    }
+    if (wave == 3 && lane == 0) pc.eta_next = pow(static_cast<double>(k + 2), -s.gamma);
+}
+
+// Draws the proposal theta' = theta + S_theta z for sweep k + 1 (c.k == k)
+// and derives the constants that sweep needs.  Called by every thread; the
+// two FP64 transcendentals of theta' run on different wavefronts.
+template <class M>
+__device__ void prepare_next(CycleState &c, const Statics &s, const Precomp &pc)
 {
     using T = typename M::T;
     constexpr int P = M::P;
-    const int64_t kn = c->k + 1;
-    double z[4 * ((P + 3) / 4)];
-#pragma unroll
-    for (int b = 0; b < (P + 3) / 4; ++b) {
-        const Block4 blk = philox(0u, static_cast<uint32_t>(kn), 1u, static_cast<uint32_t>(b), s.key0, s.key1);
-        normals<double, 4>(blk, z + 4 * b);
+    __shared__ double aux_lp[2];
+    if (threadIdx.x == 0) {
+        for (int r = 0; r < P; ++r) {
+            double v = c.theta[r];
+            for (int q = 0; q <= r; ++q) v += c.chol_theta[r * P + q] * pc.z[q];
+            c.prop[r] = v;
+            c.zprop[r] = pc.z[r];
+        }
     }
-    for (int r = 0; r < P; ++r) {
-        double v = c->theta[r];
-        for (int q = 0; q <= r; ++q) v += c->chol_theta[r * P + q] * z[q];
-        c->prop[r] = v;
-        c->zprop[r] = z[r];
+    __syncthreads();
+    if (threadIdx.x == 0) aux_lp[0] = M::aux(c.prop);
+    if (threadIdx.x == kWave) aux_lp[1] = M::log_prior(c.prop);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c.lprior_prop = aux_lp[1];
+        c.prop_valid = c.lprior_prop > -HUGE_VAL;
+        const double *tp = c.prop_valid ? c.prop : c.theta;
+        c.aux_prop = c.prop_valid ? aux_lp[0] : c.aux_cur;
+        M::derive_kc(c.theta, tp, c.aux_cur, c.aux_prop, s, kc_of<T>(&c));
+        M::z_consts(tp, c.aux_prop, c.zc_prop);
+        c.eta_next = pc.eta_next;
     }
-    c->lprior_prop = M::log_prior(c->prop);
-    c->prop_valid = c->lprior_prop > -HUGE_VAL;
-    const double *tp = c->prop_valid ? c->prop : c->theta;
-    M::derive_kc(c->theta, tp, s, kc_of<T>(c));
-    M::z_consts(tp, c->zc_prop);
-    c->eta_next = pow(static_cast<double>(kn + 1), -s.gamma);
+    __syncthreads();
 }
 
+// Metropolis-Hastings step of cycle k on theta (lane 0).
 template <class M>
-__device__ void theta_mh(CycleState *c, const Statics &s, double *theta_trace)
+__device__ void theta_mh(CycleState &c, const Statics &s, double *theta_trace, double ln_u)
 {
     constexpr int P = M::P;
-    if (!c->sums_ready) {
-        c->flags |= kFlagNoSums;
-        return;
-    }
     double delta = -HUGE_VAL;
-    if (c->used_valid) {
-        delta = c->sum_dlf - static_cast<double>(s.n) * (c->logZ_used - c->logZ_cur) + (c->lprior_used - c->lprior_cur);
+    if (c.used_valid) {
+        delta = c.sum_dlf - static_cast<double>(s.n) * (c.logZ_used - c.logZ_cur) + (c.lprior_used - c.lprior_cur);
         if (delta != delta) delta = -HUGE_VAL;
     }
     const double alpha = delta >= 0.0 ? 1.0 : exp(delta);
-    const Block4 ub = philox(0u, static_cast<uint32_t>(c->k), 2u, 0u, s.key0, s.key1);
-    const bool accepted = log(uniform24<double>(ub, 4)) < delta;
+    const bool accepted = ln_u < delta;
     if (accepted) {
-        for (int r = 0; r < P; ++r) c->theta[r] = c->used_prop[r];
-        c->logZ_cur = c->logZ_used;
-        c->lprior_cur = c->lprior_used;
+        for (int r = 0; r < P; ++r) c.theta[r] = c.used_prop[r];
+        c.logZ_cur = c.logZ_used;
+        c.lprior_cur = c.lprior_used;
+        c.aux_cur = c.aux_used;
     }
     if (s.adapt_theta) {
         double L[P * (P + 1) / 2], zz[P];
         for (int r = 0, e = 0; r < P; ++r)
-            for (int q = 0; q <= r; ++q, ++e) L[e] = c->chol_theta[r * P + q];
-        for (int r = 0; r < P; ++r) zz[r] = c->used_z[r];
-        const double eta = pow(static_cast<double>(c->k + 1), -s.gamma);
-        ram_adapt<double, P>(L, zz, eta * (alpha - s.alpha_star_theta));
+            for (int q = 0; q <= r; ++q, ++e) L[e] = c.chol_theta[r * P + q];
+        for (int r = 0; r < P; ++r) zz[r] = c.used_z[r];
+        ram_adapt<double, P>(L, zz, c.eta_used * (alpha - s.alpha_star_theta));
         for (int r = 0, e = 0; r < P; ++r)
-            for (int q = 0; q <= r; ++q, ++e) c->chol_theta[r * P + q] = L[e];
+            for (int q = 0; q <= r; ++q, ++e) c.chol_theta[r * P + q] = L[e];
     }
-    if (c->n_theta < s.trace_cap) {
-        for (int r = 0; r < P; ++r) theta_trace[c->n_theta * P + r] = c->theta[r];
-        c->n_theta += 1;
+    if (c.n_theta < s.trace_cap) {
+        for (int r = 0; r < P; ++r) theta_trace[c.n_theta * P + r] = c.theta[r];
+        c.n_theta += 1;
     } else {
-        c->flags |= kFlagTraceFull;
+        c.flags |= kFlagTraceFull;
     }
-    c->sums_ready = 0;
-    c->delta_last = delta;
-    c->alpha_last = alpha;
-    c->accepted_last = accepted;
+    c.sums_ready = 0;
+    c.delta_last = delta;
+    c.alpha_last = alpha;
+    c.accepted_last = accepted;
 }
 
 // ln Z(theta) = ln sum_j w_j f_x(x_j; theta) eps_j over the fixed ln L rule;
@@ -120,147 +172,162 @@ __device__ __forceinline__ double block_log_z(const double *zc, const double *qx
 }
 
 // ---------------------------------------------------------------------------
-// The sweep.
+// The sweep: workgroup 0 evaluates ln Z at the pending proposal; every
+// other workgroup updates one tile of 256 objects and writes the tile's
+// FP64 partial sums.  No workgroup waits on another: the epilogue kernel
+// that follows on the stream reduces the partials.
 // ---------------------------------------------------------------------------
-template <class M, bool kFull, bool kTrace>
+template <class M, bool kTrace>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> a)
 {
     using T = typename M::T;
     constexpr int D = M::D, NC = M::NC;
     __shared__ double red[3][kWavesPerBlock];
-    __shared__ int is_last;
     CycleState *cs = a.cs;
     const Statics &st = *a.st;
 
     if (blockIdx.x == 0) {
-        if (M::kSelection) {
-            const int valid = cs->prop_valid;
+        if (M::kSelection && cs->prop_valid) {
             double zc[3] = {cs->zc_prop[0], cs->zc_prop[1], cs->zc_prop[2]};
-            if (valid) {
-                const double lz = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
-                if (threadIdx.x == 0) {
-                    cs->logZ_pending = lz;
-                    if (!(lz > -HUGE_VAL && lz < HUGE_VAL)) atomicOr(&cs->flags, kFlagBadZ);
-                }
-            }
+            const double lz = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
+            if (threadIdx.x == 0) a.zout[0] = lz;
         }
-    } else {
-        const int tile = blockIdx.x - 1;
-        const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;
-        const int64_t n = a.n;
-        const int64_t k = cs->k + 1;
-        const T *kc = kc_of<T>(cs);
-        const T eta = static_cast<T>(cs->eta_next);
-        const T astar = static_cast<T>(st.alpha_star);
-        double v[3] = {0.0, 0.0, 0.0};
-        if (i < n) {
-            T x[D], S[NC], U[D], y[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) x[j] = a.chi[j * n + i];
-#pragma unroll
-            for (int e = 0; e < NC; ++e) S[e] = a.chol[e * n + i];
-            uint32_t nacc = a.acc[i];
-            const typename M::Obj o = M::load(a.dd, i, n);
-            const Block4 b = philox(static_cast<uint32_t>(i), static_cast<uint32_t>(k), 0u, 0u, st.key0, st.key1);
-            normals<T, D>(b, U);
-#pragma unroll
-            for (int r = 0; r < D; ++r) {
-                T acc_r = x[r];
-#pragma unroll
-                for (int q = 0; q <= r; ++q) acc_r += S[r * (r + 1) / 2 + q] * U[q];
-                y[r] = acc_r;
-            }
-            const Eval<T> ex = M::eval(o, x, kc, st);
-            const Eval<T> ey = M::eval(o, y, kc, st);
-            const T neg_inf = -static_cast<T>(HUGE_VAL);
-            const T delta = (ey.lpv > neg_inf) ? ey.lpv - ex.lpv : neg_inf;
-            const bool accept = log(uniform24<T>(b, 4)) < delta;
-            const T alpha = delta >= static_cast<T>(0) ? static_cast<T>(1) : exp(delta);
-            if (accept) {
-#pragma unroll
-                for (int j = 0; j < D; ++j) x[j] = y[j];
-                nacc += 1u;
-            }
-            const Eval<T> en = accept ? ey : ex;
-            ram_adapt<T, D>(S, U, eta * (alpha - astar));
-#pragma unroll
-            for (int j = 0; j < D; ++j) a.chi[j * n + i] = x[j];
-#pragma unroll
-            for (int e = 0; e < NC; ++e) a.chol[e * n + i] = S[e];
-            a.acc[i] = nacc;
-            v[0] = static_cast<double>(en.lf);
-            v[1] = static_cast<double>(M::dlf(o, x, en, kc, st));
-            v[2] = accept ? 1.0 : 0.0;
-            if (!(ex.lpv > neg_inf)) atomicOr(&cs->flags, kFlagNonFiniteState);
-            if (kTrace) {
-                a.trace[i] = ex.lp;
-                a.trace[n + i] = ey.lp;
-                a.trace[2 * n + i] = accept ? static_cast<T>(1) : static_cast<T>(0);
-#pragma unroll
-                for (int j = 0; j < D; ++j) a.trace[(3 + j) * n + i] = y[j];
-            }
-            if (a.snaps != nullptr && st.thin > 0 && k % st.thin == 0) {
-                const int64_t snap = k / st.thin - 1;
-                if (snap < st.snap_cap) {
-#pragma unroll
-                    for (int j = 0; j < D; ++j) a.snaps[(snap * D + j) * n + i] = x[j];
-                }
-            }
-        }
-        block_sum<3>(v, red);
-        if (threadIdx.x == 0) {
-            a.partials[2 * tile] = v[0];
-            a.partials[2 * tile + 1] = v[1];
-            a.pacc[tile] = static_cast<uint32_t>(v[2]);
-        }
+        return;
     }
-
-    // Last workgroup to finish runs the epilogue.
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        is_last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+    const int tile = blockIdx.x - 1;
+    const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;
+    const int64_t n = a.n;
+    const int64_t k = cs->k + 1;
+    const T *kc = kc_of<T>(cs);
+    const T eta = static_cast<T>(cs->eta_next);
+    const T astar = static_cast<T>(st.alpha_star);
     double v[3] = {0.0, 0.0, 0.0};
-    for (int t = threadIdx.x; t < a.n_tiles; t += kBlock) {
-        v[0] += a.partials[2 * t];
-        v[1] += a.partials[2 * t + 1];
-        v[2] += static_cast<double>(a.pacc[t]);
+    if (i < n) {
+        T x[D], S[NC], U[D], y[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[j] = a.chi[j * n + i];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) S[e] = a.chol[e * n + i];
+        uint32_t nacc = a.acc[i];
+        const typename M::Obj o = M::load(a.dd, i, n);
+        const Block4 b = philox(static_cast<uint32_t>(i), static_cast<uint32_t>(k), 0u, 0u, st.key0, st.key1);
+        normals<T, D>(b, U);
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            T acc_r = x[r];
+#pragma unroll
+            for (int q = 0; q <= r; ++q) acc_r += S[r * (r + 1) / 2 + q] * U[q];
+            y[r] = acc_r;
+        }
+        const Eval<T> ex = M::eval(o, x, kc, st);
+        const Eval<T> ey = M::eval(o, y, kc, st);
+        const T neg_inf = -static_cast<T>(HUGE_VAL);
+        const T delta = (ey.lpv > neg_inf) ? ey.lpv - ex.lpv : neg_inf;
+        const bool accept = log(uniform24<T>(b, 4)) < delta;
+        const T alpha = delta >= static_cast<T>(0) ? static_cast<T>(1) : exp(delta);
+        if (accept) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) x[j] = y[j];
+            nacc += 1u;
+        }
+        const Eval<T> en = accept ? ey : ex;
+        ram_adapt<T, D>(S, U, eta * (alpha - astar));
+#pragma unroll
+        for (int j = 0; j < D; ++j) a.chi[j * n + i] = x[j];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) a.chol[e * n + i] = S[e];
+        a.acc[i] = nacc;
+        v[0] = static_cast<double>(en.lf);
+        v[1] = static_cast<double>(M::dlf(o, x, en, kc, st));
+        v[2] = accept ? 1.0 : 0.0;
+        if (!(ex.lpv > neg_inf)) atomicOr(&cs->flags, kFlagNonFiniteState);
+        if (kTrace) {
+            a.trace[i] = ex.lp;
+            a.trace[n + i] = ey.lp;
+            a.trace[2 * n + i] = accept ? static_cast<T>(1) : static_cast<T>(0);
+#pragma unroll
+            for (int j = 0; j < D; ++j) a.trace[(3 + j) * n + i] = y[j];
+        }
+        if (a.snaps != nullptr && st.thin > 0 && k % st.thin == 0) {
+            const int64_t snap = k / st.thin - 1;
+            if (snap < st.snap_cap) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) a.snaps[(snap * D + j) * n + i] = x[j];
+            }
+        }
     }
     block_sum<3>(v, red);
     if (threadIdx.x == 0) {
-        cs->k += 1;
-        cs->sum_lf = v[0];
-        cs->sum_dlf = v[1];
-        cs->n_acc_last = v[2];
-        for (int r = 0; r < M::P; ++r) {
-            cs->used_prop[r] = cs->prop[r];
-            cs->used_z[r] = cs->zprop[r];
-        }
-        cs->logZ_used = cs->logZ_pending;
-        cs->lprior_used = cs->lprior_prop;
-        cs->used_valid = cs->prop_valid;
-        cs->sums_ready = 1;
-        if (kFull) theta_mh<M>(cs, st, a.theta_trace);
-        prepare_next<M>(cs, st);
-        *a.counter = 0u;
+        a.partials[tile] = v[0];
+        a.partials[a.n_tiles + tile] = v[1];
+        a.partials[2 * a.n_tiles + tile] = v[2];
     }
 }
 
-template <class M>
-__global__ void theta_kernel(CycleState *cs, const Statics *st, double *theta_trace)
+// Epilogue of a sweep (one workgroup): fixed-order reduction of the tile
+// partials, bookkeeping, then (kFull) the theta step, then the proposal
+// for the next sweep.
+template <class M, bool kFull>
+__global__ __launch_bounds__(kBlock) void epilogue_kernel(CycleState *cs, const Statics *stp, const double *partials,
+                                                          const double *zout, double *theta_trace, int32_t n_tiles)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (!cs->sums_ready) {
-            cs->flags |= kFlagNoSums;
-            return;
-        }
-        theta_mh<M>(cs, *st, theta_trace);
-        prepare_next<M>(cs, *st);
+    __shared__ CycleState c;
+    __shared__ Precomp pc;
+    __shared__ double red[3][kWavesPerBlock];
+    const Statics &st = *stp;
+    const int64_t kd = cs->k + 1;        // the sweep being finished
+    precompute<M>(pc, kd, st);           // waves 1-3, overlapping the loads below
+    // tile partials, structure of arrays [3][n_tiles]
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int t = threadIdx.x; t < n_tiles; t += kBlock) {
+        v[0] += partials[t];
+        v[1] += partials[n_tiles + t];
+        v[2] += partials[2 * n_tiles + t];
     }
+    stage_in(c, cs);
+    block_sum<3>(v, red);                // its barrier also publishes pc
+    if (threadIdx.x == 0) {
+        c.k = kd;
+        c.sum_lf = v[0];
+        c.sum_dlf = v[1];
+        c.n_acc_last = v[2];
+        for (int r = 0; r < M::P; ++r) {
+            c.used_prop[r] = c.prop[r];
+            c.used_z[r] = c.zprop[r];
+        }
+        c.logZ_used = (M::kSelection && c.prop_valid) ? zout[0] : 0.0;
+        c.lprior_used = c.lprior_prop;
+        c.used_valid = c.prop_valid;
+        c.aux_used = c.aux_prop;
+        c.eta_used = c.eta_next;
+        c.sums_ready = 1;
+        if (M::kSelection && c.prop_valid && !(c.logZ_used > -HUGE_VAL && c.logZ_used < HUGE_VAL))
+            c.flags |= kFlagBadZ;
+        if (kFull) theta_mh<M>(c, st, theta_trace, pc.ln_u);
+    }
+    __syncthreads();
+    prepare_next<M>(c, st, pc);
+    stage_out(cs, c);
+}
+
+// Theta step on its own, after a ram_sweep (plain cycle).
+template <class M>
+__global__ __launch_bounds__(kBlock) void theta_kernel(CycleState *cs, const Statics *st, double *theta_trace)
+{
+    __shared__ CycleState c;
+    __shared__ Precomp pc;
+    stage_in(c, cs);
+    const bool ready = c.sums_ready != 0;
+    precompute<M>(pc, c.k, *st);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (ready) theta_mh<M>(c, *st, theta_trace, pc.ln_u);
+        else c.flags |= kFlagNoSums;
+    }
+    __syncthreads();
+    if (ready) prepare_next<M>(c, *st, pc);
+    stage_out(cs, c);
 }
 
 // Recompute everything that depends on theta after it is set from the host.
@@ -268,19 +335,29 @@ template <class M>
 __global__ __launch_bounds__(kBlock) void set_theta_kernel(CycleState *cs, const Statics *st, const double *qx,
                                                            const double *qw, const double *qeps)
 {
+    __shared__ CycleState c;
     __shared__ double red[1][kWavesPerBlock];
+    stage_in(c, cs);
+    const double lp = M::log_prior(c.theta);
     double zc[3];
-    M::z_consts(cs->theta, zc);
-    const double lp = M::log_prior(cs->theta);
     double lz = 0.0;
-    if (M::kSelection && lp > -HUGE_VAL) lz = block_log_z(zc, qx, qw, qeps, st->nq, red);
-    if (threadIdx.x == 0) {
-        cs->lprior_cur = lp;
-        cs->logZ_cur = lz;
-        if (M::kSelection && lp > -HUGE_VAL && !(lz > -HUGE_VAL && lz < HUGE_VAL)) cs->flags |= kFlagBadZ;
-        cs->sums_ready = 0;
-        prepare_next<M>(cs, *st);
+    if (M::kSelection && lp > -HUGE_VAL) {
+        const double ag = M::aux(c.theta);
+        M::z_consts(c.theta, ag, zc);
+        lz = block_log_z(zc, qx, qw, qeps, st->nq, red);
     }
+    __shared__ Precomp pc;
+    precompute<M>(pc, c.k, *st);
+    if (threadIdx.x == 0) {
+        c.lprior_cur = lp;
+        c.logZ_cur = lz;
+        c.aux_cur = lp > -HUGE_VAL ? M::aux(c.theta) : 0.0;
+        if (M::kSelection && lp > -HUGE_VAL && !(lz > -HUGE_VAL && lz < HUGE_VAL)) c.flags |= kFlagBadZ;
+        c.sums_ready = 0;
+    }
+    __syncthreads();
+    prepare_next<M>(c, *st, pc);
+    stage_out(cs, c);
 }
 
 template <class M>
@@ -333,62 +410,59 @@ struct PopArgs {
     const T *chi;
     const T *dd;
     double *partials;
-    uint32_t *counter;
-    CycleState *cs;
+    double *zout;
     const Statics *st;
     const double *qx, *qw, *qeps;
     int64_t n;
-    int32_t n_tiles;
     double theta[kMaxP];
 };
 
+// Partial sums of log f(chi_i; theta) per tile; workgroup 0 evaluates ln Z(theta).
 template <class M>
 __global__ __launch_bounds__(kBlock) void poplik_kernel(PopArgs<typename M::T> a)
 {
     using T = typename M::T;
     __shared__ double red[1][kWavesPerBlock];
     __shared__ T kc[32];
-    __shared__ double logz;
-    __shared__ int is_last;
     const Statics &st = *a.st;
     if (blockIdx.x == 0) {
         if (M::kSelection) {
             double zc[3];
-            M::z_consts(a.theta, zc);
+            M::z_consts(a.theta, M::aux(a.theta), zc);
             const double lz = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
-            if (threadIdx.x == 0) a.cs->poplik_logz = lz;
+            if (threadIdx.x == 0) a.zout[1] = lz;
         } else if (threadIdx.x == 0) {
-            a.cs->poplik_logz = 0.0;
+            a.zout[1] = 0.0;
         }
-    } else {
-        if (threadIdx.x == 0) M::derive_kc(a.theta, a.theta, st, kc);
-        __syncthreads();
-        const int tile = blockIdx.x - 1;
-        const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;
-        double v[1] = {0.0};
-        if (i < a.n) {
-            T x[M::D];
-            for (int j = 0; j < M::D; ++j) x[j] = a.chi[j * a.n + i];
-            v[0] = static_cast<double>(M::eval(M::load(a.dd, i, a.n), x, kc, st).lf);
-        }
-        block_sum<1>(v, red);
-        if (threadIdx.x == 0) a.partials[tile] = v[0];
+        return;
     }
-    __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        is_last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
+        const double ag = M::aux(a.theta);
+        M::derive_kc(a.theta, a.theta, ag, ag, st, kc);
     }
     __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+    const int tile = blockIdx.x - 1;
+    const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;
     double v[1] = {0.0};
-    for (int t = threadIdx.x; t < a.n_tiles; t += kBlock) v[0] += a.partials[t];
+    if (i < a.n) {
+        T x[M::D];
+        for (int j = 0; j < M::D; ++j) x[j] = a.chi[j * a.n + i];
+        v[0] = static_cast<double>(M::eval(M::load(a.dd, i, a.n), x, kc, st).lf);
+    }
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) a.partials[tile] = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void poplik_finish_kernel(CycleState *cs, const double *partials,
+                                                               const double *zout, int64_t n, int32_t n_tiles)
+{
+    __shared__ double red[1][kWavesPerBlock];
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < n_tiles; t += kBlock) v[0] += partials[t];
     block_sum<1>(v, red);
     if (threadIdx.x == 0) {
-        logz = a.cs->poplik_logz;
-        a.cs->poplik_out = v[0] - static_cast<double>(a.n) * logz;
-        *a.counter = 0u;
+        cs->poplik_logz = zout[1];
+        cs->poplik_out = v[0] - static_cast<double>(n) * zout[1];
     }
 }
 

@@ -62,8 +62,9 @@ struct NN1D {
     }
     __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{dd[i], dd[n + i]}; }
     __device__ static double log_prior(const double *th) { return th[1]; }
-    __device__ static void z_consts(const double *, double *zc) { zc[0] = zc[1] = zc[2] = 0.0; }
-    __device__ static void derive_kc(const double *th, const double *tp, const Statics &, T *kc)
+    __device__ static double aux(const double *) { return 0.0; }
+    __device__ static void z_consts(const double *, double, double *zc) { zc[0] = zc[1] = zc[2] = 0.0; }
+    __device__ static void derive_kc(const double *th, const double *tp, double, double, const Statics &, T *kc)
     {
         kc[0] = th[0];
         kc[1] = exp(-th[1]);
@@ -133,8 +134,9 @@ struct NN3D {
     }
     __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{{dd[i], dd[n + i], dd[2 * n + i]}}; }
     __device__ static double log_prior(const double *) { return 0.0; }
-    __device__ static void z_consts(const double *, double *zc) { zc[0] = zc[1] = zc[2] = 0.0; }
-    __device__ static void derive_kc(const double *th, const double *tp, const Statics &, T *kc)
+    __device__ static double aux(const double *) { return 0.0; }
+    __device__ static void z_consts(const double *, double, double *zc) { zc[0] = zc[1] = zc[2] = 0.0; }
+    __device__ static void derive_kc(const double *th, const double *tp, double, double, const Statics &, T *kc)
     {
         for (int j = 0; j < 3; ++j) {
             kc[j] = th[j];
@@ -176,9 +178,9 @@ struct NN3D {
 //     [6] (beta' + 1)(ln L*' - ln L*) + lnGamma(beta'+1) - lnGamma(beta+1).
 // With q = chi - ln L*:  log f' - log f = (beta' - beta) q - e^q [5] - [6].
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void gamma_kc(const double *th, const double *tp, float *kc)
+// lg, lgp: lnGamma(beta + 1) of theta and theta' (cached per proposal).
+__device__ __forceinline__ void gamma_kc(const double *th, const double *tp, double lg, double lgp, float *kc)
 {
-    const double lg = lgamma(th[0] + 1.0), lgp = lgamma(tp[0] + 1.0);
     const float head = static_cast<float>(th[1]);
     kc[0] = static_cast<float>(th[0] + 1.0);
     kc[1] = head;
@@ -221,13 +223,18 @@ struct LF1D {
     }
     __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{dd[i], dd[n + i], dd[2 * n + i]}; }
     __device__ static double log_prior(const double *th) { return lf_beta_prior(th[0]); }
-    __device__ static void z_consts(const double *th, double *zc)
+    // the one transcendental per theta the sweeps need in FP64: lnGamma(beta + 1)
+    __device__ static double aux(const double *th) { return lgamma(th[0] + 1.0); }
+    __device__ static void z_consts(const double *th, double lg, double *zc)
     {
         zc[0] = th[0] + 1.0;
         zc[1] = th[1];
-        zc[2] = lgamma(th[0] + 1.0);
+        zc[2] = lg;
     }
-    __device__ static void derive_kc(const double *th, const double *tp, const Statics &, T *kc) { gamma_kc(th, tp, kc); }
+    __device__ static void derive_kc(const double *th, const double *tp, double lg, double lgp, const Statics &, T *kc)
+    {
+        gamma_kc(th, tp, lg, lgp, kc);
+    }
     __device__ static Eval<T> eval(const Obj &o, const T *x, const T *kc, const Statics &)
     {
         Eval<T> e;
@@ -297,10 +304,11 @@ struct LF3D {
     {
         return th[4] > 0.0 ? lf_beta_prior(th[0]) : -HUGE_VAL;
     }
-    __device__ static void z_consts(const double *th, double *zc) { LF1D::z_consts(th, zc); }
-    __device__ static void derive_kc(const double *th, const double *tp, const Statics &, T *kc)
+    __device__ static double aux(const double *th) { return LF1D::aux(th); }
+    __device__ static void z_consts(const double *th, double lg, double *zc) { LF1D::z_consts(th, lg, zc); }
+    __device__ static void derive_kc(const double *th, const double *tp, double lg, double lgp, const Statics &, T *kc)
     {
-        gamma_kc(th, tp, kc);
+        gamma_kc(th, tp, lg, lgp, kc);
         kc[7] = static_cast<float>(th[2]);
         kc[8] = static_cast<float>(th[3]);
         kc[9] = static_cast<float>(1.0 / th[4]);
