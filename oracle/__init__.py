@@ -31,16 +31,17 @@ def build(force: bool = True) -> str:
     return LIB_PATH
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(path: str = None):
+    """The oracle library at ``path`` (default: the one built here), typed for ctypes."""
+    path = path or LIB_PATH
+    if path not in _libs:
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        d, i64, u64, i32, u32 = ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32
+        L = ctypes.CDLL(path)
+        d, i64, u64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
         P = ctypes.c_void_p
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_variates.argtypes = [u64, P, P, P]
@@ -66,28 +67,42 @@ def lib():
         L.orc_theta_step.argtypes = [P, i64, P, P, P, P]
         L.orc_theta_step.restype = i32
         L.orc_run.argtypes = [P, i64, i64, P, P, P, P, P, P, P, i64, i32, i32]
-        _ = u32
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
+
+
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile oracle source text (e.g. a deliberately altered copy) to ``out_path``."""
+    src = out_path + ".c"
+    with open(src, "w") as f:
+        f.write(src_text)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-I", _HERE,
+                    "-o", out_path, src, "-lm"], check=True)
+    return out_path
+
+
+def source() -> str:
+    with open(_SRC) as f:
+        return f.read()
 
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def philox4x32_10(ctr, key) -> np.ndarray:
+def philox4x32_10(ctr, key, lib_path: str = None) -> np.ndarray:
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.zeros(4, dtype=np.uint32)
-    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    lib(lib_path).orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
     return out
 
 
-def variates(seed: int, ctr):
+def variates(seed: int, ctr, lib_path: str = None):
     c = np.ascontiguousarray(ctr, dtype=np.uint32)
     u = np.zeros(5)
     z = np.zeros(4)
-    lib().orc_variates(ctypes.c_uint64(seed), _ptr(c), _ptr(u), _ptr(z))
+    lib(lib_path).orc_variates(ctypes.c_uint64(seed), _ptr(c), _ptr(u), _ptr(z))
     return u, z
 
 
@@ -95,10 +110,10 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
-def gauss_legendre(n: int, a: float, b: float):
+def gauss_legendre(n: int, a: float, b: float, lib_path: str = None):
     x = np.zeros(n)
     w = np.zeros(n)
-    lib().orc_gauss_legendre(n, a, b, _ptr(x), _ptr(w))
+    lib(lib_path).orc_gauss_legendre(n, a, b, _ptr(x), _ptr(w))
     return x, w
 
 
@@ -121,14 +136,15 @@ class Oracle:
     """FP64 reference sampler for one dataset (a :class:`synth.workloads.Workload`)."""
 
     def __init__(self, wl, nq: int = 512, gamma: float = 2.0 / 3.0, alpha_star=None,
-                 alpha_star_theta: float = 0.4, adapt_theta: bool = True, seed=None):
+                 alpha_star_theta: float = 0.4, adapt_theta: bool = True, seed=None, lib_path: str = None):
+        self._L = lib(lib_path)
         self.wl = wl
         self.n, self.d, self.p = wl.n, wl.d, wl.p
         self.alpha_star = wl.alpha_star if alpha_star is None else alpha_star
         data = np.ascontiguousarray(wl.data, dtype=np.float64)
         consts = np.ascontiguousarray(wl.consts, dtype=np.float64)
         self.seed = wl.seed if seed is None else seed
-        self._h = lib().orc_new(wl.model, wl.n, _ptr(data), _ptr(consts), ctypes.c_uint64(self.seed),
+        self._h = self._L.orc_new(wl.model, wl.n, _ptr(data), _ptr(consts), ctypes.c_uint64(self.seed),
                                 self.alpha_star, gamma, alpha_star_theta, int(adapt_theta), nq)
         if not self._h:
             raise ValueError("oracle: unknown model")
@@ -136,7 +152,7 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_free(h)
+            self._L.orc_free(h)
             self._h = None
 
     # -- state ----------------------------------------------------------
@@ -159,28 +175,28 @@ class Oracle:
         th = np.ascontiguousarray(theta, dtype=np.float64)
         lm = ctypes.c_double()
         lp = ctypes.c_double()
-        lib().orc_log_terms(self._h, i, _ptr(xv), _ptr(th), ctypes.byref(lm), ctypes.byref(lp))
+        self._L.orc_log_terms(self._h, i, _ptr(xv), _ptr(th), ctypes.byref(lm), ctypes.byref(lp))
         return lm.value, lp.value
 
     def log_prior(self, theta) -> float:
-        return lib().orc_log_prior(self._h, _ptr(np.ascontiguousarray(theta, dtype=np.float64)))
+        return self._L.orc_log_prior(self._h, _ptr(np.ascontiguousarray(theta, dtype=np.float64)))
 
     def log_Z(self, theta) -> float:
-        return lib().orc_log_Z(self._h, _ptr(np.ascontiguousarray(theta, dtype=np.float64)))
+        return self._L.orc_log_Z(self._h, _ptr(np.ascontiguousarray(theta, dtype=np.float64)))
 
     def eps(self, x: float) -> float:
-        return lib().orc_eps(self._h, float(x))
+        return self._L.orc_eps(self._h, float(x))
 
     def pop_sum(self, theta, chi) -> float:
         th = np.ascontiguousarray(theta, dtype=np.float64)
         c = np.ascontiguousarray(chi, dtype=np.float64)
-        return lib().orc_pop_sum(self._h, _ptr(th), _ptr(c))
+        return self._L.orc_pop_sum(self._h, _ptr(th), _ptr(c))
 
     def pop_terms(self, theta, chi) -> np.ndarray:
         th = np.ascontiguousarray(theta, dtype=np.float64)
         c = np.ascontiguousarray(chi, dtype=np.float64)
         out = np.zeros(self.n)
-        lib().orc_pop_terms(self._h, _ptr(th), _ptr(c), _ptr(out))
+        self._L.orc_pop_terms(self._h, _ptr(th), _ptr(c), _ptr(out))
         return out
 
     def log_post(self, theta, pts) -> np.ndarray:
@@ -188,7 +204,7 @@ class Oracle:
         th = np.ascontiguousarray(theta, dtype=np.float64)
         x = np.ascontiguousarray(pts, dtype=np.float64)
         out = np.zeros(self.n)
-        lib().orc_log_post(self._h, _ptr(th), _ptr(x), _ptr(out))
+        self._L.orc_log_post(self._h, _ptr(th), _ptr(x), _ptr(out))
         return out
 
     def pop_loglik(self, theta, chi) -> float:
@@ -201,7 +217,7 @@ class Oracle:
         kk = st.k + 1 if k is None else k
         th = np.ascontiguousarray(st.theta if theta is None else theta, dtype=np.float64)
         tr = np.zeros((self.n, 5)) if trace else None
-        lib().orc_sweep(self._h, kk, _ptr(th), _ptr(st.chi), _ptr(st.chol), _ptr(st.acc),
+        self._L.orc_sweep(self._h, kk, _ptr(th), _ptr(st.chi), _ptr(st.chol), _ptr(st.acc),
                         _ptr(tr) if trace else None)
         st.k = kk
         return tr
@@ -209,14 +225,14 @@ class Oracle:
     def theta_proposal(self, st: State, k=None) -> np.ndarray:
         kk = st.k if k is None else k
         out = np.zeros(self.p)
-        lib().orc_theta_proposal(self._h, kk, _ptr(st.theta), _ptr(st.chol_theta), _ptr(out))
+        self._L.orc_theta_proposal(self._h, kk, _ptr(st.theta), _ptr(st.chol_theta), _ptr(out))
         return out
 
     def theta_step(self, st: State, k=None):
         """Theta step of cycle k (default: the sweep just done).  Returns info dict."""
         kk = st.k if k is None else k
         info = np.zeros(6)
-        lib().orc_theta_step(self._h, kk, _ptr(st.theta), _ptr(st.chol_theta), _ptr(st.chi), _ptr(info))
+        self._L.orc_theta_step(self._h, kk, _ptr(st.theta), _ptr(st.chol_theta), _ptr(st.chi), _ptr(info))
         return {"delta": info[0], "ln_u": info[1], "accepted": bool(info[2]), "alpha": info[3],
                 "sum_prop": info[4], "sum_cur": info[5]}
 
@@ -228,7 +244,7 @@ class Oracle:
         if chi_trace and thin > 0:
             n_snap = (st.k + n_cycles) // thin - st.k // thin
             ct = np.zeros((n_snap, self.d, self.n))
-        lib().orc_run(self._h, st.k, n_cycles, _ptr(st.theta), _ptr(st.chol_theta), _ptr(st.chi),
+        self._L.orc_run(self._h, st.k, n_cycles, _ptr(st.theta), _ptr(st.chol_theta), _ptr(st.chi),
                       _ptr(st.chol), _ptr(st.acc), _ptr(tt), _ptr(ct) if ct is not None else None,
                       thin, int(fix_theta), int(fix_chi))
         st.k += n_cycles

@@ -29,16 +29,15 @@ __device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi_b ^ c1 ^ key0;
-        const uint32_t n2 = hi_a ^ c3 ^ key1;
+        // one 32x32 -> 64-bit multiply each (a single v_mad_u64_u32)
+        const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ key0;
+        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ key1;
         c0 = n0;
-        c1 = lo_b;
+        c1 = static_cast<uint32_t>(pb);
         c2 = n2;
-        c3 = lo_a;
+        c3 = static_cast<uint32_t>(pa);
         key0 += 0x9E3779B9u;
         key1 += 0xBB67AE85u;
     }
@@ -65,25 +64,62 @@ __device__ __forceinline__ T uniform24(const Block4 &b, int j)
     return static_cast<T>(field24(b, j) + 1u) * static_cast<T>(5.9604644775390625e-08);
 }
 
-__device__ __forceinline__ void sincos_2pi(float u, float *s, float *c) { sincospif(2.0f * u, s, c); }
-__device__ __forceinline__ void sincos_2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
+// Box-Muller (1958): (u0, u1) -> z0, z1 and (u2, u3) -> z2, z3.  In single
+// precision the hardware transcendentals are used directly: v_cos_f32 and
+// v_sin_f32 take their argument in revolutions (cos(2 pi u) is one
+// instruction), v_log_f32 is log2.  The per-object log densities keep the
+// correctly rounded library functions.
+__device__ __forceinline__ float ln_fast(float u) { return __builtin_amdgcn_logf(u) * 0.693147180559945309f; }
 
-// Box-Muller (1958): (u0, u1) -> z0, z1 and (u2, u3) -> z2, z3.
 template <typename T, int NZ>
-__device__ __forceinline__ void normals(const Block4 &b, T *z)
+__device__ __forceinline__ void normals(const Block4 &b, T *z);
+
+template <int NZ>
+__device__ __forceinline__ void normals_f(const Block4 &b, float *z)
 {
-    const T r0 = sqrt(static_cast<T>(-2) * log(uniform24<T>(b, 0)));
-    T s, c;
-    sincos_2pi(uniform24<T>(b, 1), &s, &c);
+    const float u1 = uniform24<float>(b, 1);
+    const float r0 = __builtin_amdgcn_sqrtf(-2.0f * ln_fast(uniform24<float>(b, 0)));
+    z[0] = r0 * __builtin_amdgcn_cosf(u1);
+    if (NZ > 1) z[1] = r0 * __builtin_amdgcn_sinf(u1);
+    if (NZ > 2) {
+        const float u3 = uniform24<float>(b, 3);
+        const float r1 = __builtin_amdgcn_sqrtf(-2.0f * ln_fast(uniform24<float>(b, 2)));
+        z[2] = r1 * __builtin_amdgcn_cosf(u3);
+        if (NZ > 3) z[3] = r1 * __builtin_amdgcn_sinf(u3);
+    }
+}
+
+template <int NZ>
+__device__ __forceinline__ void normals_d(const Block4 &b, double *z)
+{
+    double s, c;
+    const double r0 = sqrt(-2.0 * log(uniform24<double>(b, 0)));
+    sincospi(2.0 * uniform24<double>(b, 1), &s, &c);
     z[0] = r0 * c;
     if (NZ > 1) z[1] = r0 * s;
     if (NZ > 2) {
-        const T r1 = sqrt(static_cast<T>(-2) * log(uniform24<T>(b, 2)));
-        sincos_2pi(uniform24<T>(b, 3), &s, &c);
+        const double r1 = sqrt(-2.0 * log(uniform24<double>(b, 2)));
+        sincospi(2.0 * uniform24<double>(b, 3), &s, &c);
         z[2] = r1 * c;
         if (NZ > 3) z[3] = r1 * s;
     }
 }
+
+template <typename T, int NZ>
+__device__ __forceinline__ void normals(const Block4 &b, T *z)
+{
+    if constexpr (sizeof(T) == 4) normals_f<NZ>(b, z);
+    else normals_d<NZ>(b, z);
+}
+
+// ln of the accept uniform, and alpha = min(1, e^delta) for the adaptation.
+__device__ __forceinline__ float ln_uniform(const Block4 &b, float) { return ln_fast(uniform24<float>(b, 4)); }
+__device__ __forceinline__ double ln_uniform(const Block4 &b, double) { return log(uniform24<double>(b, 4)); }
+__device__ __forceinline__ float accept_prob(float delta)
+{
+    return delta >= 0.0f ? 1.0f : __builtin_amdgcn_exp2f(delta * 1.44269504088896341f);
+}
+__device__ __forceinline__ double accept_prob(double delta) { return delta >= 0.0 ? 1.0 : exp(delta); }
 
 // ---------------------------------------------------------------------------
 // Rank-1 modification of a Cholesky factor: L' L'^T = L L^T + beta x x^T.
@@ -144,16 +180,40 @@ __device__ __forceinline__ void ram_adapt(T *S, const T *U, T c)
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic reductions.  A wavefront sums with a fixed xor butterfly; a
+// Deterministic reductions.  A wavefront sums with fixed DPP steps; a
 // workgroup adds its four wave sums in fixed order.  The result depends only
 // on the values and their lane positions, never on timing.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
+// One DPP move of a double (both 32-bit halves), all rows and banks enabled.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    const uint64_t bits = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits & 0xffffffffu), kCtrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits >> 32), kCtrl, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(lo));
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane)
+{
+    const uint64_t bits = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(bits & 0xffffffffu), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), lane);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Wavefront sum in a fixed order: within each quad (DPP quad_perm swaps),
+// then across the four quads of each 16-lane row (DPP row rotations), then
+// the four row sums read from lanes 0, 16, 32, 48 and added pairwise.  The
+// value read from each row's lane 0 is ((q0 + q1) + (q2 + q3)) of its quads.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x124>(v);   // row_ror:4
+    v += dpp_f64<0x128>(v);   // row_ror:8
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 // Sums NV values over the workgroup; result valid in thread 0.
@@ -198,7 +258,7 @@ struct CycleState {
     double lprior_cur, lprior_prop, lprior_used;
     double eta_next;               // eta of sweep k + 1
     double eta_used;               // eta of the sweep just done (also the theta step's)
-    double aux_cur, aux_prop, aux_used;   // per-theta model scalar (lnGamma(beta + 1) for LF models)
+    double aux_cur[2], aux_used[2];       // per-theta model scalars (lnGamma(beta + 1), ln s)
     double sum_lf;                 // sum_i log f(chi_i; theta) after the last sweep
     double sum_dlf;                // sum_i [log f(chi_i; used_prop) - log f(chi_i; theta)]
     double n_acc_last;             // accepted latent moves in the last sweep
@@ -206,6 +266,7 @@ struct CycleState {
     double poplik_out;             // result slot of pop_loglik
     double poplik_logz;
     double zc_prop[4];             // FP64 constants of the pending proposal for the quadrature
+    double sum_dlf_raw;            // per-object part of sum_dlf as reduced from the tiles
     int64_t k;                     // sweeps done
     int64_t n_theta;               // theta steps done (= trace rows written)
     int32_t prop_valid, used_valid;

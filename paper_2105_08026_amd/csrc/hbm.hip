@@ -44,7 +44,8 @@ struct CtxImpl {
     hipStream_t capture_stream = nullptr;
     void *dd = nullptr;
     double *partials = nullptr;     // [n_tiles][3]
-    double *zout = nullptr;         // [2]: ln Z at the pending proposal, ln Z of pop_loglik
+    double *zout = nullptr;         // [2]: ln Z of pop_loglik
+    Precomp *side = nullptr;        // values the sweep's workgroup 0 leaves for the epilogue
     double *ref_t = nullptr, *ref_w = nullptr, *qx = nullptr, *qw = nullptr, *qeps = nullptr;
     CycleState *cs = nullptr;
     Statics *st = nullptr;
@@ -126,7 +127,7 @@ struct Ops {
         a.snaps = static_cast<T *>(c->buf.chi_samples);
         a.trace = static_cast<T *>(trace);
         a.partials = c->partials;
-        a.zout = c->zout;
+        a.side = c->side;
         a.cs = c->cs;
         a.st = c->st;
         a.qx = c->qx;
@@ -159,17 +160,18 @@ struct Ops {
         }
         if (full)
             hipLaunchKernelGGL((epilogue_kernel<M, true>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st,
-                               c->partials, c->zout, c->theta_trace, c->n_tiles);
+                               c->partials, c->side, c->theta_trace, c->n_tiles);
         else
             hipLaunchKernelGGL((epilogue_kernel<M, false>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st,
-                               c->partials, c->zout, c->theta_trace, c->n_tiles);
+                               c->partials, c->side, c->theta_trace, c->n_tiles);
         LAUNCHCHK(c, "epilogue_kernel");
         return HBM_OK;
     }
 
     static hbm_status theta(CtxImpl *c)
     {
-        hipLaunchKernelGGL((theta_kernel<M>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st, c->theta_trace);
+        hipLaunchKernelGGL((theta_kernel<M>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st, c->side,
+                           c->theta_trace);
         LAUNCHCHK(c, "theta_kernel");
         return HBM_OK;
     }
@@ -306,7 +308,7 @@ void release(CtxImpl *c)
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
-    void *ptrs[] = {c->dd, c->partials, c->zout, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
+    void *ptrs[] = {c->dd, c->partials, c->zout, c->side, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
                     c->cs, c->st, c->theta_trace};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -427,6 +429,7 @@ hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, con
     if ((s = alloc(&c->dd, c->esize * c->md * c->n)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->partials), sizeof(double) * 3 * c->n_tiles)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->zout), sizeof(double) * 2)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->side), sizeof(Precomp))) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->ref_t), sizeof(double) * nq)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->ref_w), sizeof(double) * nq)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->qx), sizeof(double) * nq)) != HBM_OK ||

@@ -18,6 +18,26 @@
 
 namespace hbm {
 
+// Values an epilogue needs that do not depend on the tile reduction.  The
+// sweep kernel's workgroup 0 computes them while the object tiles run (and
+// set_theta_kernel for a theta set from the host), one wavefront each:
+//   wave 0: the expensive per-theta scalars of the proposal just judged
+//           (lnGamma(beta' + 1) ...);
+//   wave 1: the standard normals of the next proposal (Philox blocks
+//           (0, k + 1, 1, b));
+//   wave 2: ln u of the theta accept test (block (0, k, 2, 0)) and the log
+//           prior of the judged proposal;
+//   wave 3: eta of the next sweep.
+struct Precomp {
+    double z[kMaxP];
+    double aux_used[2];
+    double lprior_used;
+    double ln_u;
+    double eta_next;
+    double zraw;      // quadrature sum of ln Z at the judged proposal (before its shift)
+};
+static_assert(sizeof(Precomp) % 8 == 0, "Precomp is copied in 8-byte words");
+
 template <typename T>
 struct SweepArgs {
     T *chi;
@@ -27,7 +47,7 @@ struct SweepArgs {
     T *snaps;                  // latent snapshots or nullptr
     T *trace;                  // [3 + D][N] or nullptr
     double *partials;          // [3][n_tiles]: sum log f, sum of log f changes, accepted moves
-    double *zout;              // ln Z at the pending proposal, written by workgroup 0
+    Precomp *side;             // values for the epilogue, written by workgroup 0
     CycleState *cs;
     const Statics *st;
     const double *qx, *qw, *qeps;
@@ -55,22 +75,19 @@ __device__ __forceinline__ void stage_out(CycleState *dst, const CycleState &src
     for (int j = threadIdx.x; j < static_cast<int>(sizeof(CycleState) / 8); j += blockDim.x) d[j] = s[j];
 }
 
-// Values of the epilogue that do not depend on the reduction, computed on
-// separate wavefronts while it is in flight: the standard normals of the
-// next proposal (Philox blocks (0, k + 1, 1, b)), ln u of the theta accept
-// test (block (0, k, 2, 0)) and eta of the next sweep.
-struct Precomp {
-    double z[kMaxP];
-    double ln_u;
-    double eta_next;
-};
 
-// k: the sweep whose theta step this epilogue runs (or 0 for none).
+// k: the sweep whose theta step follows; judged: the proposal that sweep's
+// sums refer to (nullptr when there is none to judge).
 template <class M>
-__device__ __forceinline__ void precompute(Precomp &pc, int64_t k, const Statics &s)
+__device__ __forceinline__ void precompute(Precomp &pc, int64_t k, const double *judged, bool judged_valid,
+                                           const Statics &s)
 {
     constexpr int NB = (M::P + 3) / 4;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    if (wave == 0 && lane == 0 && judged != nullptr) {
+        if (judged_valid) M::aux(judged, pc.aux_used);
+        else pc.aux_used[0] = pc.aux_used[1] = 0.0;
+    }
     if (wave == 1 && lane < NB) {
         const Block4 blk = philox(0u, static_cast<uint32_t>(k + 1), 1u, static_cast<uint32_t>(lane), s.key0, s.key1);
         double z4[4];
@@ -81,41 +98,60 @@ __device__ __forceinline__ void precompute(Precomp &pc, int64_t k, const Statics
     if (wave == 2 && lane == 0) {
         const Block4 ub = philox(0u, static_cast<uint32_t>(k), 2u, 0u, s.key0, s.key1);
         pc.ln_u = log(uniform24<double>(ub, 4));
+        if (judged != nullptr) pc.lprior_used = judged_valid ? M::log_prior(judged) : -HUGE_VAL;
     }
     if (wave == 3 && lane == 0) pc.eta_next = pow(static_cast<double>(k + 2), -s.gamma);
 }
 
 // Draws the proposal theta' = theta + S_theta z for sweep k + 1 (c.k == k)
-// and derives the constants that sweep needs.  Called by every thread; the
-// two FP64 transcendentals of theta' run on different wavefronts.
+// and derives the constants that sweep needs (lane 0).
 template <class M>
 __device__ void prepare_next(CycleState &c, const Statics &s, const Precomp &pc)
 {
     using T = typename M::T;
     constexpr int P = M::P;
-    __shared__ double aux_lp[2];
-    if (threadIdx.x == 0) {
-        for (int r = 0; r < P; ++r) {
-            double v = c.theta[r];
-            for (int q = 0; q <= r; ++q) v += c.chol_theta[r * P + q] * pc.z[q];
-            c.prop[r] = v;
-            c.zprop[r] = pc.z[r];
+    for (int r = 0; r < P; ++r) {
+        double v = c.theta[r];
+        for (int q = 0; q <= r; ++q) v += c.chol_theta[r * P + q] * pc.z[q];
+        c.prop[r] = v;
+        c.zprop[r] = pc.z[r];
+    }
+    c.prop_valid = M::in_support(c.prop);
+    const double *tp = c.prop_valid ? c.prop : c.theta;
+    M::derive_kc(c.theta, tp, c.aux_cur, s, kc_of<T>(&c));
+    M::z_consts(tp, c.zc_prop);
+    c.eta_next = pc.eta_next;
+}
+
+// Turns the reduced sums of sweep c.k + 1 into the quantities its theta step
+// judges (lane 0): the proposal the sweep used, its ln Z, log prior and
+// aux scalars, and sum_i [log f(chi_i; theta') - log f(chi_i; theta)].
+template <class M>
+__device__ void finish_sweep(CycleState &c, const Statics &s, const double *v, double zraw, const Precomp &pc)
+{
+    c.k += 1;
+    c.sum_lf = v[0];
+    c.sum_dlf_raw = v[1];
+    c.n_acc_last = v[2];
+    for (int r = 0; r < M::P; ++r) {
+        c.used_prop[r] = c.prop[r];
+        c.used_z[r] = c.zprop[r];
+    }
+    c.used_valid = c.prop_valid;
+    c.aux_used[0] = pc.aux_used[0];
+    c.aux_used[1] = pc.aux_used[1];
+    c.lprior_used = pc.lprior_used;
+    c.logZ_used = 0.0;
+    c.sum_dlf = v[1];
+    if (c.used_valid) {
+        if (M::kSelection) {
+            c.logZ_used = zraw - M::logz_shift(c.aux_used);
+            if (!(c.logZ_used > -HUGE_VAL && c.logZ_used < HUGE_VAL)) c.flags |= kFlagBadZ;
         }
+        c.sum_dlf = v[1] - static_cast<double>(s.n) * M::dlf_const(c.theta, c.used_prop, c.aux_cur, c.aux_used);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) aux_lp[0] = M::aux(c.prop);
-    if (threadIdx.x == kWave) aux_lp[1] = M::log_prior(c.prop);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        c.lprior_prop = aux_lp[1];
-        c.prop_valid = c.lprior_prop > -HUGE_VAL;
-        const double *tp = c.prop_valid ? c.prop : c.theta;
-        c.aux_prop = c.prop_valid ? aux_lp[0] : c.aux_cur;
-        M::derive_kc(c.theta, tp, c.aux_cur, c.aux_prop, s, kc_of<T>(&c));
-        M::z_consts(tp, c.aux_prop, c.zc_prop);
-        c.eta_next = pc.eta_next;
-    }
-    __syncthreads();
+    c.eta_used = c.eta_next;
+    c.sums_ready = 1;
 }
 
 // Metropolis-Hastings step of cycle k on theta (lane 0).
@@ -134,7 +170,8 @@ __device__ void theta_mh(CycleState &c, const Statics &s, double *theta_trace, d
         for (int r = 0; r < P; ++r) c.theta[r] = c.used_prop[r];
         c.logZ_cur = c.logZ_used;
         c.lprior_cur = c.lprior_used;
-        c.aux_cur = c.aux_used;
+        c.aux_cur[0] = c.aux_used[0];
+        c.aux_cur[1] = c.aux_used[1];
     }
     if (s.adapt_theta) {
         double L[P * (P + 1) / 2], zz[P];
@@ -157,15 +194,17 @@ __device__ void theta_mh(CycleState &c, const Statics &s, double *theta_trace, d
     c.accepted_last = accepted;
 }
 
-// ln Z(theta) = ln sum_j w_j f_x(x_j; theta) eps_j over the fixed ln L rule;
-// every lane of one workgroup takes nodes tid, tid + 256, ...  Valid in thread 0.
+// ln Z(theta) + lnGamma(beta + 1) = ln sum_j w_j f_x(x_j; theta) Gamma(beta + 1) eps_j
+// over the fixed ln L rule (the normaliser of the gamma law is applied by
+// the caller); every lane of one workgroup takes nodes tid, tid + 256, ...
+// Valid in thread 0.
 __device__ __forceinline__ double block_log_z(const double *zc, const double *qx, const double *qw,
                                               const double *qeps, int nq, double (*red)[kWavesPerBlock])
 {
     double v[1] = {0.0};
     for (int j = threadIdx.x; j < nq; j += kBlock) {
         const double t = qx[j] - zc[1];
-        v[0] += qw[j] * exp(zc[0] * t - exp(t) - zc[2]) * qeps[j];
+        v[0] += qw[j] * exp(zc[0] * t - exp(t)) * qeps[j];
     }
     block_sum<1>(v, red);
     return log(v[0]);
@@ -187,11 +226,22 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
     const Statics &st = *a.st;
 
     if (blockIdx.x == 0) {
-        if (M::kSelection && cs->prop_valid) {
-            double zc[3] = {cs->zc_prop[0], cs->zc_prop[1], cs->zc_prop[2]};
-            const double lz = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
-            if (threadIdx.x == 0) a.zout[0] = lz;
+        // everything the epilogue needs that the objects do not decide
+        __shared__ Precomp sd;
+        const bool valid = cs->prop_valid != 0;
+        double judged[kMaxP];
+        for (int r = 0; r < M::P; ++r) judged[r] = cs->prop[r];
+        double zraw = 0.0;
+        if (M::kSelection && valid) {
+            double zc[2] = {cs->zc_prop[0], cs->zc_prop[1]};
+            zraw = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
         }
+        precompute<M>(sd, cs->k + 1, judged, valid, st);
+        if (threadIdx.x == 0) sd.zraw = zraw;
+        __syncthreads();
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(&sd);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(a.side);
+        for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
         return;
     }
     const int tile = blockIdx.x - 1;
@@ -201,7 +251,8 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
     const T *kc = kc_of<T>(cs);
     const T eta = static_cast<T>(cs->eta_next);
     const T astar = static_cast<T>(st.alpha_star);
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[2] = {0.0, 0.0};
+    bool accept = false;
     if (i < n) {
         T x[D], S[NC], U[D], y[D];
 #pragma unroll
@@ -223,8 +274,8 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         const Eval<T> ey = M::eval(o, y, kc, st);
         const T neg_inf = -static_cast<T>(HUGE_VAL);
         const T delta = (ey.lpv > neg_inf) ? ey.lpv - ex.lpv : neg_inf;
-        const bool accept = log(uniform24<T>(b, 4)) < delta;
-        const T alpha = delta >= static_cast<T>(0) ? static_cast<T>(1) : exp(delta);
+        accept = ln_uniform(b, T(0)) < delta;
+        const T alpha = accept_prob(delta);
         if (accept) {
 #pragma unroll
             for (int j = 0; j < D; ++j) x[j] = y[j];
@@ -239,7 +290,6 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         a.acc[i] = nacc;
         v[0] = static_cast<double>(en.lf);
         v[1] = static_cast<double>(M::dlf(o, x, en, kc, st));
-        v[2] = accept ? 1.0 : 0.0;
         if (!(ex.lpv > neg_inf)) atomicOr(&cs->flags, kFlagNonFiniteState);
         if (kTrace) {
             a.trace[i] = ex.lp;
@@ -256,11 +306,15 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
             }
         }
     }
-    block_sum<3>(v, red);
+    // accepted moves: one ballot per wavefront
+    __shared__ uint32_t nacc_w[kWavesPerBlock];
+    const uint32_t nw = static_cast<uint32_t>(__popcll(__ballot(accept)));
+    if ((threadIdx.x & (kWave - 1)) == 0) nacc_w[threadIdx.x / kWave] = nw;
+    block_sum<2>(v, red);
     if (threadIdx.x == 0) {
         a.partials[tile] = v[0];
         a.partials[a.n_tiles + tile] = v[1];
-        a.partials[2 * a.n_tiles + tile] = v[2];
+        a.partials[2 * a.n_tiles + tile] = static_cast<double>((nacc_w[0] + nacc_w[1]) + (nacc_w[2] + nacc_w[3]));
     }
 }
 
@@ -269,14 +323,12 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
 // for the next sweep.
 template <class M, bool kFull>
 __global__ __launch_bounds__(kBlock) void epilogue_kernel(CycleState *cs, const Statics *stp, const double *partials,
-                                                          const double *zout, double *theta_trace, int32_t n_tiles)
+                                                          const Precomp *side, double *theta_trace, int32_t n_tiles)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
     __shared__ double red[3][kWavesPerBlock];
     const Statics &st = *stp;
-    const int64_t kd = cs->k + 1;        // the sweep being finished
-    precompute<M>(pc, kd, st);           // waves 1-3, overlapping the loads below
     // tile partials, structure of arrays [3][n_tiles]
     double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll 4
@@ -285,48 +337,43 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(CycleState *cs, const 
         v[1] += partials[n_tiles + t];
         v[2] += partials[2 * n_tiles + t];
     }
-    stage_in(c, cs);
-    block_sum<3>(v, red);                // its barrier also publishes pc
-    if (threadIdx.x == 0) {
-        c.k = kd;
-        c.sum_lf = v[0];
-        c.sum_dlf = v[1];
-        c.n_acc_last = v[2];
-        for (int r = 0; r < M::P; ++r) {
-            c.used_prop[r] = c.prop[r];
-            c.used_z[r] = c.zprop[r];
-        }
-        c.logZ_used = (M::kSelection && c.prop_valid) ? zout[0] : 0.0;
-        c.lprior_used = c.lprior_prop;
-        c.used_valid = c.prop_valid;
-        c.aux_used = c.aux_prop;
-        c.eta_used = c.eta_next;
-        c.sums_ready = 1;
-        if (M::kSelection && c.prop_valid && !(c.logZ_used > -HUGE_VAL && c.logZ_used < HUGE_VAL))
-            c.flags |= kFlagBadZ;
-        if (kFull) theta_mh<M>(c, st, theta_trace, pc.ln_u);
+    {
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(side);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(&pc);
+        for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
     }
-    __syncthreads();
-    prepare_next<M>(c, st, pc);
+    stage_in(c, cs);                     // its barrier also publishes pc
+    block_sum<3>(v, red);
+    if (threadIdx.x == 0) {
+        finish_sweep<M>(c, st, v, pc.zraw, pc);
+        if (kFull) theta_mh<M>(c, st, theta_trace, pc.ln_u);
+        prepare_next<M>(c, st, pc);
+    }
     stage_out(cs, c);
 }
 
 // Theta step on its own, after a ram_sweep (plain cycle).
 template <class M>
-__global__ __launch_bounds__(kBlock) void theta_kernel(CycleState *cs, const Statics *st, double *theta_trace)
+__global__ __launch_bounds__(kBlock) void theta_kernel(CycleState *cs, const Statics *st, const Precomp *side,
+                                                       double *theta_trace)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
+    {
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(side);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(&pc);
+        for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
+    }
     stage_in(c, cs);
     const bool ready = c.sums_ready != 0;
-    precompute<M>(pc, c.k, *st);
-    __syncthreads();
     if (threadIdx.x == 0) {
-        if (ready) theta_mh<M>(c, *st, theta_trace, pc.ln_u);
-        else c.flags |= kFlagNoSums;
+        if (ready) {
+            theta_mh<M>(c, *st, theta_trace, pc.ln_u);
+            prepare_next<M>(c, *st, pc);
+        } else {
+            c.flags |= kFlagNoSums;
+        }
     }
-    __syncthreads();
-    if (ready) prepare_next<M>(c, *st, pc);
     stage_out(cs, c);
 }
 
@@ -336,27 +383,28 @@ __global__ __launch_bounds__(kBlock) void set_theta_kernel(CycleState *cs, const
                                                            const double *qw, const double *qeps)
 {
     __shared__ CycleState c;
+    __shared__ Precomp pc;
     __shared__ double red[1][kWavesPerBlock];
     stage_in(c, cs);
-    const double lp = M::log_prior(c.theta);
-    double zc[3];
+    const bool ok = M::in_support(c.theta);
+    // the judged-proposal slots of pc carry theta itself here
+    precompute<M>(pc, c.k, c.theta, ok, *st);
     double lz = 0.0;
-    if (M::kSelection && lp > -HUGE_VAL) {
-        const double ag = M::aux(c.theta);
-        M::z_consts(c.theta, ag, zc);
+    if (M::kSelection && ok) {
+        double zc[2];
+        M::z_consts(c.theta, zc);
         lz = block_log_z(zc, qx, qw, qeps, st->nq, red);
     }
-    __shared__ Precomp pc;
-    precompute<M>(pc, c.k, *st);
-    if (threadIdx.x == 0) {
-        c.lprior_cur = lp;
-        c.logZ_cur = lz;
-        c.aux_cur = lp > -HUGE_VAL ? M::aux(c.theta) : 0.0;
-        if (M::kSelection && lp > -HUGE_VAL && !(lz > -HUGE_VAL && lz < HUGE_VAL)) c.flags |= kFlagBadZ;
-        c.sums_ready = 0;
-    }
     __syncthreads();
-    prepare_next<M>(c, *st, pc);
+    if (threadIdx.x == 0) {
+        c.lprior_cur = pc.lprior_used;
+        c.aux_cur[0] = pc.aux_used[0];
+        c.aux_cur[1] = pc.aux_used[1];
+        c.logZ_cur = (M::kSelection && ok) ? lz - M::logz_shift(c.aux_cur) : 0.0;
+        if (M::kSelection && ok && !(c.logZ_cur > -HUGE_VAL && c.logZ_cur < HUGE_VAL)) c.flags |= kFlagBadZ;
+        c.sums_ready = 0;
+        prepare_next<M>(c, *st, pc);
+    }
     stage_out(cs, c);
 }
 
@@ -425,21 +473,20 @@ __global__ __launch_bounds__(kBlock) void poplik_kernel(PopArgs<typename M::T> a
     __shared__ double red[1][kWavesPerBlock];
     __shared__ T kc[32];
     const Statics &st = *a.st;
+    double ag[2];
+    M::aux(a.theta, ag);
     if (blockIdx.x == 0) {
         if (M::kSelection) {
-            double zc[3];
-            M::z_consts(a.theta, M::aux(a.theta), zc);
+            double zc[2];
+            M::z_consts(a.theta, zc);
             const double lz = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
-            if (threadIdx.x == 0) a.zout[1] = lz;
+            if (threadIdx.x == 0) a.zout[1] = lz - M::logz_shift(ag);
         } else if (threadIdx.x == 0) {
             a.zout[1] = 0.0;
         }
         return;
     }
-    if (threadIdx.x == 0) {
-        const double ag = M::aux(a.theta);
-        M::derive_kc(a.theta, a.theta, ag, ag, st, kc);
-    }
+    if (threadIdx.x == 0) M::derive_kc(a.theta, a.theta, ag, st, kc);
     __syncthreads();
     const int tile = blockIdx.x - 1;
     const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;

@@ -11,7 +11,22 @@
 //     residual is -(Fhat / sigma) expm1(...);
 //   * ln L* is split into a float head and tail, so chi - ln L* is accurate;
 //   * the change of log f between theta and theta' is formed from parameter
-//     differences (computed in FP64), never as a difference of two sums.
+//     differences, never as a difference of two sums; the part of it that is
+//     the same for every object is added once, N times, in FP64.
+//
+// Hooks every model provides (all FP64 unless noted):
+//   aux(th, a)          the expensive per-theta scalars (lnGamma, ln s), NAUX of them
+//   in_support(th)      prior support
+//   log_prior(th)       log prior density in the theta coordinates
+//   derive_kc(th, tp, a, s, kc)  per-sweep constants in the per-object precision
+//                       from the current theta (with its aux a) and the proposal tp
+//   dlf_const(th, tp, a, ap)     the object-independent part of
+//                       log f(chi; tp) - log f(chi; th), added N times
+//   z_consts(tp, zc), logz_shift(ap)  quadrature constants of ln Z; the
+//                       quadrature sum omits exp(-shift) and the shift is
+//                       subtracted afterwards
+//   eval, dlf           per-object log densities and the per-object part of
+//                       the log f change, in the per-object precision
 #pragma once
 
 #include "device.h"
@@ -20,10 +35,6 @@ namespace hbm {
 
 constexpr double kLn2Pi = 1.8378770664093454836;
 constexpr double kLn4Pi = 2.5310242469692907930;
-
-template <typename T> __device__ __forceinline__ T stat(const Statics &s, int j);
-template <> __device__ __forceinline__ float stat<float>(const Statics &s, int j) { return s.mf[j]; }
-template <> __device__ __forceinline__ double stat<double>(const Statics &s, int j) { return s.md[j]; }
 
 template <typename T> __device__ __forceinline__ T *kc_of(CycleState *c);
 template <> __device__ __forceinline__ float *kc_of<float>(CycleState *c) { return c->kc_f; }
@@ -61,10 +72,14 @@ struct NN1D {
         dd[n + i] = 1.0 / data[n + i];
     }
     __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{dd[i], dd[n + i]}; }
+    __device__ static void aux(const double *, double *a) { a[0] = a[1] = 0.0; }
+    __device__ static bool in_support(const double *) { return true; }
     __device__ static double log_prior(const double *th) { return th[1]; }
-    __device__ static double aux(const double *) { return 0.0; }
-    __device__ static void z_consts(const double *, double, double *zc) { zc[0] = zc[1] = zc[2] = 0.0; }
-    __device__ static void derive_kc(const double *th, const double *tp, double, double, const Statics &, T *kc)
+    __device__ static void z_consts(const double *, double *zc) { zc[0] = zc[1] = 0.0; }
+    __device__ static double logz_shift(const double *) { return 0.0; }
+    __device__ static double dlf_const(const double *, const double *, const double *, const double *) { return 0.0; }
+    // kc: [0] mu, [1] 1/tau, [2] ln tau + ln(2 pi)/2, [3..5] the same for theta'
+    __device__ static void derive_kc(const double *th, const double *tp, const double *, const Statics &, T *kc)
     {
         kc[0] = th[0];
         kc[1] = exp(-th[1]);
@@ -133,10 +148,13 @@ struct NN3D {
         for (int j = 0; j < 3; ++j) dd[j * n + i] = data[j * n + i];
     }
     __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{{dd[i], dd[n + i], dd[2 * n + i]}}; }
+    __device__ static void aux(const double *, double *a) { a[0] = a[1] = 0.0; }
+    __device__ static bool in_support(const double *) { return true; }
     __device__ static double log_prior(const double *) { return 0.0; }
-    __device__ static double aux(const double *) { return 0.0; }
-    __device__ static void z_consts(const double *, double, double *zc) { zc[0] = zc[1] = zc[2] = 0.0; }
-    __device__ static void derive_kc(const double *th, const double *tp, double, double, const Statics &, T *kc)
+    __device__ static void z_consts(const double *, double *zc) { zc[0] = zc[1] = 0.0; }
+    __device__ static double logz_shift(const double *) { return 0.0; }
+    __device__ static double dlf_const(const double *, const double *, const double *, const double *) { return 0.0; }
+    __device__ static void derive_kc(const double *th, const double *tp, const double *, const Statics &, T *kc)
     {
         for (int j = 0; j < 3; ++j) {
             kc[j] = th[j];
@@ -174,12 +192,12 @@ struct NN3D {
 // BB1 model as l -> 0); in chi = ln L it reads
 //   log f(chi) = (beta + 1)(chi - ln L*) - exp(chi - ln L*) - lnGamma(beta + 1).
 // kc: [0] beta + 1, [1] float head of ln L*, [2] its tail, [3] lnGamma(beta+1),
-//     [4] beta' - beta, [5] expm1(ln L* - ln L*'),
-//     [6] (beta' + 1)(ln L*' - ln L*) + lnGamma(beta'+1) - lnGamma(beta+1).
-// With q = chi - ln L*:  log f' - log f = (beta' - beta) q - e^q [5] - [6].
+//     [4] beta' - beta, [5] expm1(ln L* - ln L*').
+// With q = chi - ln L*, log f' - log f = (beta' - beta) q - e^q [5] - C where
+// C = (beta' + 1)(ln L*' - ln L*) + lnGamma(beta'+1) - lnGamma(beta+1) is the
+// object-independent part.
 // ---------------------------------------------------------------------------
-// lg, lgp: lnGamma(beta + 1) of theta and theta' (cached per proposal).
-__device__ __forceinline__ void gamma_kc(const double *th, const double *tp, double lg, double lgp, float *kc)
+__device__ __forceinline__ void gamma_kc(const double *th, const double *tp, double lg, float *kc)
 {
     const float head = static_cast<float>(th[1]);
     kc[0] = static_cast<float>(th[0] + 1.0);
@@ -187,21 +205,23 @@ __device__ __forceinline__ void gamma_kc(const double *th, const double *tp, dou
     kc[2] = static_cast<float>(th[1] - static_cast<double>(head));
     kc[3] = static_cast<float>(lg);
     kc[4] = static_cast<float>(tp[0] - th[0]);
-    const double dl = tp[1] - th[1];
-    kc[5] = static_cast<float>(expm1(-dl));
-    kc[6] = static_cast<float>((tp[0] + 1.0) * dl + (lgp - lg));
+    // single precision suffices: the factor multiplies a float per-object term
+    kc[5] = expm1f(static_cast<float>(th[1] - tp[1]));
 }
 
-__device__ __forceinline__ double lf_beta_prior(double beta)
+__device__ __forceinline__ double gamma_dconst(const double *th, const double *tp, const double *a, const double *ap)
 {
-    return (beta > -1.0 && beta < 0.0) ? -log1p(beta * beta) : -HUGE_VAL;
+    return (tp[0] + 1.0) * (tp[1] - th[1]) + (ap[0] - a[0]);
 }
+
+__device__ __forceinline__ bool lf_beta_ok(double beta) { return beta > -1.0 && beta < 0.0; }
 
 // ===========================================================================
 // Gamma luminosity function, flux-limited, known distances; chi = ln L.
 //   log l_i(chi) = -((Fhat_i - exp(chi - k_i)) / sigma_F)^2 / 2,  k_i = ln 4 pi r_i^2.
 // Derived data per object: a = Fhat / sigma_F, centre c = ln(4 pi r^2 Fhat)
 // rounded to float, and e = (exact centre) - c.
+// aux: [0] lnGamma(beta + 1).
 // ===========================================================================
 struct LF1D {
     using T = float;
@@ -222,18 +242,27 @@ struct LF1D {
         dd[2 * n + i] = static_cast<float>(centre - static_cast<double>(c));
     }
     __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{dd[i], dd[n + i], dd[2 * n + i]}; }
-    __device__ static double log_prior(const double *th) { return lf_beta_prior(th[0]); }
-    // the one transcendental per theta the sweeps need in FP64: lnGamma(beta + 1)
-    __device__ static double aux(const double *th) { return lgamma(th[0] + 1.0); }
-    __device__ static void z_consts(const double *th, double lg, double *zc)
+    __device__ static void aux(const double *th, double *a)
     {
-        zc[0] = th[0] + 1.0;
-        zc[1] = th[1];
-        zc[2] = lg;
+        a[0] = lgamma(th[0] + 1.0);
+        a[1] = 0.0;
     }
-    __device__ static void derive_kc(const double *th, const double *tp, double lg, double lgp, const Statics &, T *kc)
+    __device__ static bool in_support(const double *th) { return lf_beta_ok(th[0]); }
+    // truncated Cauchy on the slope, flat in ln L*
+    __device__ static double log_prior(const double *th) { return in_support(th) ? -log1p(th[0] * th[0]) : -HUGE_VAL; }
+    __device__ static void z_consts(const double *tp, double *zc)
     {
-        gamma_kc(th, tp, lg, lgp, kc);
+        zc[0] = tp[0] + 1.0;
+        zc[1] = tp[1];
+    }
+    __device__ static double logz_shift(const double *ap) { return ap[0]; }
+    __device__ static double dlf_const(const double *th, const double *tp, const double *a, const double *ap)
+    {
+        return gamma_dconst(th, tp, a, ap);
+    }
+    __device__ static void derive_kc(const double *th, const double *tp, const double *a, const Statics &, T *kc)
+    {
+        gamma_kc(th, tp, a[0], kc);
     }
     __device__ static Eval<T> eval(const Obj &o, const T *x, const T *kc, const Statics &)
     {
@@ -251,7 +280,7 @@ struct LF1D {
     }
     __device__ static T dlf(const Obj &, const T *, const Eval<T> &e, const T *kc, const Statics &)
     {
-        return kc[4] * e.q - e.eq * kc[5] - kc[6];
+        return kc[4] * e.q - e.eq * kc[5];
     }
 };
 
@@ -264,8 +293,10 @@ struct LF1D {
 // Derived data: a = Fhat / sigma_F, c1 = centre of ln L, e1 its residual
 // against ln 4 pi + 2 c2 + ln Fhat, c2 = ln rhat in float, e2 its residual, chat.
 // Statics mf: [0] 1/f_r, [1] 1/sigma_c, [2] ln rmax, [3] ln 3 - 3 ln rmax.
+// aux: [0] lnGamma(beta + 1), [1] ln s.
 // kc beyond the gamma part: [7] a, [8] b, [9] 1/s, [10] ln s + ln(2 pi)/2,
-//   [11] a' - a, [12] b' - b, [13] 1/s' - 1/s, [14] 1/s', [15] ln(s'/s).
+//   [11] a' - a, [12] b' - b, [13] 1/s' - 1/s, [14] 1/s'.
+// The colour term's object-independent change is -ln(s'/s).
 // ===========================================================================
 struct LF3D {
     using T = float;
@@ -300,24 +331,31 @@ struct LF3D {
     {
         return Obj{dd[i], dd[n + i], dd[2 * n + i], dd[3 * n + i], dd[4 * n + i], dd[5 * n + i]};
     }
-    __device__ static double log_prior(const double *th)
+    __device__ static void aux(const double *th, double *a)
     {
-        return th[4] > 0.0 ? lf_beta_prior(th[0]) : -HUGE_VAL;
+        a[0] = lgamma(th[0] + 1.0);
+        a[1] = log(th[4]);
     }
-    __device__ static double aux(const double *th) { return LF1D::aux(th); }
-    __device__ static void z_consts(const double *th, double lg, double *zc) { LF1D::z_consts(th, lg, zc); }
-    __device__ static void derive_kc(const double *th, const double *tp, double lg, double lgp, const Statics &, T *kc)
+    __device__ static bool in_support(const double *th) { return lf_beta_ok(th[0]) && th[4] > 0.0; }
+    // as 1-D, plus flat a and b and a uniform s > 0
+    __device__ static double log_prior(const double *th) { return in_support(th) ? -log1p(th[0] * th[0]) : -HUGE_VAL; }
+    __device__ static void z_consts(const double *tp, double *zc) { LF1D::z_consts(tp, zc); }
+    __device__ static double logz_shift(const double *ap) { return ap[0]; }
+    __device__ static double dlf_const(const double *th, const double *tp, const double *a, const double *ap)
     {
-        gamma_kc(th, tp, lg, lgp, kc);
+        return gamma_dconst(th, tp, a, ap) + (ap[1] - a[1]);
+    }
+    __device__ static void derive_kc(const double *th, const double *tp, const double *a, const Statics &, T *kc)
+    {
+        gamma_kc(th, tp, a[0], kc);
         kc[7] = static_cast<float>(th[2]);
         kc[8] = static_cast<float>(th[3]);
         kc[9] = static_cast<float>(1.0 / th[4]);
-        kc[10] = static_cast<float>(log(th[4]) + 0.5 * kLn2Pi);
+        kc[10] = static_cast<float>(a[1] + 0.5 * kLn2Pi);
         kc[11] = static_cast<float>(tp[2] - th[2]);
         kc[12] = static_cast<float>(tp[3] - th[3]);
         kc[13] = static_cast<float>(1.0 / tp[4] - 1.0 / th[4]);
         kc[14] = static_cast<float>(1.0 / tp[4]);
-        kc[15] = static_cast<float>(log(tp[4] / th[4]));
     }
     __device__ static Eval<T> eval(const Obj &o, const T *x, const T *kc, const Statics &s)
     {
@@ -344,9 +382,9 @@ struct LF3D {
     }
     __device__ static T dlf(const Obj &, const T *x, const Eval<T> &e, const T *kc, const Statics &)
     {
-        const float dg = kc[4] * e.q - e.eq * kc[5] - kc[6];
+        const float dg = kc[4] * e.q - e.eq * kc[5];
         const float du = e.res * kc[13] - (kc[11] + kc[12] * x[0]) * kc[14];
-        return dg - 0.5f * du * (2.0f * e.u + du) - kc[15];
+        return dg - 0.5f * du * (2.0f * e.u + du);
     }
 };
 
