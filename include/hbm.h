@@ -193,10 +193,11 @@ HBM_API hbm_status ram_sweep_trace(hbm_ctx *ctx, void *trace);
  * out[7] theta accepted (0/1).  Synchronous. */
 HBM_API hbm_status get_stats(hbm_ctx *ctx, double out[8]);
 
-/* Per-launch duration bookkeeping of the sweep kernel: when enabled, every
- * sweep-kernel launch is bracketed by hipEvents on the context's stream;
- * read returns the launches timed and their mean duration in ms and
- * resets the counters.  Synchronous read. */
+/* Per-launch duration of the sweep kernel: when enabled, every sweep-kernel
+ * launch carries a start and a stop hipEvent that the runtime records from
+ * the dispatch itself (hipExtLaunchKernel), and run_cycles issues plain
+ * launches instead of replaying its graph.  read returns the launches timed
+ * and their mean duration in ms and resets the counters.  Synchronous read. */
 HBM_API hbm_status kernel_timing(hbm_ctx *ctx, int32_t enable);
 HBM_API hbm_status read_kernel_timing(hbm_ctx *ctx, int64_t *n_launches, double *mean_ms);
 

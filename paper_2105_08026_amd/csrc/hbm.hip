@@ -6,6 +6,7 @@
 #include "hbm.h"
 #include "kernels.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -100,7 +101,7 @@ hbm_status hip_fail(CtxImpl *c, hipError_t e, const char *what)
 
 int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
 
-// Timing events around one sweep-kernel launch.
+// Events that time one sweep-kernel launch.
 hipEvent_t take_event(CtxImpl *c)
 {
     if (!c->ev_free.empty()) {
@@ -142,22 +143,22 @@ struct Ops {
     {
         const SweepArgs<T> a = sweep_args(c, trace);
         const dim3 grid(static_cast<unsigned>(c->n_tiles + 1));
-        hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
-            e0 = take_event(c);
-            e1 = take_event(c);
-            if (e0) HIPCHK(c, hipEventRecord(e0, c->stream));
-        }
-        if (trace)
-            hipLaunchKernelGGL((sweep_kernel<M, true>), grid, dim3(kBlock), 0, c->stream, a);
-        else
-            hipLaunchKernelGGL((sweep_kernel<M, false>), grid, dim3(kBlock), 0, c->stream, a);
-        LAUNCHCHK(c, "sweep_kernel");
-        if (c->timing && e0 && e1) {
-            HIPCHK(c, hipEventRecord(e1, c->stream));
+            // the runtime takes both timestamps from the dispatch itself
+            hipEvent_t e0 = take_event(c), e1 = take_event(c);
+            if (!e0 || !e1) return fail(c, HBM_ENOMEM, "hipEventCreate failed");
+            if (trace)
+                hipExtLaunchKernelGGL((sweep_kernel<M, true>), grid, dim3(kBlock), 0, c->stream, e0, e1, 0, a);
+            else
+                hipExtLaunchKernelGGL((sweep_kernel<M, false>), grid, dim3(kBlock), 0, c->stream, e0, e1, 0, a);
             c->ev_pending.push_back(e0);
             c->ev_pending.push_back(e1);
+        } else if (trace) {
+            hipLaunchKernelGGL((sweep_kernel<M, true>), grid, dim3(kBlock), 0, c->stream, a);
+        } else {
+            hipLaunchKernelGGL((sweep_kernel<M, false>), grid, dim3(kBlock), 0, c->stream, a);
         }
+        LAUNCHCHK(c, "sweep_kernel");
         if (full)
             hipLaunchKernelGGL((epilogue_kernel<M, true>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st,
                                c->partials, c->side, c->theta_trace, c->n_tiles);
