@@ -1,7 +1,9 @@
 """Throughput of the Metropolis-within-Gibbs hot path on one MI355X.
 
-A step is one full cycle of the sampler on the 300,000-object flux-limited
-gamma luminosity-function catalog: the fused RAM sweep of every latent
+A step is one full cycle of the sampler, by default on the 300,000-object
+flux-limited gamma luminosity-function catalog (--workload selects the 3-D
+colour catalog at 1,000,000 objects or the normal-normal models): the RAM
+sweep of every latent
 (Philox draws, proposal, target evaluation, accept, RAM factor update), the
 FP64 population log-likelihood reductions, the selection quadrature for the
 pending proposal, and the theta Metropolis-Hastings step.  Inputs are
@@ -26,10 +28,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "latent RAM updates/sec and Gibbs sweeps/sec at N=3e5; batched jobs/hour; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per object-update of the 1-D luminosity-function sweep:
-# read latent, RAM factor, accept counter (3 x 4 B) and three derived data
-# words (12 B); write latent, factor, counter (12 B).
-BYTES_PER_UPDATE = {"gamma_lf_1d": 36, "normal_normal_1d": 56, "gamma_lf_color_3d": 104, "normal_normal_3d": 136}
+# Algorithmic bytes per object-update of the sweep: read the latent, RAM
+# factor, accept counter and derived data words, write latent, factor and
+# counter.  1-D LF (FP32): 4+4+4+12 read, 12 written; 3-D LF (FP32):
+# 12+24+4+24 read, 40 written; 1-D normal-normal (FP64): 8+8+4+16 read, 20
+# written; 3-D normal-normal (FP64): 24+48+4+24 read, 76 written.
+BYTES_PER_UPDATE = {"gamma_lf_1d": 36, "normal_normal_1d": 56, "gamma_lf_color_3d": 104, "normal_normal_3d": 176}
 
 
 def parse():
@@ -37,7 +41,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=300_000)
+    ap.add_argument("--workload", default="gamma_lf_1d",
+                    choices=["gamma_lf_1d", "gamma_lf_color_3d", "normal_normal_1d", "normal_normal_3d"])
+    ap.add_argument("--n", type=int, default=None, help="objects (default: 300,000; 1,000,000 for the 3-D catalog)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -73,7 +79,10 @@ def main():
     import paper_2105_08026_amd as hbm
 
     torch.cuda.set_device(0)
-    wl = synth.gamma_lf_1d(n=args.n)
+    make = {"gamma_lf_1d": (synth.gamma_lf_1d, 300_000), "gamma_lf_color_3d": (synth.gamma_lf_3d, 1_000_000),
+            "normal_normal_1d": (synth.normal_normal_1d, 300_000), "normal_normal_3d": (synth.normal_normal_3d, 300_000)}
+    gen, n_default = make[args.workload]
+    wl = gen(n=args.n or n_default)
     total = args.warmup + 2 * args.steps
     s = hbm.Sampler(wl, device="cuda:0", max_cycles=total)
     use_graph = not args.no_graph
@@ -118,16 +127,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded flux-limited gamma luminosity-function catalog)",
-        "config": {"workload": "gamma_lf_1d", "n_objects": wl.n, "latent_dim": 1, "theta_dim": 2,
-                   "selection_quadrature_nodes": 512, "graph": use_graph, "sweeps_per_step": 1},
+        "dtype": "f32" if wl.precision == "f32" else "f64",
+        "data": f"synthetic (seeded {wl.name} catalog)",
+        "config": {"workload": wl.name, "n_objects": wl.n, "latent_dim": wl.d, "theta_dim": wl.p,
+                   "selection_quadrature_nodes": 512 if wl.model in (2, 3) else 0, "graph": use_graph,
+                   "sweeps_per_step": 1},
         "gibbs_sweeps_per_s": args.steps / wall,
         "breakdown_ms": {"step": 1e3 * wall / args.steps, "sweep_kernel": kern_ms,
                          "step_with_event_timing": 1e3 * wall_ev / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                     "kernel": "sweep_kernel<LF1D, fused theta step>", "bytes_per_update": bpu,
+                     "kernel": f"sweep_kernel<{wl.name}>", "bytes_per_update": bpu,
                      "launches_timed": n_launch},
         "accept_rate_last_sweep": stats["n_acc"] / wl.n,
         "theta_last": th[-1].tolist(),
