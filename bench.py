@@ -42,7 +42,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="gamma_lf_1d",
-                    choices=["gamma_lf_1d", "gamma_lf_color_3d", "normal_normal_1d", "normal_normal_3d"])
+                    choices=["gamma_lf_1d", "gamma_lf_color_3d", "normal_normal_1d", "normal_normal_3d",
+                             "gamma_lf_batch256"])
+    ap.add_argument("--seq-steps", type=int, default=200,
+                    help="batch workload: cycles timed per dataset in the one-dataset-per-launch comparison")
+    ap.add_argument("--job-sweeps", type=int, default=2000, help="batch workload: sweeps that make one job")
     ap.add_argument("--n", type=int, default=None, help="objects (default: 300,000; 1,000,000 for the 3-D catalog)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -67,6 +71,86 @@ def cpu_baseline(wl, seconds: float):
             "sample": f"{done} full MWG cycles of the N={wl.n} catalog ({dt:.1f} s, FP64, OpenMP over objects)"}
 
 
+def cpu_baseline_batch(wls, seconds: float):
+    """The oracle on the batch's datasets in turn, for a bounded time."""
+    import oracle
+
+    oracle.build(force=False)
+    done_updates, done_cycles, used, t0 = 0, 0, 0, time.perf_counter()
+    for wl in wls:
+        if time.perf_counter() - t0 >= seconds:
+            break
+        o = oracle.Oracle(wl)
+        st = o.initial_state()
+        o.run(st, 20)
+        done_updates += 20 * wl.n
+        done_cycles += 20
+        used += 1
+    dt = time.perf_counter() - t0
+    return {"value": done_updates / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"20 full MWG cycles of each of the first {used} datasets ({dt:.1f} s incl. setup, FP64)"}
+
+
+def bench_batch(args, torch, synth, hbm):
+    """256 luminosity-function datasets of uneven N advanced together, against
+    the same datasets run one per launch sequence."""
+    wls = synth.gamma_lf_batch(256)
+    n_tot = sum(w.n for w in wls)
+    trial = 64
+    total = 3 * (32 + trial) + args.warmup + 2 * args.steps
+    b = hbm.Batch(wls, device="cuda:0", max_cycles=total)
+    pick, us = b.autotune(trial)
+    b.run_cycles(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run_cycles(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    hbm.kernel_timing(b.ctx, True)
+    b.run_cycles(args.steps, use_graph=False)
+    n_launch, kern_ms = hbm.read_kernel_timing(b.ctx)
+    hbm.kernel_timing(b.ctx, False)
+    th_last = [b.theta_trace(j)[-1] for j in (0, 255)]
+    assert all(np.all(np.isfinite(t)) for t in th_last)
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+
+    # one dataset per launch sequence: the same datasets, each alone, back to back
+    seq = 0.0
+    for wl in wls:
+        s = hbm.Sampler(wl, device="cuda:0", max_cycles=32 + args.seq_steps)
+        s.run_cycles(32)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.run_cycles(args.seq_steps)
+        torch.cuda.synchronize()
+        seq += (time.perf_counter() - t1) / args.seq_steps
+        s.close()
+    t_cycle = wall / args.steps
+    jobs_h = 256 * 3600.0 / (args.job_sweeps * t_cycle)
+    jobs_h_seq = 256 * 3600.0 / (args.job_sweeps * seq)
+    bpu = BYTES_PER_UPDATE["gamma_lf_1d"]
+    achieved = bpu * n_tot / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    out = {
+        "metric": METRIC, "value": n_tot * args.steps / wall, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_cycle, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (256 seeded gamma-LF catalogs, N log-uniform on [1e3, 1e5])",
+        "config": {"workload": "gamma_lf_batch256", "n_datasets": 256, "n_objects_total": n_tot,
+                   "job_sweeps": args.job_sweeps, "graph": True, "tiles_per_workgroup": pick},
+        "jobs_per_hour": jobs_h, "sequential_jobs_per_hour": jobs_h_seq, "batch_speedup": jobs_h / jobs_h_seq,
+        "sequential_ms_per_cycle_sum": 1e3 * seq, "autotune_us_per_cycle": {"1": us[0], "2": us[1], "4": us[2]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "sweep_kernel<gamma_lf_1d>", "bytes_per_update": bpu, "launches_timed": n_launch,
+                     "kernel_ms": kern_ms},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(wls, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -79,6 +163,9 @@ def main():
     import paper_2105_08026_amd as hbm
 
     torch.cuda.set_device(0)
+    if args.workload == "gamma_lf_batch256":
+        bench_batch(args, torch, synth, hbm)
+        return
     make = {"gamma_lf_1d": (synth.gamma_lf_1d, 300_000), "gamma_lf_color_3d": (synth.gamma_lf_3d, 1_000_000),
             "normal_normal_1d": (synth.normal_normal_1d, 300_000), "normal_normal_3d": (synth.normal_normal_3d, 300_000)}
     gen, n_default = make[args.workload]

@@ -14,8 +14,19 @@
  * Every step runs in the library's HIP kernels.  The caller owns the latent
  * state and the data (device buffers it allocates, e.g. torch tensors); the
  * library owns only its scratch (per-object derived constants, reduction
- * partials, quadrature tables, the theta state and its trace), allocated by
- * init_chains and freed by destroy_chains.
+ * partials, quadrature tables, the theta states and their traces), allocated
+ * when a context is created and freed by destroy_chains.
+ *
+ * Pools.  A context is a pool of n_slots slots over packed buffers of
+ * `capacity` object positions.  A loaded slot holds one dataset (one
+ * catalog with its own seed, theta chain and configuration) whose objects
+ * occupy positions [obj_start, obj_start + N) of every buffer, obj_start a
+ * multiple of 256.  Every launch advances all active slots together; a
+ * slot's chain is bit-identical to the same dataset run alone, wherever it
+ * sits.  init_chains makes a one-slot pool (capacity N, obj_start 0), and the
+ * functions below then behave as for a single dataset.  init_batch packs
+ * datasets back to back; create_pool / load_datasets / unload_dataset let a
+ * scheduler admit and retire datasets between launches.
  *
  * Conventions for every function below.
  *   - Return value: HBM_OK (0) or a negative hbm_status.  No exception or
@@ -24,17 +35,20 @@
  *   - A validation failure (HBM_EINVAL, HBM_ENOSPACE) leaves the context
  *     unchanged.  A HIP failure (HBM_EHIP) poisons the context: every later
  *     call except last_error and destroy_chains returns HBM_ESTATE.
- *   - Work is enqueued on the hip stream given to init_chains.  Calls that
+ *   - Work is enqueued on the hip stream given when the context was
+ *     created (init_chains, init_batch, create_pool).  Calls that
  *     return host values synchronise that stream; the others are
  *     asynchronous.  A context is not thread-safe; distinct contexts on
  *     distinct streams may run concurrently.
- *   - Layouts are structure-of-arrays: component j of object i of an array
- *     with N objects sits at [j * N + i].  Real arrays hold float for
- *     HBM_FP32 and double for HBM_FP64 (the per-object precision).
- *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed
- *     and counter = (object, sweep, tag, block); tag 0 = latent RAM step,
- *     1 = theta proposal, 2 = theta accept.  A chain is a pure function of
- *     (data, configuration, seed), independent of launch shape.
+ *   - Layouts are structure-of-arrays: component j of object position i
+ *     sits at [j * C + i], C = the pool's capacity (N for init_chains).
+ *     Real arrays hold float for HBM_FP32 and double for HBM_FP64 (the
+ *     per-object precision).  Per-slot host arrays are indexed by slot.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = the
+ *     dataset's seed and counter = (object index within the dataset, sweep,
+ *     tag, block); tag 0 = latent RAM step, 1 = theta proposal, 2 = theta
+ *     accept.  A chain is a pure function of (data, configuration, seed),
+ *     independent of launch shape and of its slot and position in a pool.
  */
 #ifndef HBM_H
 #define HBM_H
@@ -102,19 +116,32 @@ typedef struct hbm_config {
     int32_t adapt_theta;         /* 1: RAM-adapt the theta proposal factor; 0: keep it */
     int32_t n_quad;              /* Gauss-Legendre nodes of the selection normaliser (LF: 16..4096) */
     int32_t thin_chi;            /* latent snapshot after every sweep k with k % thin_chi == 0; 0: none */
-    int32_t reserved;
+    int32_t tiles_per_group;     /* launch shape: 256-object tiles per sweep workgroup, 1, 2 or 4 (0 = 1);
+                                    init_chains / init_batch take it from (the first) config */
     int64_t max_cycles;          /* capacity of the theta trace (and bound on snapshots) */
     double theta_chol0[25];      /* initial theta proposal factor, p x p lower, row-major */
     double model_consts[16];
 } hbm_config;
 
 typedef struct hbm_buffers {
-    const void *data;   /* [m][N] model data (device), read only */
-    void *chi;          /* [d][N] latents (device), read/write */
-    void *chol;         /* [d(d+1)/2][N] packed lower RAM factors, row-major (0,0),(1,0),(1,1),... */
-    uint32_t *acc;      /* [N] per-object accepted-move counters (device) */
-    void *chi_samples;  /* [max_cycles / thin_chi][d][N] latent snapshots (device), or NULL */
+    const void *data;   /* [m][C] model data (device), read only */
+    void *chi;          /* [d][C] latents (device), read/write */
+    void *chol;         /* [d(d+1)/2][C] packed lower RAM factors, row-major (0,0),(1,0),(1,1),... */
+    uint32_t *acc;      /* [C] per-object accepted-move counters (device) */
+    void *chi_samples;  /* [snap_rows][d][C] latent snapshots (device), or NULL */
 } hbm_buffers;
+
+typedef struct hbm_pool_config {
+    int32_t model;               /* HBM_* model id shared by every slot */
+    int32_t precision;           /* must match the model */
+    int32_t n_slots;             /* datasets resident at once, 1..65535 */
+    int32_t n_quad;              /* LF: Gauss-Legendre nodes of every slot (16..4096) */
+    int64_t capacity;            /* C: object positions, the stride of every buffer (<= 2^31 - 257) */
+    int64_t max_cycles;          /* theta trace rows per slot */
+    int64_t snap_rows;           /* rows of chi_samples (0 when NULL) */
+    int32_t tiles_per_group;     /* launch shape: tiles per sweep workgroup, 1, 2 or 4 (0 = 1) */
+    int32_t reserved;            /* must be 0 */
+} hbm_pool_config;
 
 /* Create a sampler (Sec. 2.2: "X_1 with pi(X_1) > 0, S_1 = I").
  * chi0_host: [d][N] starting latents (copied into buffers->chi), or NULL to
@@ -127,23 +154,62 @@ typedef struct hbm_buffers {
 HBM_API hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, const double *chi0_host,
                        const double *theta0, void *hip_stream, hbm_ctx **out);
 
-/* n_sweeps RAM sweeps of all latents at the current theta (eq 2.4, eq 2.6).
+/* A batch of n_datasets catalogs of one model, advanced together (one
+ * launch per sweep for all of them).  Dataset j occupies positions
+ * [o_j, o_j + N_j) with o_0 = 0 and o_{j+1} = o_j + 256 ceil(N_j / 256); the
+ * capacity C is o_last + N_last.  The caller fills data and chi at those
+ * positions before the call.  configs[j] carries N_j, its seed and every
+ * other setting; model, precision and n_quad must agree.  theta0:
+ * [n_datasets][p].  Datasets sit in slots 0..n_datasets-1.  Fails as
+ * init_chains does, naming the first bad dataset. */
+HBM_API hbm_status init_batch(int32_t n_datasets, const hbm_config *configs, const hbm_buffers *buffers,
+                              const double *theta0, void *hip_stream, hbm_ctx **out);
+
+/* An empty pool (every slot free) over the caller's packed buffers. */
+HBM_API hbm_status create_pool(const hbm_pool_config *pool, const hbm_buffers *buffers, void *hip_stream,
+                               hbm_ctx **out);
+
+/* Load count datasets into free slots: dataset q goes to slots[q] at
+ * positions [obj_start[q], obj_start[q] + N_q), obj_start[q] a multiple of
+ * 256, inside the capacity and disjoint from every loaded dataset.  The
+ * caller has written its data and starting latents there.  theta0:
+ * [count][p].  budgets (nullable): theta steps after which the dataset
+ * stops (0 = no limit, at most its max_cycles); a stopped dataset keeps its
+ * samples until unloaded.  Initialises each dataset as init_chains does;
+ * on failure no slot is loaded.  Synchronous. */
+HBM_API hbm_status load_datasets(hbm_ctx *ctx, int32_t count, const int32_t *slots, const int64_t *obj_start,
+                                 const hbm_config *configs, const double *theta0, const int64_t *budgets);
+
+/* Free a slot and its object range (its samples are no longer readable).
+ * Synchronous. */
+HBM_API hbm_status unload_dataset(hbm_ctx *ctx, int32_t slot);
+
+/* Host-side state of a slot, without touching the device: out[0] loaded,
+ * out[1] active (loaded, budget not spent), out[2] sweeps done, out[3]
+ * theta steps done, out[4] obj_start, out[5] N. */
+HBM_API hbm_status slot_info(hbm_ctx *ctx, int32_t slot, int64_t out[6]);
+
+/* n_sweeps RAM sweeps of all latents of every active slot at its current
+ * theta (eq 2.4, eq 2.6).
  * Sweep k (1-based, counted over the context's life) draws block
  * (i, k, 0, 0) for object i, proposes Y = X + S U with U ~ N(0, I_d),
  * accepts when ln u < log pi(Y) - log pi(X), and adapts S with
  * eta = (k+1)^-gamma.  Each sweep also reduces, in FP64 and in a fixed
  * order, sum_i log f(chi_i; theta) and sum_i [log f(chi_i; theta') -
  * log f(chi_i; theta)] for the pending proposal theta', plus Z(theta'),
- * for the next theta_step.  out_accept_rate (nullable): mean acceptance
- * of the last sweep; non-NULL makes the call synchronous. */
+ * for the next theta_step.  out_accept_rate (nullable): [n_slots] mean
+ * acceptance of the last sweep (NaN for inactive slots); non-NULL makes the
+ * call synchronous. */
 HBM_API hbm_status ram_sweep(hbm_ctx *ctx, int32_t n_sweeps, double *out_accept_rate);
 
 /* sum_i log f(chi_i; theta) - N ln Z(theta) at the current latents, FP64
- * accumulation (the N-term sum a theta MH step consumes).  theta: [p] host.
+ * accumulation (the N-term sum a theta MH step consumes), for every loaded
+ * slot.  theta: [n_slots][p] host; out: [n_slots] (NaN for free slots).
  * Synchronous. */
 HBM_API hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out);
 
-/* One Metropolis-Hastings step on theta for the sweep just done: the
+/* One Metropolis-Hastings step on theta of every active slot, for the
+ * sweep just done: the
  * pending proposal theta' = theta + S_theta z (z from block (0, k, 1, b)) is
  * accepted when ln u < Delta (u from block (0, k, 2, 0)),
  * Delta = sum_i [log f(chi_i; theta') - log f(chi_i; theta)]
@@ -151,47 +217,65 @@ HBM_API hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out);
  * Delta = -inf outside the prior support; then S_theta is RAM-adapted and
  * theta is appended to the trace.  Runs on the device.  Requires a
  * ram_sweep since the last theta_step (HBM_ESTATE otherwise); HBM_ENOSPACE
- * when the trace is full.  out_accepted (nullable): 1 if accepted.
- * Synchronous. */
+ * when the trace is full.  out_accepted (nullable): [n_slots], 1 if
+ * accepted, 0 if not, -1 for slots that took no step.  Synchronous. */
 HBM_API hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted);
 
-/* n_cycles full cycles (sweep then theta step), with the theta step fused
- * into the sweep kernel's last workgroup, so no host round trip happens
- * between cycles; the sequence is replayed from a captured hipGraph when
- * use_graph != 0.  Results are identical to alternating ram_sweep(1) and
- * theta_step.  Asynchronous. */
+/* n_cycles full cycles (sweep then theta step) of every active slot: each
+ * cycle is the sweep kernel followed by an epilogue kernel that reduces the
+ * partials and takes the theta step on the device, so no host round trip
+ * happens between cycles; the sequence is replayed from a captured hipGraph
+ * when use_graph != 0.  A slot whose budget is reached stops at that cycle.
+ * Results are identical to alternating ram_sweep(1) and theta_step.
+ * Asynchronous. */
 HBM_API hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph);
 
-/* Copy recorded samples to host.  theta_out: [count][p] rows first..first+count-1
- * of the theta trace (or NULL).  chi_out: [count][d][N] latent snapshots
- * first..first+count-1 in the per-object precision (or NULL).  With both NULL
- * *n_written receives the number of theta rows recorded.  Synchronous. */
-HBM_API hbm_status get_samples(hbm_ctx *ctx, int64_t first, int64_t count, double *theta_out,
+/* Copy a slot's recorded samples to host.  theta_out: [count][p] rows
+ * first..first+count-1 of its theta trace (or NULL).  chi_out: [count][d][N]
+ * latent snapshots first..first+count-1 of its N objects, in the per-object
+ * precision (or NULL).  With both NULL *n_written receives the number of
+ * theta rows recorded.  Synchronous. */
+HBM_API hbm_status get_samples(hbm_ctx *ctx, int32_t slot, int64_t first, int64_t count, double *theta_out,
                        void *chi_out, int64_t *n_written);
 
-/* Current theta [p], theta factor [p][p] (either nullable) and sweeps done. */
-HBM_API hbm_status get_theta(hbm_ctx *ctx, double *theta, double *chol_theta, int64_t *k);
+/* A slot's current theta [p], theta factor [p][p] (either nullable) and
+ * sweeps done. */
+HBM_API hbm_status get_theta(hbm_ctx *ctx, int32_t slot, double *theta, double *chol_theta, int64_t *k);
 
-/* Overwrite theta, its factor and the sweep counter k (lockstep replay and
- * resume).  The caller's latent buffers are taken as they are.  Recomputes
- * Z(theta) and the pending proposal for sweep k + 1.  HBM_EDOMAIN when theta
- * is outside the prior support. */
-HBM_API hbm_status set_theta(hbm_ctx *ctx, const double *theta, const double *chol_theta, int64_t k);
+/* Overwrite a slot's theta, its factor and its sweep counter k (lockstep
+ * replay and resume).  The caller's latent buffers are taken as they are.
+ * Recomputes Z(theta) and the pending proposal for sweep k + 1.
+ * HBM_EDOMAIN when theta is outside the prior support. */
+HBM_API hbm_status set_theta(hbm_ctx *ctx, int32_t slot, const double *theta, const double *chol_theta, int64_t k);
 
 /* One sweep like ram_sweep that also writes, per object, in the per-object
  * precision: trace[0][i] = log pi_i(X), trace[1][i] = log pi_i(Y) (member
  * log likelihood plus log population density, with the constants of the
  * densities documented above), trace[2][i] = 1 if accepted else 0, and
  * trace[3 + j][i] = component j of the proposal Y; trace is a device buffer
- * [3 + d][N].  Synchronous. */
+ * [3 + d][C].  Synchronous. */
 HBM_API hbm_status ram_sweep_trace(hbm_ctx *ctx, void *trace);
 
-/* Statistics of the last sweep and theta step: out[0] sum log f(chi; theta),
+/* Statistics of a slot's last sweep and theta step: out[0] sum log f(chi; theta),
  * out[1] sum of per-object log f differences at theta', out[2] ln Z(theta),
  * out[3] ln Z(theta'), out[4] Delta of the last theta step, out[5] its
  * acceptance probability, out[6] accepted latent moves of the last sweep,
  * out[7] theta accepted (0/1).  Synchronous. */
-HBM_API hbm_status get_stats(hbm_ctx *ctx, double out[8]);
+HBM_API hbm_status get_stats(hbm_ctx *ctx, int32_t slot, double out[8]);
+
+/* Launch shape of the sweep kernel: 256-object tiles per workgroup (1, 2 or
+ * 4).  Every tile is still reduced on its own in a fixed order, so results
+ * do not depend on the shape.  Drops the captured graph.  Synchronous. */
+HBM_API hbm_status set_launch(hbm_ctx *ctx, int32_t tiles_per_group);
+
+/* Autotuner of the launch shape: for each shape, 32 warm-up cycles then
+ * trial_cycles timed cycles (graph replay, hipEvents on the context's
+ * stream); keeps the fastest.  The cycles are real cycles of every active
+ * slot (3 (32 + trial_cycles) of them, counted against max_cycles), and
+ * since results do not depend on the shape, tuning during burn-in changes
+ * no chain.  out_tiles_per_group (nullable): the choice; out_us (nullable):
+ * [3] microseconds per cycle for shapes 1, 2, 4.  Synchronous. */
+HBM_API hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t *out_tiles_per_group, double out_us[3]);
 
 /* Per-launch duration of the sweep kernel: when enabled, every sweep-kernel
  * launch carries a start and a stop hipEvent that the runtime records from

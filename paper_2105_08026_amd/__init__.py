@@ -24,9 +24,12 @@ HBM_OK, HBM_EINVAL, HBM_ENOMEM, HBM_EHIP, HBM_EDOMAIN, HBM_ESTATE, HBM_ENOSPACE 
 HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_3D = 1, 2, 3, 4
 HBM_FP64, HBM_FP32 = 1, 2
 
-EXPORTED = ("init_chains", "ram_sweep", "pop_loglik", "theta_step", "run_cycles", "get_samples",
-            "get_theta", "set_theta", "ram_sweep_trace", "get_stats", "kernel_timing",
-            "read_kernel_timing", "last_error", "destroy_chains")
+EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
+            "ram_sweep", "pop_loglik", "theta_step", "run_cycles", "get_samples", "get_theta", "set_theta",
+            "ram_sweep_trace", "get_stats", "set_launch", "autotune", "kernel_timing", "read_kernel_timing",
+            "last_error", "destroy_chains")
+
+TILE = 256   # objects per tile: datasets in a pool start on multiples of this
 
 _MODEL_DIMS = {  # model -> (d, p, m, precision)
     HBM_NORMAL_NORMAL_1D: (1, 2, 2, HBM_FP64),
@@ -47,7 +50,7 @@ class Config(ctypes.Structure):
         ("model", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_objects", ctypes.c_int64),
         ("seed", ctypes.c_uint64), ("target_accept", ctypes.c_double), ("eta_exponent", ctypes.c_double),
         ("s0", ctypes.c_double), ("theta_target_accept", ctypes.c_double), ("adapt_theta", ctypes.c_int32),
-        ("n_quad", ctypes.c_int32), ("thin_chi", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_quad", ctypes.c_int32), ("thin_chi", ctypes.c_int32), ("tiles_per_group", ctypes.c_int32),
         ("max_cycles", ctypes.c_int64), ("theta_chol0", ctypes.c_double * 25), ("model_consts", ctypes.c_double * 16),
     ]
 
@@ -55,6 +58,12 @@ class Config(ctypes.Structure):
 class Buffers(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("chi", ctypes.c_void_p), ("chol", ctypes.c_void_p),
                 ("acc", ctypes.c_void_p), ("chi_samples", ctypes.c_void_p)]
+
+
+class PoolConfig(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_slots", ctypes.c_int32),
+                ("n_quad", ctypes.c_int32), ("capacity", ctypes.c_int64), ("max_cycles", ctypes.c_int64),
+                ("snap_rows", ctypes.c_int64), ("tiles_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -70,15 +79,22 @@ def lib():
         P, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         sig = {
             "init_chains": [P, P, P, P, P, P],
+            "init_batch": [i32, P, P, P, P, P],
+            "create_pool": [P, P, P, P],
+            "load_datasets": [P, i32, P, P, P, P, P],
+            "unload_dataset": [P, i32],
+            "slot_info": [P, i32, P],
             "ram_sweep": [P, i32, P],
             "pop_loglik": [P, P, P],
             "theta_step": [P, P],
             "run_cycles": [P, i64, i32],
-            "get_samples": [P, i64, i64, P, P, P],
-            "get_theta": [P, P, P, P],
-            "set_theta": [P, P, P, i64],
+            "get_samples": [P, i32, i64, i64, P, P, P],
+            "get_theta": [P, i32, P, P, P],
+            "set_theta": [P, i32, P, P, i64],
             "ram_sweep_trace": [P, P],
-            "get_stats": [P, P],
+            "get_stats": [P, i32, P],
+            "set_launch": [P, i32],
+            "autotune": [P, i32, P, P],
             "kernel_timing": [P, i32],
             "read_kernel_timing": [P, P, P],
         }
@@ -121,67 +137,119 @@ def init_chains(config: Config, buffers: Buffers, chi0: Optional[np.ndarray], th
     return ctx
 
 
-def ram_sweep(ctx, n_sweeps: int = 1, rate: bool = False):
-    r = ctypes.c_double()
-    _check(lib().ram_sweep(ctx, n_sweeps, ctypes.byref(r) if rate else None), ctx)
-    return r.value if rate else None
+def init_batch(configs, buffers: Buffers, theta0s, stream: int = 0):
+    arr = (Config * len(configs))(*configs)
+    t0 = _arr(theta0s)
+    ctx = ctypes.c_void_p()
+    _check(lib().init_batch(len(configs), arr, ctypes.byref(buffers), _ptr(t0), ctypes.c_void_p(stream),
+                            ctypes.byref(ctx)), None)
+    return ctx
 
 
-def pop_loglik(ctx, theta) -> float:
-    out = ctypes.c_double()
-    _check(lib().pop_loglik(ctx, _ptr(_arr(theta)), ctypes.byref(out)), ctx)
-    return out.value
+def create_pool(pool: PoolConfig, buffers: Buffers, stream: int = 0):
+    ctx = ctypes.c_void_p()
+    _check(lib().create_pool(ctypes.byref(pool), ctypes.byref(buffers), ctypes.c_void_p(stream), ctypes.byref(ctx)),
+           None)
+    return ctx
 
 
-def theta_step(ctx) -> bool:
-    acc = ctypes.c_int32()
-    _check(lib().theta_step(ctx, ctypes.byref(acc)), ctx)
-    return bool(acc.value)
+def load_datasets(ctx, slots, obj_starts, configs, theta0s, budgets=None):
+    n = len(configs)
+    sl = _arr(slots, np.int32)
+    os_ = _arr(obj_starts, np.int64)
+    arr = (Config * n)(*configs)
+    t0 = _arr(theta0s)
+    bu = None if budgets is None else _arr(budgets, np.int64)
+    _check(lib().load_datasets(ctx, n, _ptr(sl), _ptr(os_), arr, _ptr(t0), None if bu is None else _ptr(bu)), ctx)
+
+
+def unload_dataset(ctx, slot: int):
+    _check(lib().unload_dataset(ctx, slot), ctx)
+
+
+def slot_info(ctx, slot: int) -> dict:
+    out = np.zeros(6, dtype=np.int64)
+    _check(lib().slot_info(ctx, slot, _ptr(out)), ctx)
+    return dict(zip(("loaded", "active", "k", "n_theta", "obj_start", "n"), out.tolist()))
+
+
+def ram_sweep(ctx, n_sweeps: int = 1, rate: bool = False, n_slots: int = 1):
+    """Sweeps every active slot; with rate=True returns the [n_slots] acceptance rates."""
+    r = np.zeros(n_slots)
+    _check(lib().ram_sweep(ctx, n_sweeps, _ptr(r) if rate else None), ctx)
+    return r if rate else None
+
+
+def pop_loglik(ctx, thetas) -> np.ndarray:
+    """thetas: [n_slots][p]; returns [n_slots] (NaN for free slots)."""
+    th = _arr(thetas)
+    out = np.zeros(th.shape[0])
+    _check(lib().pop_loglik(ctx, _ptr(th), _ptr(out)), ctx)
+    return out
+
+
+def theta_step(ctx, n_slots: int = 1) -> np.ndarray:
+    """Returns [n_slots]: 1 accepted, 0 rejected, -1 no step (inactive slot)."""
+    acc = np.zeros(n_slots, dtype=np.int32)
+    _check(lib().theta_step(ctx, _ptr(acc)), ctx)
+    return acc
 
 
 def run_cycles(ctx, n_cycles: int, use_graph: bool = True):
     _check(lib().run_cycles(ctx, n_cycles, int(use_graph)), ctx)
 
 
-def get_samples(ctx, first: int, count: int, p: int, chi_shape=None, chi_dtype=None):
+def get_samples(ctx, slot: int, first: int, count: int, p: int, chi_shape=None, chi_dtype=None):
     """Returns (theta rows [count][p], latent snapshots [count][d][N] or None)."""
     th = np.zeros((count, p))
     ch = None if chi_shape is None else np.zeros((count, *chi_shape), dtype=chi_dtype)
     nw = ctypes.c_int64()
     if count > 0:
-        _check(lib().get_samples(ctx, first, count, _ptr(th), None, ctypes.byref(nw)), ctx)
+        _check(lib().get_samples(ctx, slot, first, count, _ptr(th), None, ctypes.byref(nw)), ctx)
         if ch is not None:
-            _check(lib().get_samples(ctx, first, count, None, _ptr(ch), ctypes.byref(nw)), ctx)
+            _check(lib().get_samples(ctx, slot, first, count, None, _ptr(ch), ctypes.byref(nw)), ctx)
     return th, ch
 
 
-def n_theta_samples(ctx) -> int:
+def n_theta_samples(ctx, slot: int = 0) -> int:
     nw = ctypes.c_int64()
-    _check(lib().get_samples(ctx, 0, 0, None, None, ctypes.byref(nw)), ctx)
+    _check(lib().get_samples(ctx, slot, 0, 0, None, None, ctypes.byref(nw)), ctx)
     return nw.value
 
 
-def get_theta(ctx, p: int):
+def get_theta(ctx, p: int, slot: int = 0):
     th = np.zeros(p)
     ch = np.zeros((p, p))
     k = ctypes.c_int64()
-    _check(lib().get_theta(ctx, _ptr(th), _ptr(ch), ctypes.byref(k)), ctx)
+    _check(lib().get_theta(ctx, slot, _ptr(th), _ptr(ch), ctypes.byref(k)), ctx)
     return th, ch, k.value
 
 
-def set_theta(ctx, theta, chol_theta, k: int):
-    _check(lib().set_theta(ctx, _ptr(_arr(theta)), _ptr(_arr(chol_theta)), k), ctx)
+def set_theta(ctx, theta, chol_theta, k: int, slot: int = 0):
+    _check(lib().set_theta(ctx, slot, _ptr(_arr(theta)), _ptr(_arr(chol_theta)), k), ctx)
 
 
 def ram_sweep_trace(ctx, trace_ptr: int):
     _check(lib().ram_sweep_trace(ctx, ctypes.c_void_p(trace_ptr)), ctx)
 
 
-def get_stats(ctx) -> dict:
+def get_stats(ctx, slot: int = 0) -> dict:
     out = np.zeros(8)
-    _check(lib().get_stats(ctx, _ptr(out)), ctx)
+    _check(lib().get_stats(ctx, slot, _ptr(out)), ctx)
     keys = ("sum_lf", "sum_dlf", "logZ_cur", "logZ_prop", "delta", "alpha", "n_acc", "accepted")
     return dict(zip(keys, out.tolist()))
+
+
+def set_launch(ctx, tiles_per_group: int):
+    _check(lib().set_launch(ctx, tiles_per_group), ctx)
+
+
+def autotune(ctx, trial_cycles: int = 64):
+    """Runs 3 x (32 + trial_cycles) real cycles; returns (chosen tiles per workgroup, us/cycle for 1, 2, 4)."""
+    pick = ctypes.c_int32()
+    us = np.zeros(3)
+    _check(lib().autotune(ctx, trial_cycles, ctypes.byref(pick), _ptr(us)), ctx)
+    return pick.value, us
 
 
 def kernel_timing(ctx, enable: bool):
@@ -200,50 +268,55 @@ def destroy_chains(ctx):
         lib().destroy_chains(ctx)
 
 
-# -- convenience wrapper -------------------------------------------------------
+# -- convenience wrappers ------------------------------------------------------
 
-class Sampler:
-    """One dataset's chains: torch-owned device buffers plus a library context.
+def make_config(wl, max_cycles: int = 10000, thin: int = 0, s0: float = 1.0, adapt_theta: bool = True,
+                n_quad: int = 512, gamma: float = 2.0 / 3.0, alpha_star_theta: float = 0.4, seed=None) -> Config:
+    """The hbm_config of a :mod:`synth` workload."""
+    d, p, m, prec = _MODEL_DIMS[wl.model]
+    cfg = Config()
+    cfg.model, cfg.precision, cfg.n_objects = wl.model, prec, wl.n
+    cfg.seed = int(wl.seed if seed is None else seed)
+    cfg.target_accept, cfg.eta_exponent, cfg.s0 = wl.alpha_star, gamma, s0
+    cfg.theta_target_accept, cfg.adapt_theta = alpha_star_theta, int(adapt_theta)
+    cfg.n_quad, cfg.thin_chi, cfg.max_cycles = n_quad, thin, max_cycles
+    ch0 = np.asarray(wl.theta_chol0, dtype=np.float64)
+    for r in range(p):
+        for q in range(p):
+            cfg.theta_chol0[r * p + q] = ch0[r, q] if q <= r else 0.0
+    for j in range(16):
+        cfg.model_consts[j] = float(wl.consts[j])
+    return cfg
 
-    ``wl`` is a workload from :mod:`synth` (data arrays, constants, theta0,
-    chi0).  Buffers: data [m][N], chi [d][N], chol [d(d+1)/2][N], acc [N]
-    (int32 storage of the uint32 counters), snapshots [max_cycles/thin][d][N].
-    """
 
-    def __init__(self, wl, device: str = "cuda:0", max_cycles: int = 10000, thin: int = 0, s0: float = 1.0,
-                 adapt_theta: bool = True, n_quad: int = 512, gamma: float = 2.0 / 3.0,
-                 alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None, seed=None):
-        d, p, m, prec = _MODEL_DIMS[wl.model]
-        self.wl, self.d, self.p, self.n = wl, d, p, wl.n
+def packed_offsets(ns):
+    """Object offsets of datasets packed back to back, each on a tile boundary, and the capacity."""
+    offs, o = [], 0
+    for n in ns:
+        offs.append(o)
+        o += -(-int(n) // TILE) * TILE
+    return offs, (offs[-1] + int(ns[-1]) if ns else 0)
+
+
+class _Chains:
+    """Shared plumbing: torch-owned packed device buffers and a context."""
+
+    def _alloc(self, model: int, cap: int, snap_rows: int, device, stream):
+        d, p, m, prec = _MODEL_DIMS[model]
+        self.model, self.d, self.p, self.m, self.cap = model, d, p, m, cap
         self.dtype = torch.float64 if prec == HBM_FP64 else torch.float32
+        self.npdtype = np.float64 if prec == HBM_FP64 else np.float32
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
-            self.data = torch.as_tensor(np.ascontiguousarray(wl.data), dtype=self.dtype, device=self.device)
-            self.chi = torch.empty((d, wl.n), dtype=self.dtype, device=self.device)
-            self.chol = torch.empty((d * (d + 1) // 2, wl.n), dtype=self.dtype, device=self.device)
-            self.acc = torch.empty((wl.n,), dtype=torch.int32, device=self.device)
-            n_snap = max_cycles // thin if thin > 0 else 0
-            self.snaps = torch.empty((max(n_snap, 1), d, wl.n), dtype=self.dtype, device=self.device) if n_snap else None
-        cfg = Config()
-        cfg.model, cfg.precision, cfg.n_objects = wl.model, prec, wl.n
-        cfg.seed = int(wl.seed if seed is None else seed)
-        cfg.target_accept, cfg.eta_exponent, cfg.s0 = wl.alpha_star, gamma, s0
-        cfg.theta_target_accept, cfg.adapt_theta = alpha_star_theta, int(adapt_theta)
-        cfg.n_quad, cfg.thin_chi, cfg.max_cycles = n_quad, thin, max_cycles
-        ch0 = np.asarray(wl.theta_chol0, dtype=np.float64)
-        for r in range(p):
-            for q in range(p):
-                cfg.theta_chol0[r * p + q] = ch0[r, q] if q <= r else 0.0
-        for j in range(16):
-            cfg.model_consts[j] = float(wl.consts[j])
-        self.config = cfg
-        bufs = Buffers(self.data.data_ptr(), self.chi.data_ptr(), self.chol.data_ptr(), self.acc.data_ptr(),
-                       self.snaps.data_ptr() if self.snaps is not None else None)
-        self.buffers = bufs
-        torch.cuda.synchronize(self.device)
-        with torch.cuda.device(self.device):
-            self.ctx = init_chains(cfg, bufs, wl.chi0, wl.theta0, self.stream.cuda_stream)
+            self.data = torch.zeros((m, cap), dtype=self.dtype, device=self.device)
+            self.chi = torch.zeros((d, cap), dtype=self.dtype, device=self.device)
+            self.chol = torch.empty((d * (d + 1) // 2, cap), dtype=self.dtype, device=self.device)
+            self.acc = torch.empty((cap,), dtype=torch.int32, device=self.device)
+            self.snaps = (torch.empty((snap_rows, d, cap), dtype=self.dtype, device=self.device)
+                          if snap_rows > 0 else None)
+        self.buffers = Buffers(self.data.data_ptr(), self.chi.data_ptr(), self.chol.data_ptr(), self.acc.data_ptr(),
+                               self.snaps.data_ptr() if self.snaps is not None else None)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -256,18 +329,46 @@ class Sampler:
         except Exception:
             pass
 
-    # methods mirror the ABI
-    def ram_sweep(self, n: int = 1, rate: bool = False):
-        return ram_sweep(self.ctx, n, rate)
-
-    def theta_step(self) -> bool:
-        return theta_step(self.ctx)
-
     def run_cycles(self, n: int, use_graph: bool = True):
         run_cycles(self.ctx, n, use_graph)
 
+    def autotune(self, trial_cycles: int = 64):
+        return autotune(self.ctx, trial_cycles)
+
+    def set_launch(self, tiles_per_group: int):
+        set_launch(self.ctx, tiles_per_group)
+
+
+class Sampler(_Chains):
+    """One dataset's chains: torch-owned device buffers plus a library context.
+
+    ``wl`` is a workload from :mod:`synth` (data arrays, constants, theta0,
+    chi0).  Buffers: data [m][N], chi [d][N], chol [d(d+1)/2][N], acc [N]
+    (int32 storage of the uint32 counters), snapshots [max_cycles/thin][d][N].
+    """
+
+    def __init__(self, wl, device: str = "cuda:0", max_cycles: int = 10000, thin: int = 0, s0: float = 1.0,
+                 adapt_theta: bool = True, n_quad: int = 512, gamma: float = 2.0 / 3.0,
+                 alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None, seed=None):
+        self.wl, self.n = wl, wl.n
+        self._alloc(wl.model, wl.n, max_cycles // thin if thin > 0 else 0, device, stream)
+        with torch.no_grad():
+            self.data.copy_(torch.as_tensor(np.ascontiguousarray(wl.data), dtype=self.dtype))
+        self.config = make_config(wl, max_cycles, thin, s0, adapt_theta, n_quad, gamma, alpha_star_theta, seed)
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            self.ctx = init_chains(self.config, self.buffers, wl.chi0, wl.theta0, self.stream.cuda_stream)
+
+    # methods mirror the ABI
+    def ram_sweep(self, n: int = 1, rate: bool = False):
+        r = ram_sweep(self.ctx, n, rate)
+        return float(r[0]) if rate else None
+
+    def theta_step(self) -> bool:
+        return bool(theta_step(self.ctx)[0] == 1)
+
     def pop_loglik(self, theta) -> float:
-        return pop_loglik(self.ctx, theta)
+        return float(pop_loglik(self.ctx, np.asarray(theta, dtype=np.float64).reshape(1, -1))[0])
 
     def theta(self):
         return get_theta(self.ctx, self.p)
@@ -280,14 +381,10 @@ class Sampler:
 
     def theta_trace(self) -> np.ndarray:
         n = n_theta_samples(self.ctx)
-        return get_samples(self.ctx, 0, n, self.p)[0]
+        return get_samples(self.ctx, 0, 0, n, self.p)[0]
 
     def chi_snapshots(self, first: int, count: int) -> np.ndarray:
-        npdt = np.float64 if self.dtype == torch.float64 else np.float32
-        nw = ctypes.c_int64()
-        out = np.zeros((count, self.d, self.n), dtype=npdt)
-        _check(lib().get_samples(self.ctx, first, count, None, _ptr(out), ctypes.byref(nw)), self.ctx)
-        return out
+        return get_samples(self.ctx, 0, first, count, self.p, (self.d, self.n), self.npdtype)[1]
 
     def trace_sweep(self) -> np.ndarray:
         """One sweep returning per-object (log pi(X), log pi(Y), accepted, Y[0..d-1]) as float64 [3 + d][N]."""
@@ -308,3 +405,162 @@ class Sampler:
             self.chol.copy_(torch.as_tensor(np.asarray(chol), dtype=self.dtype))
             self.acc.copy_(torch.as_tensor(np.asarray(acc).astype(np.uint32).view(np.int32)))
         torch.cuda.synchronize(self.device)
+
+
+class Batch(_Chains):
+    """Many datasets of one model advanced together (init_batch).
+
+    Dataset j sits in slot j at objects [offsets[j], offsets[j] + N_j) of the
+    packed buffers; every launch covers all of them.
+    """
+
+    def __init__(self, wls, device: str = "cuda:0", max_cycles: int = 10000, s0: float = 1.0,
+                 adapt_theta: bool = True, n_quad: int = 512, gamma: float = 2.0 / 3.0,
+                 alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None):
+        self.wls = list(wls)
+        ns = [w.n for w in self.wls]
+        self.offsets, cap = packed_offsets(ns)
+        self.ns = ns
+        self._alloc(self.wls[0].model, cap, 0, device, stream)
+        data = np.zeros((self.m, cap), dtype=self.npdtype)
+        chi = np.zeros((self.d, cap), dtype=self.npdtype)
+        for w, o in zip(self.wls, self.offsets):
+            data[:, o:o + w.n] = w.data
+            chi[:, o:o + w.n] = w.chi0
+        with torch.no_grad():
+            self.data.copy_(torch.as_tensor(data))
+            self.chi.copy_(torch.as_tensor(chi))
+        self.configs = [make_config(w, max_cycles, 0, s0, adapt_theta, n_quad, gamma, alpha_star_theta)
+                        for w in self.wls]
+        theta0 = np.array([w.theta0 for w in self.wls], dtype=np.float64)
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            self.ctx = init_batch(self.configs, self.buffers, theta0, self.stream.cuda_stream)
+
+    @property
+    def n_datasets(self) -> int:
+        return len(self.wls)
+
+    def ram_sweep(self, n: int = 1, rate: bool = False):
+        return ram_sweep(self.ctx, n, rate, self.n_datasets)
+
+    def theta_step(self) -> np.ndarray:
+        return theta_step(self.ctx, self.n_datasets)
+
+    def pop_loglik(self, thetas) -> np.ndarray:
+        return pop_loglik(self.ctx, thetas)
+
+    def theta(self, j: int):
+        return get_theta(self.ctx, self.p, j)
+
+    def stats(self, j: int) -> dict:
+        return get_stats(self.ctx, j)
+
+    def theta_trace(self, j: int) -> np.ndarray:
+        n = n_theta_samples(self.ctx, j)
+        return get_samples(self.ctx, j, 0, n, self.p)[0]
+
+    def latents(self, j: int) -> np.ndarray:
+        """Host copy of dataset j's latents [d][N_j]."""
+        torch.cuda.synchronize(self.device)
+        o = self.offsets[j]
+        return self.chi[:, o:o + self.ns[j]].double().cpu().numpy()
+
+
+class Pool(_Chains):
+    """A fixed pool of slots over packed buffers for continuous batching.
+
+    Datasets are admitted into a free slot and a free run of object tiles
+    (first fit), advance together with every other resident dataset, stop on
+    the device when their theta-step budget is spent, and are retired to
+    free their slot and tiles.
+    """
+
+    def __init__(self, model: int, capacity: int, n_slots: int, max_cycles: int, device: str = "cuda:0",
+                 n_quad: int = 512, stream: Optional[torch.cuda.Stream] = None):
+        cap = -(-int(capacity) // TILE) * TILE
+        self._alloc(model, cap, 0, device, stream)
+        pc = PoolConfig()
+        pc.model, pc.precision, pc.n_slots = model, _MODEL_DIMS[model][3], n_slots
+        pc.n_quad, pc.capacity, pc.max_cycles, pc.snap_rows = n_quad, cap, max_cycles, 0
+        self.pool_config, self.n_slots, self.max_cycles = pc, n_slots, max_cycles
+        self.free_slots = list(range(n_slots - 1, -1, -1))
+        self.tiles = np.full(cap // TILE, -1, dtype=np.int64)     # slot owning each tile
+        self.resident = {}                                          # slot -> (obj_start, n)
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            self.ctx = create_pool(pc, self.buffers, self.stream.cuda_stream)
+
+    def _find_tiles(self, nt: int):
+        run = 0
+        for t in range(self.tiles.size):
+            run = run + 1 if self.tiles[t] < 0 else 0
+            if run == nt:
+                return t - nt + 1
+        return None
+
+    def fits(self, n: int) -> bool:
+        return bool(self.free_slots) and self._find_tiles(-(-n // TILE)) is not None
+
+    def admit(self, wls, budgets, **cfg_kw):
+        """Loads the workloads that fit, in order, and returns their slots (None where one did not fit)."""
+        slots, starts, cfgs, th0, bud, placed = [], [], [], [], [], []
+        for w, b in zip(wls, budgets):
+            nt = -(-w.n // TILE)
+            t0 = self._find_tiles(nt) if self.free_slots else None
+            if t0 is None:
+                placed.append(None)
+                continue
+            slot = self.free_slots.pop()
+            self.tiles[t0:t0 + nt] = slot
+            o = t0 * TILE
+            slots.append(slot)
+            starts.append(o)
+            cfgs.append(make_config(w, max_cycles=self.max_cycles, **cfg_kw))
+            th0.append(w.theta0)
+            bud.append(b)
+            placed.append(slot)
+            self.resident[slot] = (o, w.n)
+        if slots:
+            # data and starting latents at their positions, then one load call
+            with torch.no_grad():
+                for w, o in zip([w for w, s in zip(wls, placed) if s is not None], starts):
+                    self.data[:, o:o + w.n].copy_(torch.as_tensor(np.asarray(w.data, dtype=self.npdtype)))
+                    self.chi[:, o:o + w.n].copy_(torch.as_tensor(np.asarray(w.chi0, dtype=self.npdtype)))
+            torch.cuda.current_stream(self.device).synchronize()
+            try:
+                load_datasets(self.ctx, slots, starts, cfgs, np.array(th0, dtype=np.float64), bud)
+            except Exception:
+                for sl in slots:
+                    self._release(sl)
+                raise
+        return placed
+
+    def _release(self, slot: int):
+        self.tiles[self.tiles == slot] = -1
+        self.resident.pop(slot, None)
+        self.free_slots.append(slot)
+
+    def retire(self, slot: int) -> np.ndarray:
+        """Returns the slot's theta trace and frees the slot."""
+        tr = self.theta_trace(slot)
+        unload_dataset(self.ctx, slot)
+        self._release(slot)
+        return tr
+
+    def info(self, slot: int) -> dict:
+        return slot_info(self.ctx, slot)
+
+    def finished(self):
+        """Resident slots whose budget is spent (host bookkeeping, no device read)."""
+        return [s for s in self.resident if not slot_info(self.ctx, s)["active"]]
+
+    def theta_trace(self, slot: int) -> np.ndarray:
+        n = n_theta_samples(self.ctx, slot)
+        return get_samples(self.ctx, slot, 0, n, self.p)[0]
+
+    def latents(self, slot: int) -> np.ndarray:
+        """Host copy of a resident dataset's latents [d][N]."""
+        torch.cuda.synchronize(self.device)
+        o, n = self.resident[slot]
+        return self.chi[:, o:o + n].double().cpu().numpy()

@@ -269,19 +269,27 @@ struct CycleState {
     double sum_dlf_raw;            // per-object part of sum_dlf as reduced from the tiles
     int64_t k;                     // sweeps done
     int64_t n_theta;               // theta steps done (= trace rows written)
+    int64_t budget;                // theta steps after which the dataset stops (0: no limit)
     int32_t prop_valid, used_valid;
     int32_t sums_ready;
     int32_t accepted_last;
     int32_t flags;
     int32_t first_bad;             // smallest object index with a non-finite initial density
+    int32_t active;                // 0: the dataset's tiles and theta step are skipped
+    int32_t pad_;
     float kc_f[32];                // per-sweep kernel constants, FP32 models
     double kc_d[32];               // per-sweep kernel constants, FP64 models
 };
 static_assert(sizeof(CycleState) % 8 == 0, "CycleState is staged through LDS in 8-byte words");
 
-// Per-context constants that never change after init.
+// Per-dataset constants, fixed while the dataset is loaded.  Datasets are
+// packed back to back in the caller's arrays; each starts a new 256-object
+// tile, so no tile straddles two datasets.
 struct Statics {
-    int64_t n;
+    int64_t n;                     // objects of this dataset
+    int64_t obj_start;             // its first object in the packed arrays
+    int32_t tile_start;            // its first tile
+    int32_t n_tiles;               // its tiles, ceil(n / 256)
     int64_t trace_cap;             // rows of the theta trace
     int64_t snap_cap;              // latent snapshots that fit
     int32_t thin;
@@ -291,6 +299,7 @@ struct Statics {
     uint32_t key0, key1;
     double gamma;                  // eta exponent
     double alpha_star, alpha_star_theta;
+    double s0;                     // initial latent factor S_1 = s0 I
     double mc[16];                 // model constants as given
     double md[16];                 // derived model constants (FP64)
     float mf[16];                  // derived model constants (FP32)

@@ -1,8 +1,16 @@
 // Host runtime and C ABI of the sampler (declared in include/hbm.h).
 //
 // The host only validates arguments, allocates the library's scratch,
-// enqueues kernels and copies results; all sampler arithmetic runs in the
-// kernels of kernels.h.
+// keeps the slot table of a pool, enqueues kernels and copies results; all
+// sampler arithmetic runs in the kernels of kernels.h.
+//
+// A context is a pool of slots.  Each loaded slot holds one dataset whose
+// objects occupy a contiguous, tile-aligned range of the caller's packed
+// [component][capacity] buffers.  Every launch covers all slots at once
+// (one side workgroup per slot, one workgroup per 256-object tile); a
+// device-side flag per slot switches a dataset off when it is unloaded or
+// its theta-step budget is spent, so a captured graph stays valid while
+// datasets come and go.
 #include "hbm.h"
 #include "kernels.h"
 
@@ -28,33 +36,52 @@ struct CtxImpl;
 struct Launch {
     hbm_status (*sweep)(CtxImpl *, bool full, void *trace);
     hbm_status (*theta)(CtxImpl *);
-    hbm_status (*set_theta)(CtxImpl *);
-    hbm_status (*poplik)(CtxImpl *, const double *theta);
-    hbm_status (*prepare)(CtxImpl *);
-    hbm_status (*check_init)(CtxImpl *);
+    hbm_status (*set_theta)(CtxImpl *);       // slots flagged in c->which
+    hbm_status (*poplik)(CtxImpl *);          // theta of every slot in c->theta_in
+    hbm_status (*prepare)(CtxImpl *);         // slots flagged in c->which
+    hbm_status (*check_init)(CtxImpl *);      // slots flagged in c->which
+    hbm_status (*quadrature)(CtxImpl *);      // reference Gauss-Legendre rule
+};
+
+// Host mirror of one slot.  Every field follows from the calls made, so the
+// host never has to read the device to know a slot's progress.
+struct Slot {
+    bool loaded = false;
+    bool active = false;       // loaded and budget not spent
+    bool sums_ready = false;   // a plain sweep waits for its theta step
+    int64_t n = 0, obj_start = 0;
+    int32_t tile_start = 0, n_tiles = 0;
+    int64_t k = 0, n_theta = 0, budget = 0, trace_cap = 0, snap_cap = 0;
+    int32_t thin = 0;
 };
 
 struct CtxImpl {
-    hbm_config cfg{};
+    hbm_pool_config pool{};
     hbm_buffers buf{};
     int d = 0, p = 0, m = 0, md = 0, nc = 0;
     size_t esize = 0;
-    int64_t n = 0;
-    int32_t n_tiles = 0;
+    int64_t cap = 0;                // object positions (array stride)
+    int32_t n_tiles = 0;            // ceil(cap / 256)
+    int32_t n_slots = 0;
+    int32_t nq = 1;
+    int32_t tpw = 1;                // tiles per sweep workgroup (1, 2 or 4)
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
-    void *dd = nullptr;
-    double *partials = nullptr;     // [n_tiles][3]
-    double *zout = nullptr;         // [2]: ln Z of pop_loglik
-    Precomp *side = nullptr;        // values the sweep's workgroup 0 leaves for the epilogue
-    double *ref_t = nullptr, *ref_w = nullptr, *qx = nullptr, *qw = nullptr, *qeps = nullptr;
-    CycleState *cs = nullptr;
-    Statics *st = nullptr;
-    double *theta_trace = nullptr;
-    int64_t trace_cap = 0, snap_cap = 0;
-    // host bookkeeping that mirrors the device state
-    int64_t k = 0, n_theta = 0;
-    bool sums_ready = false;
+    void *dd = nullptr;             // [md][cap] derived per-object data
+    double *partials = nullptr;     // [3][n_tiles]
+    double *pout = nullptr;         // [n_slots][2] results of pop_loglik
+    double *theta_in = nullptr;     // [n_slots][p] arguments of pop_loglik
+    Precomp *side = nullptr;        // [n_slots] values the side workgroups leave for the epilogue
+    double *ref_t = nullptr, *ref_w = nullptr;       // [nq]
+    double *qx = nullptr, *qw = nullptr, *qeps = nullptr;   // [n_slots][nq]
+    CycleState *cs = nullptr;       // [n_slots]
+    Statics *st = nullptr;          // [n_slots]
+    double *theta_trace = nullptr;  // [n_slots][max_cycles][p]
+    int32_t *tile_ds = nullptr;     // [n_tiles] slot of each tile or -1
+    int32_t *which = nullptr;       // [n_slots] slots an initialisation kernel acts on
+    std::vector<Slot> slots;
+    std::vector<int32_t> h_tile_ds, h_which;
+    std::vector<CycleState> h_cs;   // staging of state reads
     bool poisoned = false;
     std::string err;
     const Launch *ops = nullptr;
@@ -68,6 +95,13 @@ struct CtxImpl {
     int64_t timed_launches = 0;
     double timed_ms = 0.0;
 };
+
+}  // namespace
+
+// The opaque handle of the C ABI.
+struct hbm_ctx : CtxImpl {};
+
+namespace {
 
 hbm_status fail(CtxImpl *c, hbm_status code, const std::string &msg)
 {
@@ -99,7 +133,7 @@ hbm_status hip_fail(CtxImpl *c, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail((c), e_, what); \
     } while (0)
 
-int blocks_for(int64_t n) { return static_cast<int>((n + kBlock - 1) / kBlock); }
+int32_t tiles_for(int64_t n) { return static_cast<int32_t>((n + kBlock - 1) / kBlock); }
 
 // Events that time one sweep-kernel launch.
 hipEvent_t take_event(CtxImpl *c)
@@ -118,7 +152,7 @@ template <class M>
 struct Ops {
     using T = typename M::T;
 
-    static SweepArgs<T> sweep_args(CtxImpl *c, void *trace)
+    static hbm_status sweep(CtxImpl *c, bool full, void *trace)
     {
         SweepArgs<T> a;
         a.chi = static_cast<T *>(c->buf.chi);
@@ -134,95 +168,113 @@ struct Ops {
         a.qx = c->qx;
         a.qw = c->qw;
         a.qeps = c->qeps;
-        a.n = c->n;
-        a.n_tiles = c->n_tiles;
-        return a;
-    }
-
-    static hbm_status sweep(CtxImpl *c, bool full, void *trace)
-    {
-        const SweepArgs<T> a = sweep_args(c, trace);
-        const dim3 grid(static_cast<unsigned>(c->n_tiles + 1));
+        a.tile_ds = c->tile_ds;
+        a.n_total = c->cap;
+        a.n_tiles_total = c->n_tiles;
+        a.n_ds = c->n_slots;
+        a.nq = c->nq;
+        // traced sweeps (a checking aid) always take one tile per workgroup
+        const int tpw = trace ? 1 : c->tpw;
+        const dim3 grid(static_cast<unsigned>(c->n_slots + (c->n_tiles + tpw - 1) / tpw));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
             // the runtime takes both timestamps from the dispatch itself
-            hipEvent_t e0 = take_event(c), e1 = take_event(c);
+            e0 = take_event(c);
+            e1 = take_event(c);
             if (!e0 || !e1) return fail(c, HBM_ENOMEM, "hipEventCreate failed");
-            if (trace)
-                hipExtLaunchKernelGGL((sweep_kernel<M, true>), grid, dim3(kBlock), 0, c->stream, e0, e1, 0, a);
-            else
-                hipExtLaunchKernelGGL((sweep_kernel<M, false>), grid, dim3(kBlock), 0, c->stream, e0, e1, 0, a);
             c->ev_pending.push_back(e0);
             c->ev_pending.push_back(e1);
-        } else if (trace) {
-            hipLaunchKernelGGL((sweep_kernel<M, true>), grid, dim3(kBlock), 0, c->stream, a);
-        } else {
-            hipLaunchKernelGGL((sweep_kernel<M, false>), grid, dim3(kBlock), 0, c->stream, a);
         }
+        if (trace) launch_sweep<true, 1>(c, grid, a, e0, e1);
+        else if (tpw == 4) launch_sweep<false, 4>(c, grid, a, e0, e1);
+        else if (tpw == 2) launch_sweep<false, 2>(c, grid, a, e0, e1);
+        else launch_sweep<false, 1>(c, grid, a, e0, e1);
         LAUNCHCHK(c, "sweep_kernel");
+        const EpiArgs e = epi_args(c);
         if (full)
-            hipLaunchKernelGGL((epilogue_kernel<M, true>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st,
-                               c->partials, c->side, c->theta_trace, c->n_tiles);
+            hipLaunchKernelGGL((epilogue_kernel<M, true>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, e);
         else
-            hipLaunchKernelGGL((epilogue_kernel<M, false>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st,
-                               c->partials, c->side, c->theta_trace, c->n_tiles);
+            hipLaunchKernelGGL((epilogue_kernel<M, false>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, e);
         LAUNCHCHK(c, "epilogue_kernel");
         return HBM_OK;
     }
 
+    template <bool kTrace, int TPW>
+    static void launch_sweep(CtxImpl *c, dim3 grid, const SweepArgs<T> &a, hipEvent_t e0, hipEvent_t e1)
+    {
+        if (e0)
+            hipExtLaunchKernelGGL((sweep_kernel<M, kTrace, TPW>), grid, dim3(kBlock), 0, c->stream, e0, e1, 0, a);
+        else
+            hipLaunchKernelGGL((sweep_kernel<M, kTrace, TPW>), grid, dim3(kBlock), 0, c->stream, a);
+    }
+
+    static EpiArgs epi_args(CtxImpl *c)
+    {
+        EpiArgs e;
+        e.cs = c->cs;
+        e.st = c->st;
+        e.partials = c->partials;
+        e.side = c->side;
+        e.theta_trace = c->theta_trace;
+        e.trace_stride = c->pool.max_cycles;
+        e.n_tiles_total = c->n_tiles;
+        return e;
+    }
+
     static hbm_status theta(CtxImpl *c)
     {
-        hipLaunchKernelGGL((theta_kernel<M>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st, c->side,
-                           c->theta_trace);
+        hipLaunchKernelGGL((theta_kernel<M>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, epi_args(c));
         LAUNCHCHK(c, "theta_kernel");
         return HBM_OK;
     }
 
     static hbm_status set_theta(CtxImpl *c)
     {
-        hipLaunchKernelGGL((set_theta_kernel<M>), dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->st, c->qx, c->qw,
-                           c->qeps);
+        hipLaunchKernelGGL((set_theta_kernel<M>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, c->cs, c->st, c->qx,
+                           c->qw, c->qeps, c->nq, c->which);
         LAUNCHCHK(c, "set_theta_kernel");
         return HBM_OK;
     }
 
-    static hbm_status poplik(CtxImpl *c, const double *theta)
+    static hbm_status poplik(CtxImpl *c)
     {
         PopArgs<T> a;
         a.chi = static_cast<const T *>(c->buf.chi);
         a.dd = static_cast<const T *>(c->dd);
         a.partials = c->partials;
-        a.zout = c->zout;
+        a.pout = c->pout;
+        a.theta = c->theta_in;
         a.st = c->st;
         a.qx = c->qx;
         a.qw = c->qw;
         a.qeps = c->qeps;
-        a.n = c->n;
-        for (int r = 0; r < kMaxP; ++r) a.theta[r] = r < M::P ? theta[r] : 0.0;
-        hipLaunchKernelGGL((poplik_kernel<M>), dim3(c->n_tiles + 1), dim3(kBlock), 0, c->stream, a);
+        a.tile_ds = c->tile_ds;
+        a.n_total = c->cap;
+        a.n_tiles_total = c->n_tiles;
+        a.n_ds = c->n_slots;
+        a.nq = c->nq;
+        hipLaunchKernelGGL((poplik_kernel<M>), dim3(c->n_slots + c->n_tiles), dim3(kBlock), 0, c->stream, a);
         LAUNCHCHK(c, "poplik_kernel");
-        hipLaunchKernelGGL(poplik_finish_kernel, dim3(1), dim3(kBlock), 0, c->stream, c->cs, c->partials, c->zout,
-                           c->n, c->n_tiles);
+        hipLaunchKernelGGL(poplik_finish_kernel, dim3(c->n_slots), dim3(kBlock), 0, c->stream, c->st, c->partials,
+                           c->pout);
         LAUNCHCHK(c, "poplik_finish_kernel");
         return HBM_OK;
     }
 
     static hbm_status prepare(CtxImpl *c)
     {
-        hipLaunchKernelGGL((statics_kernel<M>), dim3(1), dim3(1), 0, c->stream, c->st);
+        hipLaunchKernelGGL((statics_kernel<M>), dim3(c->n_slots), dim3(1), 0, c->stream, c->st, c->which);
         LAUNCHCHK(c, "statics_kernel");
-        hipLaunchKernelGGL((derive_data_kernel<M>), dim3(blocks_for(c->n)), dim3(kBlock), 0, c->stream,
-                           static_cast<const T *>(c->buf.data), static_cast<T *>(c->dd), c->st);
+        hipLaunchKernelGGL((derive_data_kernel<M>), dim3(c->n_tiles), dim3(kBlock), 0, c->stream,
+                           static_cast<const T *>(c->buf.data), static_cast<T *>(c->dd), c->st, c->tile_ds, c->which,
+                           c->cap);
         LAUNCHCHK(c, "derive_data_kernel");
-        hipLaunchKernelGGL((init_chain_kernel<M>), dim3(blocks_for(c->n)), dim3(kBlock), 0, c->stream,
-                           static_cast<T *>(c->buf.chol), c->buf.acc, c->cfg.s0, c->st);
+        hipLaunchKernelGGL((init_chain_kernel<M>), dim3(c->n_tiles), dim3(kBlock), 0, c->stream,
+                           static_cast<T *>(c->buf.chol), c->buf.acc, c->st, c->tile_ds, c->which, c->cap);
         LAUNCHCHK(c, "init_chain_kernel");
         if (M::kSelection) {
-            const int nq = c->cfg.n_quad;
-            hipLaunchKernelGGL(gauss_legendre_kernel, dim3((nq + 127) / 128), dim3(128), 0, c->stream, c->ref_t,
-                               c->ref_w, nq);
-            LAUNCHCHK(c, "gauss_legendre_kernel");
-            hipLaunchKernelGGL(eps_table_kernel, dim3((nq + 63) / 64), dim3(64), 0, c->stream, c->ref_t, c->ref_w,
-                               c->qx, c->qw, c->qeps, c->st);
+            hipLaunchKernelGGL(eps_table_kernel, dim3((c->nq + 63) / 64, c->n_slots), dim3(64), 0, c->stream, c->ref_t,
+                               c->ref_w, c->qx, c->qw, c->qeps, c->st, c->which);
             LAUNCHCHK(c, "eps_table_kernel");
         }
         return HBM_OK;
@@ -230,15 +282,25 @@ struct Ops {
 
     static hbm_status check_init(CtxImpl *c)
     {
-        hipLaunchKernelGGL((check_init_kernel<M>), dim3(blocks_for(c->n)), dim3(kBlock), 0, c->stream,
-                           static_cast<const T *>(c->buf.chi), static_cast<const T *>(c->dd), c->cs, c->st);
+        hipLaunchKernelGGL((check_init_kernel<M>), dim3(c->n_tiles), dim3(kBlock), 0, c->stream,
+                           static_cast<const T *>(c->buf.chi), static_cast<const T *>(c->dd), c->cs, c->st,
+                           c->tile_ds, c->which, c->cap);
         LAUNCHCHK(c, "check_init_kernel");
+        return HBM_OK;
+    }
+
+    static hbm_status quadrature(CtxImpl *c)
+    {
+        if (!M::kSelection) return HBM_OK;
+        hipLaunchKernelGGL(gauss_legendre_kernel, dim3((c->nq + 127) / 128), dim3(128), 0, c->stream, c->ref_t,
+                           c->ref_w, c->nq);
+        LAUNCHCHK(c, "gauss_legendre_kernel");
         return HBM_OK;
     }
 
     static const Launch *table()
     {
-        static const Launch t{&sweep, &theta, &set_theta, &poplik, &prepare, &check_init};
+        static const Launch t{&sweep, &theta, &set_theta, &poplik, &prepare, &check_init, &quadrature};
         return &t;
     }
 };
@@ -268,35 +330,59 @@ hbm_status usable(CtxImpl *c)
     return HBM_OK;
 }
 
-hbm_status read_state(CtxImpl *c, CycleState *h)
+hbm_status check_slot(CtxImpl *c, int32_t slot, bool need_loaded)
 {
-    HIPCHK(c, hipMemcpyAsync(h, c->cs, sizeof(CycleState), hipMemcpyDeviceToHost, c->stream));
+    if (slot < 0 || slot >= c->n_slots) return fail(c, HBM_EINVAL, "slot out of range");
+    if (need_loaded && !c->slots[slot].loaded) return fail(c, HBM_EINVAL, "slot holds no dataset");
+    return HBM_OK;
+}
+
+hbm_status read_slot(CtxImpl *c, int32_t slot, CycleState *h)
+{
+    HIPCHK(c, hipMemcpyAsync(h, c->cs + slot, sizeof(CycleState), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HBM_OK;
 }
 
-hbm_status clear_flags(CtxImpl *c)
+hbm_status read_all(CtxImpl *c)
 {
-    const int32_t zero = 0;
-    HIPCHK(c, hipMemcpyAsync(reinterpret_cast<char *>(c->cs) + offsetof(CycleState, flags), &zero, sizeof(zero),
+    HIPCHK(c, hipMemcpyAsync(c->h_cs.data(), c->cs, sizeof(CycleState) * c->n_slots, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HBM_OK;
+}
+
+template <typename V>
+hbm_status put_field(CtxImpl *c, int32_t slot, size_t offset, V value)
+{
+    HIPCHK(c, hipMemcpyAsync(reinterpret_cast<char *>(c->cs + slot) + offset, &value, sizeof(V),
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HBM_OK;
 }
 
-// Turns sticky device flags into a status after a synchronising call.
-hbm_status check_flags(CtxImpl *c, const CycleState &h)
+// Turns the sticky device flags of every slot (read into c->h_cs) into a
+// status, and clears them.
+hbm_status check_flags(CtxImpl *c)
 {
-    if (h.flags == 0) return HBM_OK;
+    int32_t all = 0;
     std::string msg;
-    if (h.flags & kFlagNonFiniteState) msg += "non-finite latent log density; ";
-    if (h.flags & kFlagBadZ) msg += "selection normaliser not positive and finite; ";
-    if (h.flags & kFlagTraceFull) msg += "theta trace full; ";
-    if (h.flags & kFlagNoSums) msg += "theta step without a sweep; ";
-    hbm_status st = clear_flags(c);
-    if (st != HBM_OK) return st;
-    if (h.flags & (kFlagNonFiniteState | kFlagBadZ)) return fail(c, HBM_EDOMAIN, msg);
-    if (h.flags & kFlagTraceFull) return fail(c, HBM_ENOSPACE, msg);
+    for (int32_t j = 0; j < c->n_slots; ++j) {
+        const int32_t f = c->h_cs[j].flags;
+        if (f == 0) continue;
+        all |= f;
+        std::string m;
+        if (f & kFlagNonFiniteState) m += "non-finite latent log density; ";
+        if (f & kFlagBadZ) m += "selection normaliser not positive and finite; ";
+        if (f & kFlagTraceFull) m += "theta trace full; ";
+        if (f & kFlagNoSums) m += "theta step without a sweep; ";
+        if (msg.size() < 512) msg += (c->n_slots > 1 ? "slot " + std::to_string(j) + ": " : std::string()) + m;
+        hbm_status s = put_field<int32_t>(c, j, offsetof(CycleState, flags), 0);
+        if (s != HBM_OK) return s;
+    }
+    if (all == 0) return HBM_OK;
+    if (all & (kFlagNonFiniteState | kFlagBadZ)) return fail(c, HBM_EDOMAIN, msg);
+    if (all & kFlagTraceFull) return fail(c, HBM_ENOSPACE, msg);
     return fail(c, HBM_ESTATE, msg);
 }
 
@@ -309,52 +395,71 @@ void release(CtxImpl *c)
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
-    void *ptrs[] = {c->dd, c->partials, c->zout, c->side, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
-                    c->cs, c->st, c->theta_trace};
+    void *ptrs[] = {c->dd, c->partials, c->pout, c->theta_in, c->side, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
+                    c->cs, c->st, c->theta_trace, c->tile_ds, c->which};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    delete c;
+    delete static_cast<hbm_ctx *>(c);
 }
 
-hbm_status validate_config(const hbm_config *cfg, const hbm_buffers *b, const double *theta0, ModelInfo *mi)
+// Checks one dataset's configuration (everything but its placement).
+hbm_status validate_dataset(CtxImpl *c, const hbm_config *cfg, const double *theta0, const ModelInfo &mi)
 {
-    if (!cfg || !b || !theta0) return fail(nullptr, HBM_EINVAL, "config, buffers and theta0 must be non-NULL");
-    if (!model_info(cfg->model, mi)) return fail(nullptr, HBM_EINVAL, "unknown model id");
-    if (cfg->precision != mi->precision)
-        return fail(nullptr, HBM_EINVAL, "precision does not match the model (NN: FP64, LF: FP32)");
+    if (!cfg || !theta0) return fail(c, HBM_EINVAL, "config and theta0 must be non-NULL");
+    if (cfg->precision != mi.precision)
+        return fail(c, HBM_EINVAL, "precision does not match the model (NN: FP64, LF: FP32)");
     if (cfg->n_objects < 1 || cfg->n_objects > (int64_t)INT32_MAX - kBlock)
-        return fail(nullptr, HBM_EINVAL, "n_objects must be in [1, 2^31 - 257]");
-    if (!b->data || !b->chi || !b->chol || !b->acc)
-        return fail(nullptr, HBM_EINVAL, "data, chi, chol and acc buffers must be non-NULL");
+        return fail(c, HBM_EINVAL, "n_objects must be in [1, 2^31 - 257]");
     if (!(cfg->target_accept > 0.0 && cfg->target_accept < 1.0) ||
         !(cfg->theta_target_accept > 0.0 && cfg->theta_target_accept < 1.0))
-        return fail(nullptr, HBM_EINVAL, "target acceptance rates must lie in (0, 1)");
+        return fail(c, HBM_EINVAL, "target acceptance rates must lie in (0, 1)");
     if (!(cfg->eta_exponent > 0.5 && cfg->eta_exponent <= 1.0))
-        return fail(nullptr, HBM_EINVAL, "eta_exponent must lie in (1/2, 1]");
-    if (!(cfg->s0 > 0.0) || !std::isfinite(cfg->s0)) return fail(nullptr, HBM_EINVAL, "s0 must be positive");
-    if (cfg->thin_chi < 0 || cfg->max_cycles < 0) return fail(nullptr, HBM_EINVAL, "thin_chi and max_cycles must be >= 0");
+        return fail(c, HBM_EINVAL, "eta_exponent must lie in (1/2, 1]");
+    if (!(cfg->s0 > 0.0) || !std::isfinite(cfg->s0)) return fail(c, HBM_EINVAL, "s0 must be positive");
+    if (cfg->thin_chi < 0 || cfg->max_cycles < 0) return fail(c, HBM_EINVAL, "thin_chi and max_cycles must be >= 0");
     if (has_selection(cfg->model)) {
-        if (cfg->n_quad < 16 || cfg->n_quad > 4096) return fail(nullptr, HBM_EINVAL, "n_quad must be in [16, 4096]");
         const double *mc = cfg->model_consts;
         if (!(mc[0] > 0.0) || !(mc[1] > 0.0) || !(mc[2] > 0.0) || !std::isfinite(mc[3]))
-            return fail(nullptr, HBM_EINVAL, "LF model constants need F_th, sigma_F, rmax > 0 and a finite ln L0");
+            return fail(c, HBM_EINVAL, "LF model constants need F_th, sigma_F, rmax > 0 and a finite ln L0");
         if (cfg->model == HBM_GAMMA_LF_COLOR_3D && (!(mc[4] > 0.0) || !(mc[5] > 0.0)))
-            return fail(nullptr, HBM_EINVAL, "LF colour model needs f_r > 0 and sigma_c > 0");
+            return fail(c, HBM_EINVAL, "LF colour model needs f_r > 0 and sigma_c > 0");
     }
     if (cfg->model == HBM_NORMAL_NORMAL_3D) {
         const double *mc = cfg->model_consts;
         const double a = mc[0], b2 = mc[1], c2 = mc[2], d2 = mc[3], e2 = mc[4], f2 = mc[5];
         const double det = a * (c2 * f2 - e2 * e2) - b2 * (b2 * f2 - e2 * d2) + d2 * (b2 * e2 - c2 * d2);
         if (!(a > 0.0) || !(a * c2 - b2 * b2 > 0.0) || !(det > 0.0) || !(mc[6] > 0) || !(mc[7] > 0) || !(mc[8] > 0))
-            return fail(nullptr, HBM_EINVAL, "C_pop must be positive definite and sigma_j > 0");
+            return fail(c, HBM_EINVAL, "C_pop must be positive definite and sigma_j > 0");
     }
-    for (int r = 0; r < mi->p; ++r) {
-        if (!std::isfinite(theta0[r])) return fail(nullptr, HBM_EINVAL, "theta0 must be finite");
-        if (!(cfg->theta_chol0[r * mi->p + r] > 0.0))
-            return fail(nullptr, HBM_EINVAL, "theta_chol0 must have a positive diagonal");
+    for (int r = 0; r < mi.p; ++r) {
+        if (!std::isfinite(theta0[r])) return fail(c, HBM_EINVAL, "theta0 must be finite");
+        if (!(cfg->theta_chol0[r * mi.p + r] > 0.0))
+            return fail(c, HBM_EINVAL, "theta_chol0 must have a positive diagonal");
         for (int q = 0; q <= r; ++q)
-            if (!std::isfinite(cfg->theta_chol0[r * mi->p + q])) return fail(nullptr, HBM_EINVAL, "theta_chol0 not finite");
+            if (!std::isfinite(cfg->theta_chol0[r * mi.p + q])) return fail(c, HBM_EINVAL, "theta_chol0 not finite");
     }
+    return HBM_OK;
+}
+
+hbm_status validate_pool(const hbm_pool_config *pool, const hbm_buffers *b, ModelInfo *mi)
+{
+    if (!pool || !b) return fail(nullptr, HBM_EINVAL, "pool config and buffers must be non-NULL");
+    if (!model_info(pool->model, mi)) return fail(nullptr, HBM_EINVAL, "unknown model id");
+    if (pool->precision != mi->precision)
+        return fail(nullptr, HBM_EINVAL, "precision does not match the model (NN: FP64, LF: FP32)");
+    if (pool->n_slots < 1 || pool->n_slots > 65535) return fail(nullptr, HBM_EINVAL, "n_slots must be in [1, 65535]");
+    if (pool->capacity < 1 || pool->capacity > (int64_t)INT32_MAX - kBlock)
+        return fail(nullptr, HBM_EINVAL, "capacity must be in [1, 2^31 - 257]");
+    if (pool->max_cycles < 0 || pool->snap_rows < 0) return fail(nullptr, HBM_EINVAL, "max_cycles and snap_rows >= 0");
+    if (has_selection(pool->model) && (pool->n_quad < 16 || pool->n_quad > 4096))
+        return fail(nullptr, HBM_EINVAL, "n_quad must be in [16, 4096]");
+    if (!b->data || !b->chi || !b->chol || !b->acc)
+        return fail(nullptr, HBM_EINVAL, "data, chi, chol and acc buffers must be non-NULL");
+    if (pool->tiles_per_group != 0 && pool->tiles_per_group != 1 && pool->tiles_per_group != 2 &&
+        pool->tiles_per_group != 4)
+        return fail(nullptr, HBM_EINVAL, "tiles_per_group must be 0 (default), 1, 2 or 4");
+    if (pool->snap_rows > 0 && !b->chi_samples)
+        return fail(nullptr, HBM_EINVAL, "snap_rows > 0 needs a chi_samples buffer");
     return HBM_OK;
 }
 
@@ -380,24 +485,14 @@ hbm_status drain_timing(CtxImpl *c)
     return HBM_OK;
 }
 
-}  // namespace
-
-struct hbm_ctx : CtxImpl {};
-
-extern "C" {
-
-hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, const double *chi0_host,
-                       const double *theta0, void *hip_stream, hbm_ctx **out)
+hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, void *hip_stream, CtxImpl **out)
 {
-    if (!out) return fail(nullptr, HBM_EINVAL, "out must be non-NULL");
-    *out = nullptr;
     ModelInfo mi;
-    hbm_status s = validate_config(config, buffers, theta0, &mi);
+    hbm_status s = validate_pool(pool, buffers, &mi);
     if (s != HBM_OK) return s;
-
     CtxImpl *c = new (std::nothrow) hbm_ctx();
     if (!c) return fail(nullptr, HBM_ENOMEM, "host allocation failed");
-    c->cfg = *config;
+    c->pool = *pool;
     c->buf = *buffers;
     c->d = mi.d;
     c->p = mi.p;
@@ -405,12 +500,17 @@ hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, con
     c->md = mi.md;
     c->nc = mi.d * (mi.d + 1) / 2;
     c->esize = mi.precision == HBM_FP64 ? 8 : 4;
-    c->n = config->n_objects;
-    c->n_tiles = blocks_for(c->n);
+    c->cap = pool->capacity;
+    c->n_tiles = tiles_for(c->cap);
+    c->n_slots = pool->n_slots;
+    c->nq = has_selection(pool->model) ? pool->n_quad : 1;
+    c->tpw = pool->tiles_per_group > 0 ? pool->tiles_per_group : 1;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->ops = mi.ops;
-    c->trace_cap = config->max_cycles;
-    c->snap_cap = (config->thin_chi > 0 && buffers->chi_samples) ? config->max_cycles / config->thin_chi : 0;
+    c->slots.assign(c->n_slots, Slot{});
+    c->h_tile_ds.assign(c->n_tiles, -1);
+    c->h_which.assign(c->n_slots, 0);
+    c->h_cs.resize(c->n_slots);
 
     auto bail = [&](hbm_status code) {
         g_init_error = c->err;
@@ -425,80 +525,337 @@ hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, con
         }
         return HBM_OK;
     };
-    const bool sel = has_selection(config->model);
-    const int nq = sel ? config->n_quad : 1;
-    if ((s = alloc(&c->dd, c->esize * c->md * c->n)) != HBM_OK ||
+    const size_t ns = static_cast<size_t>(c->n_slots), nq = static_cast<size_t>(c->nq);
+    if ((s = alloc(&c->dd, c->esize * c->md * c->cap)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->partials), sizeof(double) * 3 * c->n_tiles)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->zout), sizeof(double) * 2)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->side), sizeof(Precomp))) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->pout), sizeof(double) * 2 * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->theta_in), sizeof(double) * c->p * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->side), sizeof(Precomp) * ns)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->ref_t), sizeof(double) * nq)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->ref_w), sizeof(double) * nq)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->qx), sizeof(double) * nq)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->qw), sizeof(double) * nq)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->qeps), sizeof(double) * nq)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->cs), sizeof(CycleState))) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->st), sizeof(Statics))) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->theta_trace), sizeof(double) * c->p * c->trace_cap)) != HBM_OK)
+        (s = alloc(reinterpret_cast<void **>(&c->qx), sizeof(double) * nq * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->qw), sizeof(double) * nq * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->qeps), sizeof(double) * nq * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->cs), sizeof(CycleState) * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->st), sizeof(Statics) * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->theta_trace),
+                   sizeof(double) * c->p * static_cast<size_t>(pool->max_cycles) * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->tile_ds), sizeof(int32_t) * c->n_tiles)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->which), sizeof(int32_t) * ns)) != HBM_OK)
         return bail(s);
-
-    Statics hs;
-    std::memset(&hs, 0, sizeof(hs));
-    hs.n = c->n;
-    hs.trace_cap = c->trace_cap;
-    hs.snap_cap = c->snap_cap;
-    hs.thin = config->thin_chi;
-    hs.nq = nq;
-    hs.adapt_theta = config->adapt_theta;
-    hs.p = c->p;
-    hs.key0 = static_cast<uint32_t>(config->seed & 0xffffffffu);
-    hs.key1 = static_cast<uint32_t>(config->seed >> 32);
-    hs.gamma = config->eta_exponent;
-    hs.alpha_star = config->target_accept;
-    hs.alpha_star_theta = config->theta_target_accept;
-    std::memcpy(hs.mc, config->model_consts, sizeof(hs.mc));
-
-    CycleState hc;
-    std::memset(&hc, 0, sizeof(hc));
-    for (int r = 0; r < c->p; ++r) {
-        hc.theta[r] = theta0[r];
-        for (int q = 0; q < c->p; ++q) hc.chol_theta[r * c->p + q] = q <= r ? config->theta_chol0[r * c->p + q] : 0.0;
-    }
-    hc.first_bad = INT32_MAX;
-
+    // every slot starts empty: zero statics (n = 0) and inactive states
+    std::vector<Statics> hs(ns);
+    std::memset(hs.data(), 0, sizeof(Statics) * ns);
+    std::memset(c->h_cs.data(), 0, sizeof(CycleState) * ns);
     hipError_t e;
-    if ((e = hipMemcpyAsync(c->st, &hs, sizeof(hs), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(c->cs, &hc, sizeof(hc), hipMemcpyHostToDevice, c->stream)) != hipSuccess) {
-        hip_fail(c, e, "init copies");
+    if ((e = hipMemcpyAsync(c->st, hs.data(), sizeof(Statics) * ns, hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(c->cs, c->h_cs.data(), sizeof(CycleState) * ns, hipMemcpyHostToDevice, c->stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(c->tile_ds, c->h_tile_ds.data(), sizeof(int32_t) * c->n_tiles, hipMemcpyHostToDevice,
+                            c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+        hip_fail(c, e, "pool initialisation copies");
         return bail(HBM_EHIP);
     }
+    if ((s = c->ops->quadrature(c)) != HBM_OK) return bail(s);
+    *out = c;
+    return HBM_OK;
+}
+
+// Loads datasets into free slots (the body of load_datasets).
+hbm_status load(CtxImpl *c, int32_t count, const int32_t *slots, const int64_t *obj_start, const hbm_config *configs,
+                const double *theta0, const int64_t *budgets)
+{
+    if (count < 1 || !slots || !obj_start || !configs || !theta0)
+        return fail(c, HBM_EINVAL, "count >= 1 and non-NULL slots, obj_start, configs and theta0");
+    ModelInfo mi;
+    model_info(c->pool.model, &mi);
+    std::vector<int32_t> owner(c->h_tile_ds);
+    for (int32_t q = 0; q < count; ++q) {
+        const hbm_config *cfg = configs + q;
+        const int32_t j = slots[q];
+        const std::string who = count > 1 ? "dataset " + std::to_string(q) + ": " : std::string();
+        hbm_status s = check_slot(c, j, false);
+        if (s != HBM_OK) return s;
+        if (c->slots[j].loaded) return fail(c, HBM_EINVAL, who + "slot already holds a dataset");
+        if (cfg->model != c->pool.model) return fail(c, HBM_EINVAL, who + "model differs from the pool's");
+        if ((s = validate_dataset(c, cfg, theta0 + static_cast<size_t>(q) * c->p, mi)) != HBM_OK) {
+            c->err = who + c->err;
+            return s;
+        }
+        if (has_selection(cfg->model) && cfg->n_quad != c->pool.n_quad)
+            return fail(c, HBM_EINVAL, who + "n_quad differs from the pool's");
+        if (cfg->max_cycles > c->pool.max_cycles) return fail(c, HBM_EINVAL, who + "max_cycles exceeds the pool's");
+        const int64_t b = budgets ? budgets[q] : 0;
+        if (b < 0 || b > cfg->max_cycles) return fail(c, HBM_EINVAL, who + "budget must be in [0, max_cycles]");
+        const int64_t o = obj_start[q];
+        if (o < 0 || o % kBlock != 0 || o + cfg->n_objects > c->cap)
+            return fail(c, HBM_EINVAL, who + "obj_start must be a multiple of 256 with obj_start + n <= capacity");
+        const int32_t t0 = static_cast<int32_t>(o / kBlock), nt = tiles_for(cfg->n_objects);
+        for (int32_t t = t0; t < t0 + nt; ++t) {
+            if (owner[t] >= 0) return fail(c, HBM_EINVAL, who + "object range overlaps another dataset");
+            owner[t] = j;
+        }
+        for (int32_t r = 0; r < q; ++r)
+            if (slots[r] == j) return fail(c, HBM_EINVAL, who + "slot listed twice");
+    }
+
+    // statics and states of the new slots
+    std::vector<Statics> hs(count);
+    std::vector<CycleState> hc(count);
+    std::memset(hs.data(), 0, sizeof(Statics) * count);
+    std::memset(hc.data(), 0, sizeof(CycleState) * count);
+    std::fill(c->h_which.begin(), c->h_which.end(), 0);
+    for (int32_t q = 0; q < count; ++q) {
+        const hbm_config *cfg = configs + q;
+        const int64_t o = obj_start[q];
+        Statics &s = hs[q];
+        s.n = cfg->n_objects;
+        s.obj_start = o;
+        s.tile_start = static_cast<int32_t>(o / kBlock);
+        s.n_tiles = tiles_for(cfg->n_objects);
+        s.trace_cap = cfg->max_cycles;
+        s.snap_cap = 0;
+        if (cfg->thin_chi > 0 && c->buf.chi_samples) {
+            const int64_t want = cfg->max_cycles / cfg->thin_chi;
+            s.snap_cap = want < c->pool.snap_rows ? want : c->pool.snap_rows;
+        }
+        s.thin = cfg->thin_chi;
+        s.nq = c->nq;
+        s.adapt_theta = cfg->adapt_theta;
+        s.p = c->p;
+        s.key0 = static_cast<uint32_t>(cfg->seed & 0xffffffffu);
+        s.key1 = static_cast<uint32_t>(cfg->seed >> 32);
+        s.gamma = cfg->eta_exponent;
+        s.alpha_star = cfg->target_accept;
+        s.alpha_star_theta = cfg->theta_target_accept;
+        s.s0 = cfg->s0;
+        std::memcpy(s.mc, cfg->model_consts, sizeof(s.mc));
+        CycleState &h = hc[q];
+        const double *t0 = theta0 + static_cast<size_t>(q) * c->p;
+        for (int r = 0; r < c->p; ++r) {
+            h.theta[r] = t0[r];
+            for (int qq = 0; qq < c->p; ++qq)
+                h.chol_theta[r * c->p + qq] = qq <= r ? cfg->theta_chol0[r * c->p + qq] : 0.0;
+        }
+        h.first_bad = INT32_MAX;
+        h.budget = budgets ? budgets[q] : 0;
+        h.active = 1;
+        c->h_which[slots[q]] = 1;
+    }
+    for (int32_t q = 0; q < count; ++q) {
+        HIPCHK(c, hipMemcpyAsync(c->st + slots[q], &hs[q], sizeof(Statics), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->cs + slots[q], &hc[q], sizeof(CycleState), hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->tile_ds, owner.data(), sizeof(int32_t) * c->n_tiles, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->which, c->h_which.data(), sizeof(int32_t) * c->n_slots, hipMemcpyHostToDevice,
+                             c->stream));
+    hbm_status s;
+    if ((s = c->ops->prepare(c)) != HBM_OK) return s;
+    if ((s = c->ops->set_theta(c)) != HBM_OK) return s;
+    if ((s = c->ops->check_init(c)) != HBM_OK) return s;
+    if ((s = read_all(c)) != HBM_OK) return s;
+
+    // the first failing dataset, if any, fails the whole call
+    std::string msg;
+    for (int32_t q = 0; q < count && msg.empty(); ++q) {
+        const CycleState &b = c->h_cs[slots[q]];
+        const std::string who = count > 1 ? "dataset " + std::to_string(q) + ": " : std::string();
+        if (!(b.lprior_cur > -HUGE_VAL)) msg = who + "theta0 is outside the prior support";
+        else if (b.flags & kFlagBadZ) msg = who + "selection normaliser Z(theta0) is not positive and finite";
+        else if (b.flags & kFlagNonFiniteState)
+            msg = who + "non-finite initial log density at object " + std::to_string(b.first_bad);
+    }
+    if (!msg.empty()) {
+        // leave the failed slots empty again
+        std::vector<CycleState> zero(1);
+        std::memset(zero.data(), 0, sizeof(CycleState));
+        Statics zs;
+        std::memset(&zs, 0, sizeof(zs));
+        for (int32_t q = 0; q < count; ++q) {
+            HIPCHK(c, hipMemcpyAsync(c->cs + slots[q], zero.data(), sizeof(CycleState), hipMemcpyHostToDevice,
+                                     c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->st + slots[q], &zs, sizeof(Statics), hipMemcpyHostToDevice, c->stream));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->tile_ds, c->h_tile_ds.data(), sizeof(int32_t) * c->n_tiles,
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return fail(c, HBM_EDOMAIN, msg);
+    }
+    c->h_tile_ds.swap(owner);
+    for (int32_t q = 0; q < count; ++q) {
+        Slot &sl = c->slots[slots[q]];
+        sl = Slot{};
+        sl.loaded = sl.active = true;
+        sl.n = hs[q].n;
+        sl.obj_start = hs[q].obj_start;
+        sl.tile_start = hs[q].tile_start;
+        sl.n_tiles = hs[q].n_tiles;
+        sl.budget = hc[q].budget;
+        sl.trace_cap = hs[q].trace_cap;
+        sl.snap_cap = hs[q].snap_cap;
+        sl.thin = hs[q].thin;
+    }
+    return HBM_OK;
+}
+
+// Theta steps a slot takes in n more full cycles.
+int64_t cycles_taken(const Slot &s, int64_t n)
+{
+    if (!s.active) return 0;
+    if (s.budget > 0 && s.n_theta + n > s.budget) return s.budget - s.n_theta;
+    return n;
+}
+
+void after_theta_steps(Slot &s, int64_t n)
+{
+    s.k += n;
+    s.n_theta += n;
+    if (s.budget > 0 && s.n_theta >= s.budget) s.active = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+hbm_status create_pool(const hbm_pool_config *pool, const hbm_buffers *buffers, void *hip_stream, hbm_ctx **out)
+{
+    if (!out) return fail(nullptr, HBM_EINVAL, "out must be non-NULL");
+    *out = nullptr;
+    CtxImpl *c = nullptr;
+    hbm_status s = create_ctx(pool, buffers, hip_stream, &c);
+    if (s == HBM_OK) *out = static_cast<hbm_ctx *>(c);
+    return s;
+}
+
+hbm_status load_datasets(hbm_ctx *ctx, int32_t count, const int32_t *slots, const int64_t *obj_start,
+                         const hbm_config *configs, const double *theta0, const int64_t *budgets)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) { return load(c, count, slots, obj_start, configs, theta0, budgets); });
+}
+
+hbm_status unload_dataset(hbm_ctx *ctx, int32_t slot)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        hbm_status s = check_slot(c, slot, true);
+        if (s != HBM_OK) return s;
+        Slot &sl = c->slots[slot];
+        for (int32_t t = sl.tile_start; t < sl.tile_start + sl.n_tiles; ++t) c->h_tile_ds[t] = -1;
+        HIPCHK(c, hipMemcpyAsync(c->tile_ds + sl.tile_start, c->h_tile_ds.data() + sl.tile_start,
+                                 sizeof(int32_t) * sl.n_tiles, hipMemcpyHostToDevice, c->stream));
+        const int64_t zero_n = 0;
+        HIPCHK(c, hipMemcpyAsync(reinterpret_cast<char *>(c->st + slot) + offsetof(Statics, n), &zero_n,
+                                 sizeof(zero_n), hipMemcpyHostToDevice, c->stream));
+        if ((s = put_field<int32_t>(c, slot, offsetof(CycleState, active), 0)) != HBM_OK) return s;
+        sl = Slot{};
+        return HBM_OK;
+    });
+}
+
+hbm_status slot_info(hbm_ctx *ctx, int32_t slot, int64_t out[6])
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (!out) return fail(c, HBM_EINVAL, "out must be non-NULL");
+        hbm_status s = check_slot(c, slot, false);
+        if (s != HBM_OK) return s;
+        const Slot &sl = c->slots[slot];
+        out[0] = sl.loaded;
+        out[1] = sl.active;
+        out[2] = sl.k;
+        out[3] = sl.n_theta;
+        out[4] = sl.obj_start;
+        out[5] = sl.n;
+        return HBM_OK;
+    });
+}
+
+hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, const double *chi0_host,
+                       const double *theta0, void *hip_stream, hbm_ctx **out)
+{
+    if (!out) return fail(nullptr, HBM_EINVAL, "out must be non-NULL");
+    *out = nullptr;
+    if (!config || !buffers || !theta0) return fail(nullptr, HBM_EINVAL, "config, buffers and theta0 must be non-NULL");
+    hbm_pool_config pool;
+    std::memset(&pool, 0, sizeof(pool));
+    pool.model = config->model;
+    pool.precision = config->precision;
+    pool.n_slots = 1;
+    pool.n_quad = config->n_quad;
+    pool.capacity = config->n_objects;
+    pool.max_cycles = config->max_cycles;
+    pool.snap_rows = (config->thin_chi > 0 && buffers->chi_samples) ? config->max_cycles / config->thin_chi : 0;
+    pool.tiles_per_group = config->tiles_per_group;
+    // dataset checks first, so a bad dataset reports its own reason
+    ModelInfo mi;
+    if (!model_info(config->model, &mi)) return fail(nullptr, HBM_EINVAL, "unknown model id");
+    hbm_status s = validate_dataset(nullptr, config, theta0, mi);
+    if (s != HBM_OK) return s;
+    if (has_selection(config->model) && (config->n_quad < 16 || config->n_quad > 4096))
+        return fail(nullptr, HBM_EINVAL, "n_quad must be in [16, 4096]");
+    CtxImpl *c = nullptr;
+    if ((s = create_ctx(&pool, buffers, hip_stream, &c)) != HBM_OK) return s;
     if (chi0_host) {
-        std::vector<char> tmp(c->esize * c->d * c->n);
-        for (int64_t j = 0; j < c->d * c->n; ++j) {
+        std::vector<char> tmp(c->esize * c->d * c->cap);
+        for (int64_t j = 0; j < c->d * c->cap; ++j) {
             if (c->esize == 4) reinterpret_cast<float *>(tmp.data())[j] = static_cast<float>(chi0_host[j]);
             else reinterpret_cast<double *>(tmp.data())[j] = chi0_host[j];
         }
+        hipError_t e;
         if ((e = hipMemcpyAsync(c->buf.chi, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
             (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
             hip_fail(c, e, "chi0 copy");
-            return bail(HBM_EHIP);
+            g_init_error = c->err;
+            release(c);
+            return HBM_EHIP;
         }
     }
-    if ((s = c->ops->prepare(c)) != HBM_OK) return bail(s);
-    if ((s = c->ops->set_theta(c)) != HBM_OK) return bail(s);
-    if ((s = c->ops->check_init(c)) != HBM_OK) return bail(s);
-    CycleState back;
-    if ((s = read_state(c, &back)) != HBM_OK) return bail(s);
-    if (!(back.lprior_cur > -HUGE_VAL)) {
-        c->err = "theta0 is outside the prior support";
-        return bail(HBM_EDOMAIN);
+    const int32_t slot = 0;
+    const int64_t o = 0;
+    if ((s = load(c, 1, &slot, &o, config, theta0, nullptr)) != HBM_OK) {
+        g_init_error = c->err;
+        release(c);
+        return s;
     }
-    if (back.flags & kFlagBadZ) {
-        c->err = "selection normaliser Z(theta0) is not positive and finite";
-        return bail(HBM_EDOMAIN);
+    *out = static_cast<hbm_ctx *>(c);
+    return HBM_OK;
+}
+
+hbm_status init_batch(int32_t n_datasets, const hbm_config *configs, const hbm_buffers *buffers, const double *theta0,
+                      void *hip_stream, hbm_ctx **out)
+{
+    if (!out) return fail(nullptr, HBM_EINVAL, "out must be non-NULL");
+    *out = nullptr;
+    if (n_datasets < 1 || n_datasets > 65535 || !configs || !buffers || !theta0)
+        return fail(nullptr, HBM_EINVAL, "1 <= n_datasets <= 65535 and non-NULL configs, buffers, theta0");
+    std::vector<int32_t> slots(n_datasets);
+    std::vector<int64_t> starts(n_datasets);
+    hbm_pool_config pool;
+    std::memset(&pool, 0, sizeof(pool));
+    pool.model = configs[0].model;
+    pool.precision = configs[0].precision;
+    pool.n_slots = n_datasets;
+    pool.n_quad = configs[0].n_quad;
+    pool.tiles_per_group = configs[0].tiles_per_group;
+    int64_t o = 0;
+    for (int32_t q = 0; q < n_datasets; ++q) {
+        const hbm_config &cf = configs[q];
+        if (cf.n_objects < 1 || cf.n_objects > (int64_t)INT32_MAX - kBlock)
+            return fail(nullptr, HBM_EINVAL, "n_objects must be in [1, 2^31 - 257]");
+        slots[q] = q;
+        starts[q] = o;
+        pool.capacity = o + cf.n_objects;
+        o += static_cast<int64_t>(tiles_for(cf.n_objects)) * kBlock;
+        if (cf.max_cycles > pool.max_cycles) pool.max_cycles = cf.max_cycles;
+        if (cf.thin_chi > 0 && buffers->chi_samples && cf.max_cycles / cf.thin_chi > pool.snap_rows)
+            pool.snap_rows = cf.max_cycles / cf.thin_chi;
     }
-    if (back.flags & kFlagNonFiniteState) {
-        c->err = "non-finite initial log density at object " + std::to_string(back.first_bad);
-        return bail(HBM_EDOMAIN);
+    CtxImpl *c = nullptr;
+    hbm_status s = create_ctx(&pool, buffers, hip_stream, &c);
+    if (s != HBM_OK) return s;
+    if ((s = load(c, n_datasets, slots.data(), starts.data(), configs, theta0, nullptr)) != HBM_OK) {
+        g_init_error = c->err;
+        release(c);
+        return s;
     }
     *out = static_cast<hbm_ctx *>(c);
     return HBM_OK;
@@ -511,15 +868,19 @@ hbm_status ram_sweep(hbm_ctx *ctx, int32_t n_sweeps, double *out_accept_rate)
         for (int32_t s = 0; s < n_sweeps; ++s) {
             hbm_status st = c->ops->sweep(c, false, nullptr);
             if (st != HBM_OK) return st;
-            c->k += 1;
-            c->sums_ready = true;
+            for (Slot &sl : c->slots)
+                if (sl.active) {
+                    sl.k += 1;
+                    sl.sums_ready = true;
+                }
         }
         if (out_accept_rate) {
-            CycleState h;
-            hbm_status st = read_state(c, &h);
+            hbm_status st = read_all(c);
             if (st != HBM_OK) return st;
-            *out_accept_rate = h.n_acc_last / static_cast<double>(c->n);
-            return check_flags(c, h);
+            for (int32_t j = 0; j < c->n_slots; ++j)
+                out_accept_rate[j] = c->slots[j].active ? c->h_cs[j].n_acc_last / static_cast<double>(c->slots[j].n)
+                                                        : static_cast<double>(NAN);
+            return check_flags(c);
         }
         return HBM_OK;
     });
@@ -529,13 +890,22 @@ hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
         if (!theta || !out) return fail(c, HBM_EINVAL, "theta and out must be non-NULL");
-        for (int r = 0; r < c->p; ++r)
-            if (!std::isfinite(theta[r])) return fail(c, HBM_EINVAL, "theta must be finite");
-        hbm_status st = c->ops->poplik(c, theta);
+        std::vector<double> th(static_cast<size_t>(c->n_slots) * c->p, 0.0);
+        for (int32_t j = 0; j < c->n_slots; ++j) {
+            if (!c->slots[j].loaded) continue;
+            for (int r = 0; r < c->p; ++r) {
+                const double v = theta[static_cast<size_t>(j) * c->p + r];
+                if (!std::isfinite(v)) return fail(c, HBM_EINVAL, "theta must be finite");
+                th[static_cast<size_t>(j) * c->p + r] = v;
+            }
+        }
+        HIPCHK(c, hipMemcpyAsync(c->theta_in, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, c->stream));
+        hbm_status st = c->ops->poplik(c);
         if (st != HBM_OK) return st;
-        CycleState h;
-        if ((st = read_state(c, &h)) != HBM_OK) return st;
-        *out = h.poplik_out;
+        std::vector<double> po(2 * static_cast<size_t>(c->n_slots));
+        HIPCHK(c, hipMemcpyAsync(po.data(), c->pout, sizeof(double) * po.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int32_t j = 0; j < c->n_slots; ++j) out[j] = c->slots[j].loaded ? po[2 * j + 1] : static_cast<double>(NAN);
         return HBM_OK;
     });
 }
@@ -543,16 +913,26 @@ hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out)
 hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
-        if (!c->sums_ready) return fail(c, HBM_ESTATE, "theta_step needs a ram_sweep since the last theta step");
-        if (c->n_theta >= c->trace_cap) return fail(c, HBM_ENOSPACE, "theta trace full (max_cycles)");
+        for (const Slot &sl : c->slots) {
+            if (!sl.active) continue;
+            if (!sl.sums_ready) return fail(c, HBM_ESTATE, "theta_step needs a ram_sweep since the last theta step");
+            if (sl.n_theta >= sl.trace_cap) return fail(c, HBM_ENOSPACE, "theta trace full (max_cycles)");
+        }
         hbm_status st = c->ops->theta(c);
         if (st != HBM_OK) return st;
-        c->sums_ready = false;
-        c->n_theta += 1;
-        CycleState h;
-        if ((st = read_state(c, &h)) != HBM_OK) return st;
-        if (out_accepted) *out_accepted = h.accepted_last;
-        return check_flags(c, h);
+        std::vector<char> stepped(c->n_slots, 0);
+        for (int32_t j = 0; j < c->n_slots; ++j) {
+            Slot &sl = c->slots[j];
+            if (!sl.active) continue;
+            stepped[j] = 1;
+            sl.sums_ready = false;
+            sl.n_theta += 1;
+            if (sl.budget > 0 && sl.n_theta >= sl.budget) sl.active = false;
+        }
+        if ((st = read_all(c)) != HBM_OK) return st;
+        if (out_accepted)
+            for (int32_t j = 0; j < c->n_slots; ++j) out_accepted[j] = stepped[j] ? c->h_cs[j].accepted_last : -1;
+        return check_flags(c);
     });
 }
 
@@ -560,8 +940,12 @@ hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
         if (n_cycles < 0) return fail(c, HBM_EINVAL, "n_cycles must be >= 0");
-        if (c->n_theta + n_cycles > c->trace_cap) return fail(c, HBM_ENOSPACE, "theta trace would overflow (max_cycles)");
-        if (c->sums_ready) return fail(c, HBM_ESTATE, "a ram_sweep is waiting for its theta_step");
+        for (const Slot &sl : c->slots) {
+            if (!sl.active) continue;
+            if (sl.sums_ready) return fail(c, HBM_ESTATE, "a ram_sweep is waiting for its theta_step");
+            if (sl.n_theta + cycles_taken(sl, n_cycles) > sl.trace_cap)
+                return fail(c, HBM_ENOSPACE, "theta trace would overflow (max_cycles)");
+        }
         int64_t left = n_cycles;
         if (use_graph && !c->timing && n_cycles > 0) {
             const int64_t glen = 32;
@@ -591,46 +975,54 @@ hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph)
             hbm_status st = c->ops->sweep(c, true, nullptr);
             if (st != HBM_OK) return st;
         }
-        c->k += n_cycles;
-        c->n_theta += n_cycles;
+        for (Slot &sl : c->slots) after_theta_steps(sl, cycles_taken(sl, n_cycles));
         return HBM_OK;
     });
 }
 
-hbm_status get_samples(hbm_ctx *ctx, int64_t first, int64_t count, double *theta_out, void *chi_out,
+hbm_status get_samples(hbm_ctx *ctx, int32_t slot, int64_t first, int64_t count, double *theta_out, void *chi_out,
                        int64_t *n_written)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        hbm_status s = check_slot(c, slot, true);
+        if (s != HBM_OK) return s;
         if (first < 0 || count < 0) return fail(c, HBM_EINVAL, "first and count must be >= 0");
+        const Slot &sl = c->slots[slot];
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (!theta_out && !chi_out) {
-            if (n_written) *n_written = c->n_theta;
+            if (n_written) *n_written = sl.n_theta;
             return HBM_OK;
         }
         if (theta_out) {
-            if (first + count > c->n_theta) return fail(c, HBM_EINVAL, "theta rows requested beyond the trace");
-            HIPCHK(c, hipMemcpy(theta_out, c->theta_trace + first * c->p, sizeof(double) * c->p * count,
-                                hipMemcpyDeviceToHost));
+            if (first + count > sl.n_theta) return fail(c, HBM_EINVAL, "theta rows requested beyond the trace");
+            const double *src = c->theta_trace + (static_cast<size_t>(slot) * c->pool.max_cycles + first) * c->p;
+            HIPCHK(c, hipMemcpy(theta_out, src, sizeof(double) * c->p * count, hipMemcpyDeviceToHost));
         }
         if (chi_out) {
-            const int64_t taken = c->cfg.thin_chi > 0 ? c->k / c->cfg.thin_chi : 0;
-            const int64_t have = taken < c->snap_cap ? taken : c->snap_cap;
+            const int64_t taken = sl.thin > 0 ? sl.k / sl.thin : 0;
+            const int64_t have = taken < sl.snap_cap ? taken : sl.snap_cap;
             if (first + count > have) return fail(c, HBM_EINVAL, "latent snapshots requested beyond those taken");
-            const size_t row = c->esize * c->d * c->n;
-            HIPCHK(c, hipMemcpy(chi_out, static_cast<char *>(c->buf.chi_samples) + row * first, row * count,
-                                hipMemcpyDeviceToHost));
+            if (count > 0) {
+                // rows (snapshot, component) of the slot's object range
+                const size_t w = c->esize * sl.n, pitch = c->esize * c->cap;
+                const char *src = static_cast<const char *>(c->buf.chi_samples) +
+                                  pitch * static_cast<size_t>(first * c->d) + c->esize * sl.obj_start;
+                HIPCHK(c, hipMemcpy2D(chi_out, w, src, pitch, w, static_cast<size_t>(count * c->d),
+                                      hipMemcpyDeviceToHost));
+            }
         }
         if (n_written) *n_written = count;
         return HBM_OK;
     });
 }
 
-hbm_status get_theta(hbm_ctx *ctx, double *theta, double *chol_theta, int64_t *k)
+hbm_status get_theta(hbm_ctx *ctx, int32_t slot, double *theta, double *chol_theta, int64_t *k)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
-        CycleState h;
-        hbm_status st = read_state(c, &h);
+        hbm_status st = check_slot(c, slot, true);
         if (st != HBM_OK) return st;
+        CycleState &h = c->h_cs[slot];
+        if ((st = read_slot(c, slot, &h)) != HBM_OK) return st;
         if (theta) std::memcpy(theta, h.theta, sizeof(double) * c->p);
         if (chol_theta) std::memcpy(chol_theta, h.chol_theta, sizeof(double) * c->p * c->p);
         if (k) *k = h.k;
@@ -638,34 +1030,39 @@ hbm_status get_theta(hbm_ctx *ctx, double *theta, double *chol_theta, int64_t *k
     });
 }
 
-hbm_status set_theta(hbm_ctx *ctx, const double *theta, const double *chol_theta, int64_t k)
+hbm_status set_theta(hbm_ctx *ctx, int32_t slot, const double *theta, const double *chol_theta, int64_t k)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        hbm_status st = check_slot(c, slot, true);
+        if (st != HBM_OK) return st;
         if (!theta || !chol_theta || k < 0) return fail(c, HBM_EINVAL, "theta, chol_theta non-NULL and k >= 0");
         for (int r = 0; r < c->p; ++r) {
             if (!std::isfinite(theta[r]) || !(chol_theta[r * c->p + r] > 0.0))
                 return fail(c, HBM_EINVAL, "theta finite and chol_theta with a positive diagonal");
         }
         CycleState h;
-        hbm_status st = read_state(c, &h);
-        if (st != HBM_OK) return st;
-        CycleState keep = h;
+        if ((st = read_slot(c, slot, &h)) != HBM_OK) return st;
+        const CycleState keep = h;
         for (int r = 0; r < c->p; ++r) {
             h.theta[r] = theta[r];
             for (int q = 0; q < c->p; ++q) h.chol_theta[r * c->p + q] = q <= r ? chol_theta[r * c->p + q] : 0.0;
         }
         h.k = k;
-        HIPCHK(c, hipMemcpyAsync(c->cs, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+        std::fill(c->h_which.begin(), c->h_which.end(), 0);
+        c->h_which[slot] = 1;
+        HIPCHK(c, hipMemcpyAsync(c->cs + slot, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->which, c->h_which.data(), sizeof(int32_t) * c->n_slots, hipMemcpyHostToDevice,
+                                 c->stream));
         if ((st = c->ops->set_theta(c)) != HBM_OK) return st;
         CycleState back;
-        if ((st = read_state(c, &back)) != HBM_OK) return st;
+        if ((st = read_slot(c, slot, &back)) != HBM_OK) return st;
         if (!(back.lprior_cur > -HUGE_VAL) || (back.flags & kFlagBadZ)) {
-            HIPCHK(c, hipMemcpyAsync(c->cs, &keep, sizeof(keep), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->cs + slot, &keep, sizeof(keep), hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             return fail(c, HBM_EDOMAIN, "theta outside the prior support or Z(theta) not positive");
         }
-        c->k = k;
-        c->sums_ready = false;
+        c->slots[slot].k = k;
+        c->slots[slot].sums_ready = false;
         return HBM_OK;
     });
 }
@@ -676,21 +1073,24 @@ hbm_status ram_sweep_trace(hbm_ctx *ctx, void *trace)
         if (!trace) return fail(c, HBM_EINVAL, "trace must be non-NULL");
         hbm_status st = c->ops->sweep(c, false, trace);
         if (st != HBM_OK) return st;
-        c->k += 1;
-        c->sums_ready = true;
-        CycleState h;
-        if ((st = read_state(c, &h)) != HBM_OK) return st;
-        return check_flags(c, h);
+        for (Slot &sl : c->slots)
+            if (sl.active) {
+                sl.k += 1;
+                sl.sums_ready = true;
+            }
+        if ((st = read_all(c)) != HBM_OK) return st;
+        return check_flags(c);
     });
 }
 
-hbm_status get_stats(hbm_ctx *ctx, double out[8])
+hbm_status get_stats(hbm_ctx *ctx, int32_t slot, double out[8])
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
-        if (!out) return fail(c, HBM_EINVAL, "out must be non-NULL");
-        CycleState h;
-        hbm_status st = read_state(c, &h);
+        hbm_status st = check_slot(c, slot, true);
         if (st != HBM_OK) return st;
+        if (!out) return fail(c, HBM_EINVAL, "out must be non-NULL");
+        CycleState &h = c->h_cs[slot];
+        if ((st = read_slot(c, slot, &h)) != HBM_OK) return st;
         out[0] = h.sum_lf;
         out[1] = h.sum_dlf;
         out[2] = h.logZ_cur;
@@ -699,6 +1099,71 @@ hbm_status get_stats(hbm_ctx *ctx, double out[8])
         out[5] = h.alpha_last;
         out[6] = h.n_acc_last;
         out[7] = h.accepted_last;
+        return HBM_OK;
+    });
+}
+
+hbm_status set_launch(hbm_ctx *ctx, int32_t tiles_per_group)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (tiles_per_group != 1 && tiles_per_group != 2 && tiles_per_group != 4)
+            return fail(c, HBM_EINVAL, "tiles_per_group must be 1, 2 or 4");
+        if (tiles_per_group == c->tpw) return HBM_OK;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
+        if (c->graph) HIPCHK(c, hipGraphDestroy(c->graph));
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+        c->graph_len = 0;
+        c->tpw = tiles_per_group;
+        return HBM_OK;
+    });
+}
+
+hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t *out_tiles_per_group, double out_us[3])
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (trial_cycles < 1) return fail(c, HBM_EINVAL, "trial_cycles must be >= 1");
+        const int64_t warm = 32, per = warm + trial_cycles, total = 3 * per;
+        for (const Slot &sl : c->slots) {
+            if (!sl.active) continue;
+            if (sl.sums_ready) return fail(c, HBM_ESTATE, "a ram_sweep is waiting for its theta_step");
+            if (sl.n_theta + cycles_taken(sl, total) > sl.trace_cap)
+                return fail(c, HBM_ENOSPACE, "theta trace too small for the autotuner's cycles");
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHK(c, hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(c, HBM_ENOMEM, "hipEventCreate failed");
+        }
+        const int32_t cand[3] = {1, 2, 4};
+        double best = HUGE_VAL;
+        int32_t pick = c->tpw;
+        hbm_status st = HBM_OK;
+        for (int q = 0; q < 3 && st == HBM_OK; ++q) {
+            float ms = 0.0f;
+            hipError_t e = hipSuccess;
+            if ((st = set_launch(ctx, cand[q])) != HBM_OK || (st = run_cycles(ctx, warm, 1)) != HBM_OK) break;
+            if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) { st = hip_fail(c, e, "hipEventRecord"); break; }
+            if ((st = run_cycles(ctx, trial_cycles, 1)) != HBM_OK) break;
+            if ((e = hipEventRecord(e1, c->stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+                st = hip_fail(c, e, "autotune timing");
+                break;
+            }
+            const double us = 1e3 * ms / trial_cycles;
+            if (out_us) out_us[q] = us;
+            if (us < best) {
+                best = us;
+                pick = cand[q];
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != HBM_OK) return st;
+        if ((st = set_launch(ctx, pick)) != HBM_OK) return st;
+        if (out_tiles_per_group) *out_tiles_per_group = pick;
         return HBM_OK;
     });
 }

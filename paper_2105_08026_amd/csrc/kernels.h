@@ -4,7 +4,7 @@
 //                   per-tile FP64 partial sums the theta step consumes, and
 //                   the selection quadrature for the pending theta'
 //                   (workgroup 0).
-//  epilogue_kernel  one workgroup: fixed-order reduction of the partials,
+//  epilogue_kernel  one workgroup per dataset: fixed-order reduction of the partials,
 //                   then the theta Metropolis-Hastings step (fused cycles)
 //                   and the next proposal.  Kept out of the sweep kernel:
 //                   a cross-workgroup release inside it would write back
@@ -38,21 +38,28 @@ struct Precomp {
 };
 static_assert(sizeof(Precomp) % 8 == 0, "Precomp is copied in 8-byte words");
 
+// Arguments of the sweep kernel.  Arrays of the packed datasets are
+// component-major with stride n_total; per-dataset tables are indexed by the
+// dataset (quadrature tables with stride nq, theta traces with stride
+// trace_stride rows of p).
 template <typename T>
 struct SweepArgs {
     T *chi;
     T *chol;
     uint32_t *acc;
-    const T *dd;               // derived per-object data [MD][N]
-    T *snaps;                  // latent snapshots or nullptr
-    T *trace;                  // [3 + D][N] or nullptr
-    double *partials;          // [3][n_tiles]: sum log f, sum of log f changes, accepted moves
-    Precomp *side;             // values for the epilogue, written by workgroup 0
-    CycleState *cs;
-    const Statics *st;
-    const double *qx, *qw, *qeps;
-    int64_t n;
-    int32_t n_tiles;
+    const T *dd;               // derived per-object data [MD][n_total]
+    T *snaps;                  // latent snapshots [snap][D][n_total] or nullptr
+    T *trace;                  // [3 + D][n_total] or nullptr
+    double *partials;          // [3][n_tiles_total]: sum log f, sum of log f changes, accepted moves
+    Precomp *side;             // [n_ds] values for the epilogue, written by the side workgroups
+    CycleState *cs;            // [n_ds]
+    const Statics *st;         // [n_ds]
+    const double *qx, *qw, *qeps;   // [n_ds][nq]
+    const int32_t *tile_ds;    // dataset of each tile, -1 for an unused tile
+    int64_t n_total;
+    int32_t n_tiles_total;
+    int32_t n_ds;
+    int32_t nq;
 };
 
 // ---------------------------------------------------------------------------
@@ -192,6 +199,7 @@ __device__ void theta_mh(CycleState &c, const Statics &s, double *theta_trace, d
     c.delta_last = delta;
     c.alpha_last = alpha;
     c.accepted_last = accepted;
+    if (c.budget > 0 && c.n_theta >= c.budget) c.active = 0;
 }
 
 // ln Z(theta) + lnGamma(beta + 1) = ln sum_j w_j f_x(x_j; theta) Gamma(beta + 1) eps_j
@@ -211,189 +219,262 @@ __device__ __forceinline__ double block_log_z(const double *zc, const double *qx
 }
 
 // ---------------------------------------------------------------------------
-// The sweep: workgroup 0 evaluates ln Z at the pending proposal; every
-// other workgroup updates one tile of 256 objects and writes the tile's
-// FP64 partial sums.  No workgroup waits on another: the epilogue kernel
-// that follows on the stream reduces the partials.
+// The sweep.  Workgroups 0 .. n_ds-1 are side workgroups, one per dataset:
+// ln Z at its pending proposal and every FP64 value of its theta step that
+// the objects do not decide.  Every other workgroup updates one tile of 256
+// objects of one dataset and writes the tile's FP64 partial sums.  No
+// workgroup waits on another: the epilogue kernel that follows on the
+// stream reduces the partials.
 // ---------------------------------------------------------------------------
+// One object's RAM step (steps (a)-(e) of the sweep) and its contributions
+// to the tile sums; returns whether the move was accepted.
 template <class M, bool kTrace>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> a)
+__device__ __forceinline__ bool update_object(const SweepArgs<typename M::T> &a, int ds, int64_t il, double *v)
 {
     using T = typename M::T;
     constexpr int D = M::D, NC = M::NC;
-    __shared__ double red[3][kWavesPerBlock];
-    CycleState *cs = a.cs;
-    const Statics &st = *a.st;
+    const CycleState *cs = a.cs + ds;
+    const Statics &st = a.st[ds];
+    const int64_t i = st.obj_start + il;             // object in the packed arrays
+    const int64_t n = a.n_total;
+    const int64_t k = cs->k + 1;
+    const T *kc = kc_of<T>(const_cast<CycleState *>(cs));
+    const T eta = static_cast<T>(cs->eta_next);
+    const T astar = static_cast<T>(st.alpha_star);
+    T x[D], S[NC], U[D], y[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) x[j] = a.chi[j * n + i];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) S[e] = a.chol[e * n + i];
+    uint32_t nacc = a.acc[i];
+    const typename M::Obj o = M::load(a.dd, i, n);
+    const Block4 b = philox(static_cast<uint32_t>(il), static_cast<uint32_t>(k), 0u, 0u, st.key0, st.key1);
+    normals<T, D>(b, U);
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+        T acc_r = x[r];
+#pragma unroll
+        for (int q = 0; q <= r; ++q) acc_r += S[r * (r + 1) / 2 + q] * U[q];
+        y[r] = acc_r;
+    }
+    const Eval<T> ex = M::eval(o, x, kc, st);
+    const Eval<T> ey = M::eval(o, y, kc, st);
+    const T neg_inf = -static_cast<T>(HUGE_VAL);
+    const T delta = (ey.lpv > neg_inf) ? ey.lpv - ex.lpv : neg_inf;
+    const bool accept = ln_uniform(b, T(0)) < delta;
+    const T alpha = accept_prob(delta);
+    if (accept) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[j] = y[j];
+        nacc += 1u;
+    }
+    const Eval<T> en = accept ? ey : ex;
+    ram_adapt<T, D>(S, U, eta * (alpha - astar));
+#pragma unroll
+    for (int j = 0; j < D; ++j) a.chi[j * n + i] = x[j];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) a.chol[e * n + i] = S[e];
+    a.acc[i] = nacc;
+    v[0] = static_cast<double>(en.lf);
+    v[1] = static_cast<double>(M::dlf(o, x, en, kc, st));
+    if (!(ex.lpv > neg_inf)) atomicOr(&a.cs[ds].flags, kFlagNonFiniteState);
+    if (kTrace) {
+        a.trace[i] = ex.lp;
+        a.trace[n + i] = ey.lp;
+        a.trace[2 * n + i] = accept ? static_cast<T>(1) : static_cast<T>(0);
+#pragma unroll
+        for (int j = 0; j < D; ++j) a.trace[(3 + j) * n + i] = y[j];
+    }
+    if (a.snaps != nullptr && st.thin > 0 && k % st.thin == 0) {
+        const int64_t snap = k / st.thin - 1;
+        if (snap < st.snap_cap) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) a.snaps[(snap * D + j) * n + i] = x[j];
+        }
+    }
+    return accept;
+}
 
-    if (blockIdx.x == 0) {
-        // everything the epilogue needs that the objects do not decide
+// ---------------------------------------------------------------------------
+// The sweep.  Workgroups 0 .. n_ds-1 are side workgroups, one per dataset:
+// ln Z at its pending proposal and every FP64 value of its theta step that
+// the objects do not decide.  Every other workgroup updates TPW consecutive
+// tiles of 256 objects (lane t takes object t of each) and writes one set of
+// FP64 partial sums per tile, reduced in the same fixed order whatever TPW
+// is, so the launch shape never changes a result.  No workgroup waits on
+// another: the epilogue kernel that follows on the stream reduces the
+// partials.
+// ---------------------------------------------------------------------------
+template <class M, bool kTrace, int TPW>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> a)
+{
+    __shared__ double red[2 * TPW][kWavesPerBlock];
+    __shared__ uint32_t nacc_w[TPW][kWavesPerBlock];
+
+    if (static_cast<int>(blockIdx.x) < a.n_ds) {
+        const int ds = blockIdx.x;
+        CycleState *cs = a.cs + ds;
+        if (!cs->active) return;
+        const Statics &st = a.st[ds];
         __shared__ Precomp sd;
+        __shared__ double zred[1][kWavesPerBlock];
         const bool valid = cs->prop_valid != 0;
         double judged[kMaxP];
         for (int r = 0; r < M::P; ++r) judged[r] = cs->prop[r];
         double zraw = 0.0;
         if (M::kSelection && valid) {
             double zc[2] = {cs->zc_prop[0], cs->zc_prop[1]};
-            zraw = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
+            const int64_t qo = static_cast<int64_t>(ds) * a.nq;
+            zraw = block_log_z(zc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, zred);
         }
         precompute<M>(sd, cs->k + 1, judged, valid, st);
         if (threadIdx.x == 0) sd.zraw = zraw;
         __syncthreads();
         const uint64_t *src = reinterpret_cast<const uint64_t *>(&sd);
-        uint64_t *dst = reinterpret_cast<uint64_t *>(a.side);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(a.side + ds);
         for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
         return;
     }
-    const int tile = blockIdx.x - 1;
-    const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;
-    const int64_t n = a.n;
-    const int64_t k = cs->k + 1;
-    const T *kc = kc_of<T>(cs);
-    const T eta = static_cast<T>(cs->eta_next);
-    const T astar = static_cast<T>(st.alpha_star);
-    double v[2] = {0.0, 0.0};
-    bool accept = false;
-    if (i < n) {
-        T x[D], S[NC], U[D], y[D];
+
+    const int g0 = (static_cast<int>(blockIdx.x) - a.n_ds) * TPW;     // first tile
+    int dss[TPW];
+    bool any = false;
 #pragma unroll
-        for (int j = 0; j < D; ++j) x[j] = a.chi[j * n + i];
-#pragma unroll
-        for (int e = 0; e < NC; ++e) S[e] = a.chol[e * n + i];
-        uint32_t nacc = a.acc[i];
-        const typename M::Obj o = M::load(a.dd, i, n);
-        const Block4 b = philox(static_cast<uint32_t>(i), static_cast<uint32_t>(k), 0u, 0u, st.key0, st.key1);
-        normals<T, D>(b, U);
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            T acc_r = x[r];
-#pragma unroll
-            for (int q = 0; q <= r; ++q) acc_r += S[r * (r + 1) / 2 + q] * U[q];
-            y[r] = acc_r;
-        }
-        const Eval<T> ex = M::eval(o, x, kc, st);
-        const Eval<T> ey = M::eval(o, y, kc, st);
-        const T neg_inf = -static_cast<T>(HUGE_VAL);
-        const T delta = (ey.lpv > neg_inf) ? ey.lpv - ex.lpv : neg_inf;
-        accept = ln_uniform(b, T(0)) < delta;
-        const T alpha = accept_prob(delta);
-        if (accept) {
-#pragma unroll
-            for (int j = 0; j < D; ++j) x[j] = y[j];
-            nacc += 1u;
-        }
-        const Eval<T> en = accept ? ey : ex;
-        ram_adapt<T, D>(S, U, eta * (alpha - astar));
-#pragma unroll
-        for (int j = 0; j < D; ++j) a.chi[j * n + i] = x[j];
-#pragma unroll
-        for (int e = 0; e < NC; ++e) a.chol[e * n + i] = S[e];
-        a.acc[i] = nacc;
-        v[0] = static_cast<double>(en.lf);
-        v[1] = static_cast<double>(M::dlf(o, x, en, kc, st));
-        if (!(ex.lpv > neg_inf)) atomicOr(&cs->flags, kFlagNonFiniteState);
-        if (kTrace) {
-            a.trace[i] = ex.lp;
-            a.trace[n + i] = ey.lp;
-            a.trace[2 * n + i] = accept ? static_cast<T>(1) : static_cast<T>(0);
-#pragma unroll
-            for (int j = 0; j < D; ++j) a.trace[(3 + j) * n + i] = y[j];
-        }
-        if (a.snaps != nullptr && st.thin > 0 && k % st.thin == 0) {
-            const int64_t snap = k / st.thin - 1;
-            if (snap < st.snap_cap) {
-#pragma unroll
-                for (int j = 0; j < D; ++j) a.snaps[(snap * D + j) * n + i] = x[j];
-            }
-        }
+    for (int u = 0; u < TPW; ++u) {
+        const int g = g0 + u;
+        int ds = (g < a.n_tiles_total) ? a.tile_ds[g] : -1;
+        if (ds >= 0 && !a.cs[ds].active) ds = -1;     // no epilogue reads this tile
+        dss[u] = ds;
+        any = any || ds >= 0;
     }
-    // accepted moves: one ballot per wavefront
-    __shared__ uint32_t nacc_w[kWavesPerBlock];
-    const uint32_t nw = static_cast<uint32_t>(__popcll(__ballot(accept)));
-    if ((threadIdx.x & (kWave - 1)) == 0) nacc_w[threadIdx.x / kWave] = nw;
-    block_sum<2>(v, red);
+    if (!any) return;
+    double v[2 * TPW];
+    bool accepted[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        v[2 * u] = v[2 * u + 1] = 0.0;
+        accepted[u] = false;
+        const int ds = dss[u];
+        if (ds < 0) continue;
+        const int64_t il = static_cast<int64_t>(g0 + u - a.st[ds].tile_start) * kBlock + threadIdx.x;
+        if (il < a.st[ds].n) accepted[u] = update_object<M, kTrace>(a, ds, il, v + 2 * u);
+    }
+    // accepted moves: one ballot per wavefront and tile
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const uint32_t nw = static_cast<uint32_t>(__popcll(__ballot(accepted[u])));
+        if ((threadIdx.x & (kWave - 1)) == 0) nacc_w[u][threadIdx.x / kWave] = nw;
+    }
+    block_sum<2 * TPW>(v, red);
     if (threadIdx.x == 0) {
-        a.partials[tile] = v[0];
-        a.partials[a.n_tiles + tile] = v[1];
-        a.partials[2 * a.n_tiles + tile] = static_cast<double>((nacc_w[0] + nacc_w[1]) + (nacc_w[2] + nacc_w[3]));
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            if (dss[u] < 0) continue;
+            const int g = g0 + u;
+            a.partials[g] = v[2 * u];
+            a.partials[a.n_tiles_total + g] = v[2 * u + 1];
+            a.partials[2 * a.n_tiles_total + g] =
+                static_cast<double>((nacc_w[u][0] + nacc_w[u][1]) + (nacc_w[u][2] + nacc_w[u][3]));
+        }
     }
 }
 
-// Epilogue of a sweep (one workgroup): fixed-order reduction of the tile
-// partials, bookkeeping, then (kFull) the theta step, then the proposal
-// for the next sweep.
+struct EpiArgs {
+    CycleState *cs;
+    const Statics *st;
+    const double *partials;
+    const Precomp *side;
+    double *theta_trace;       // [n_ds][trace_stride][p]
+    int64_t trace_stride;
+    int32_t n_tiles_total;
+};
+
+// Epilogue of a sweep, one workgroup per dataset: fixed-order reduction of
+// the dataset's tile partials, bookkeeping, then (kFull) the theta step,
+// then the proposal for the next sweep.
 template <class M, bool kFull>
-__global__ __launch_bounds__(kBlock) void epilogue_kernel(CycleState *cs, const Statics *stp, const double *partials,
-                                                          const Precomp *side, double *theta_trace, int32_t n_tiles)
+__global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
     __shared__ double red[3][kWavesPerBlock];
-    const Statics &st = *stp;
-    // tile partials, structure of arrays [3][n_tiles]
+    const int ds = blockIdx.x;
+    if (!a.cs[ds].active) return;
+    const Statics &st = a.st[ds];
+    const int32_t t0 = st.tile_start, nt = st.n_tiles, ntt = a.n_tiles_total;
+    // tile partials of this dataset, structure of arrays [3][n_tiles_total]
     double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll 4
-    for (int t = threadIdx.x; t < n_tiles; t += kBlock) {
-        v[0] += partials[t];
-        v[1] += partials[n_tiles + t];
-        v[2] += partials[2 * n_tiles + t];
+    for (int t = threadIdx.x; t < nt; t += kBlock) {
+        v[0] += a.partials[t0 + t];
+        v[1] += a.partials[ntt + t0 + t];
+        v[2] += a.partials[2 * ntt + t0 + t];
     }
     {
-        const uint64_t *src = reinterpret_cast<const uint64_t *>(side);
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(a.side + ds);
         uint64_t *dst = reinterpret_cast<uint64_t *>(&pc);
         for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
     }
-    stage_in(c, cs);                     // its barrier also publishes pc
+    stage_in(c, a.cs + ds);              // its barrier also publishes pc
     block_sum<3>(v, red);
     if (threadIdx.x == 0) {
         finish_sweep<M>(c, st, v, pc.zraw, pc);
-        if (kFull) theta_mh<M>(c, st, theta_trace, pc.ln_u);
+        if (kFull) theta_mh<M>(c, st, a.theta_trace + ds * a.trace_stride * M::P, pc.ln_u);
         prepare_next<M>(c, st, pc);
     }
-    stage_out(cs, c);
+    stage_out(a.cs + ds, c);
 }
 
-// Theta step on its own, after a ram_sweep (plain cycle).
+// Theta step on its own, after a ram_sweep (plain cycle), one workgroup per dataset.
 template <class M>
-__global__ __launch_bounds__(kBlock) void theta_kernel(CycleState *cs, const Statics *st, const Precomp *side,
-                                                       double *theta_trace)
+__global__ __launch_bounds__(kBlock) void theta_kernel(EpiArgs a)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
+    const int ds = blockIdx.x;
+    if (!a.cs[ds].active) return;
     {
-        const uint64_t *src = reinterpret_cast<const uint64_t *>(side);
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(a.side + ds);
         uint64_t *dst = reinterpret_cast<uint64_t *>(&pc);
         for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
     }
-    stage_in(c, cs);
+    stage_in(c, a.cs + ds);
     const bool ready = c.sums_ready != 0;
     if (threadIdx.x == 0) {
         if (ready) {
-            theta_mh<M>(c, *st, theta_trace, pc.ln_u);
-            prepare_next<M>(c, *st, pc);
+            theta_mh<M>(c, a.st[ds], a.theta_trace + ds * a.trace_stride * M::P, pc.ln_u);
+            prepare_next<M>(c, a.st[ds], pc);
         } else {
             c.flags |= kFlagNoSums;
         }
     }
-    stage_out(cs, c);
+    stage_out(a.cs + ds, c);
 }
 
-// Recompute everything that depends on theta after it is set from the host.
+// Recompute everything that depends on theta after it is set from the host,
+// for the datasets whose flag in `which` is set (one workgroup each).
 template <class M>
-__global__ __launch_bounds__(kBlock) void set_theta_kernel(CycleState *cs, const Statics *st, const double *qx,
-                                                           const double *qw, const double *qeps)
+__global__ __launch_bounds__(kBlock) void set_theta_kernel(CycleState *cs_all, const Statics *st_all,
+                                                           const double *qx, const double *qw, const double *qeps,
+                                                           int32_t nq, const int32_t *which)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
     __shared__ double red[1][kWavesPerBlock];
+    const int ds = blockIdx.x;
+    if (!which[ds]) return;
+    CycleState *cs = cs_all + ds;
+    const Statics &st = st_all[ds];
     stage_in(c, cs);
     const bool ok = M::in_support(c.theta);
     // the judged-proposal slots of pc carry theta itself here
-    precompute<M>(pc, c.k, c.theta, ok, *st);
+    precompute<M>(pc, c.k, c.theta, ok, st);
     double lz = 0.0;
     if (M::kSelection && ok) {
         double zc[2];
         M::z_consts(c.theta, zc);
-        lz = block_log_z(zc, qx, qw, qeps, st->nq, red);
+        const int64_t qo = static_cast<int64_t>(ds) * nq;
+        lz = block_log_z(zc, qx + qo, qw + qo, qeps + qo, nq, red);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -403,53 +484,66 @@ __global__ __launch_bounds__(kBlock) void set_theta_kernel(CycleState *cs, const
         c.logZ_cur = (M::kSelection && ok) ? lz - M::logz_shift(c.aux_cur) : 0.0;
         if (M::kSelection && ok && !(c.logZ_cur > -HUGE_VAL && c.logZ_cur < HUGE_VAL)) c.flags |= kFlagBadZ;
         c.sums_ready = 0;
-        prepare_next<M>(c, *st, pc);
+        prepare_next<M>(c, st, pc);
     }
     stage_out(cs, c);
 }
 
 template <class M>
-__global__ void statics_kernel(Statics *st)
+__global__ void statics_kernel(Statics *st, const int32_t *which)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) M::derive_statics(*st);
+    if (threadIdx.x == 0 && which[blockIdx.x]) M::derive_statics(st[blockIdx.x]);
 }
 
+// Per-tile kernels of the initialisation: each workgroup takes one tile of
+// one dataset (tiles of unloaded or unselected datasets are skipped).
 template <class M>
 __global__ __launch_bounds__(kBlock) void derive_data_kernel(const typename M::T *data, typename M::T *dd,
-                                                             const Statics *st)
+                                                             const Statics *st, const int32_t *tile_ds,
+                                                             const int32_t *which, int64_t n_total)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i < st->n) M::derive_obj(data, dd, i, st->n, *st);
+    const int ds = tile_ds[blockIdx.x];
+    if (ds < 0 || !which[ds]) return;
+    const Statics &s = st[ds];
+    const int64_t il = static_cast<int64_t>(blockIdx.x - s.tile_start) * kBlock + threadIdx.x;
+    if (il < s.n) M::derive_obj(data, dd, s.obj_start + il, n_total, s);
 }
 
 template <class M>
-__global__ __launch_bounds__(kBlock) void init_chain_kernel(typename M::T *chol, uint32_t *acc, double s0,
-                                                            const Statics *st)
+__global__ __launch_bounds__(kBlock) void init_chain_kernel(typename M::T *chol, uint32_t *acc, const Statics *st, const int32_t *tile_ds,
+                                                            const int32_t *which, int64_t n_total)
 {
     using T = typename M::T;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const int64_t n = st->n;
-    if (i >= n) return;
+    const int ds = tile_ds[blockIdx.x];
+    if (ds < 0 || !which[ds]) return;
+    const Statics &s = st[ds];
+    const int64_t il = static_cast<int64_t>(blockIdx.x - s.tile_start) * kBlock + threadIdx.x;
+    if (il >= s.n) return;
+    const int64_t i = s.obj_start + il;
     for (int r = 0, e = 0; r < M::D; ++r)
-        for (int q = 0; q <= r; ++q, ++e) chol[e * n + i] = (r == q) ? static_cast<T>(s0) : static_cast<T>(0);
+        for (int q = 0; q <= r; ++q, ++e) chol[e * n_total + i] = (r == q) ? static_cast<T>(s.s0) : static_cast<T>(0);
     acc[i] = 0u;
 }
 
 // Flags objects whose starting log density is not finite (pi(X_1) > 0 is required).
 template <class M>
 __global__ __launch_bounds__(kBlock) void check_init_kernel(const typename M::T *chi, const typename M::T *dd,
-                                                            CycleState *cs, const Statics *st)
+                                                            CycleState *cs, const Statics *st, const int32_t *tile_ds,
+                                                            const int32_t *which, int64_t n_total)
 {
     using T = typename M::T;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const int64_t n = st->n;
-    if (i >= n) return;
+    const int ds = tile_ds[blockIdx.x];
+    if (ds < 0 || !which[ds]) return;
+    const Statics &s = st[ds];
+    const int64_t il = static_cast<int64_t>(blockIdx.x - s.tile_start) * kBlock + threadIdx.x;
+    if (il >= s.n) return;
+    const int64_t i = s.obj_start + il;
     T x[M::D];
-    for (int j = 0; j < M::D; ++j) x[j] = chi[j * n + i];
-    const Eval<T> e = M::eval(M::load(dd, i, n), x, kc_of<T>(cs), *st);
+    for (int j = 0; j < M::D; ++j) x[j] = chi[j * n_total + i];
+    const Eval<T> e = M::eval(M::load(dd, i, n_total), x, kc_of<T>(cs + ds), s);
     if (!(e.lpv > -static_cast<T>(HUGE_VAL) && e.lpv < static_cast<T>(HUGE_VAL))) {
-        atomicMin(&cs->first_bad, static_cast<int32_t>(i));
-        atomicOr(&cs->flags, kFlagNonFiniteState);
+        atomicMin(&cs[ds].first_bad, static_cast<int32_t>(il));
+        atomicOr(&cs[ds].flags, kFlagNonFiniteState);
     }
 }
 
@@ -458,59 +552,76 @@ struct PopArgs {
     const T *chi;
     const T *dd;
     double *partials;
-    double *zout;
+    double *pout;              // [n_ds][2]: ln Z(theta), sum log f - N ln Z
+    const double *theta;       // [n_ds][p]
     const Statics *st;
     const double *qx, *qw, *qeps;
-    int64_t n;
-    double theta[kMaxP];
+    const int32_t *tile_ds;
+    int64_t n_total;
+    int32_t n_tiles_total;
+    int32_t n_ds;
+    int32_t nq;
 };
 
-// Partial sums of log f(chi_i; theta) per tile; workgroup 0 evaluates ln Z(theta).
+// Partial sums of log f(chi_i; theta_ds) per tile; side workgroups evaluate ln Z(theta_ds).
 template <class M>
 __global__ __launch_bounds__(kBlock) void poplik_kernel(PopArgs<typename M::T> a)
 {
     using T = typename M::T;
     __shared__ double red[1][kWavesPerBlock];
     __shared__ T kc[32];
-    const Statics &st = *a.st;
-    double ag[2];
-    M::aux(a.theta, ag);
-    if (blockIdx.x == 0) {
+    if (static_cast<int>(blockIdx.x) < a.n_ds) {
+        const int ds = blockIdx.x;
+        if (a.st[ds].n == 0) {                    // empty slot
+            if (threadIdx.x == 0) a.pout[2 * ds] = a.pout[2 * ds + 1] = static_cast<double>(NAN);
+            return;
+        }
+        const double *th = a.theta + ds * M::P;
+        double ag[2];
+        M::aux(th, ag);
+        double lz = 0.0;
         if (M::kSelection) {
             double zc[2];
-            M::z_consts(a.theta, zc);
-            const double lz = block_log_z(zc, a.qx, a.qw, a.qeps, st.nq, red);
-            if (threadIdx.x == 0) a.zout[1] = lz - M::logz_shift(ag);
-        } else if (threadIdx.x == 0) {
-            a.zout[1] = 0.0;
+            M::z_consts(th, zc);
+            const int64_t qo = static_cast<int64_t>(ds) * a.nq;
+            lz = block_log_z(zc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, red) - M::logz_shift(ag);
         }
+        if (threadIdx.x == 0) a.pout[2 * ds] = lz;
         return;
     }
-    if (threadIdx.x == 0) M::derive_kc(a.theta, a.theta, ag, st, kc);
+    const int g = blockIdx.x - a.n_ds;
+    const int ds = a.tile_ds[g];
+    if (ds < 0) return;
+    const Statics &st = a.st[ds];
+    const double *th = a.theta + ds * M::P;
+    if (threadIdx.x == 0) {
+        double ag[2];
+        M::aux(th, ag);
+        M::derive_kc(th, th, ag, st, kc);
+    }
     __syncthreads();
-    const int tile = blockIdx.x - 1;
-    const int64_t i = static_cast<int64_t>(tile) * kBlock + threadIdx.x;
+    const int64_t il = static_cast<int64_t>(g - st.tile_start) * kBlock + threadIdx.x;
     double v[1] = {0.0};
-    if (i < a.n) {
+    if (il < st.n) {
+        const int64_t i = st.obj_start + il;
         T x[M::D];
-        for (int j = 0; j < M::D; ++j) x[j] = a.chi[j * a.n + i];
-        v[0] = static_cast<double>(M::eval(M::load(a.dd, i, a.n), x, kc, st).lf);
+        for (int j = 0; j < M::D; ++j) x[j] = a.chi[j * a.n_total + i];
+        v[0] = static_cast<double>(M::eval(M::load(a.dd, i, a.n_total), x, kc, st).lf);
     }
     block_sum<1>(v, red);
-    if (threadIdx.x == 0) a.partials[tile] = v[0];
+    if (threadIdx.x == 0) a.partials[g] = v[0];
 }
 
-__global__ __launch_bounds__(kBlock) void poplik_finish_kernel(CycleState *cs, const double *partials,
-                                                               const double *zout, int64_t n, int32_t n_tiles)
+__global__ __launch_bounds__(kBlock) void poplik_finish_kernel(const Statics *st, const double *partials, double *pout)
 {
     __shared__ double red[1][kWavesPerBlock];
+    const int ds = blockIdx.x;
+    const Statics &s = st[ds];
+    if (s.n == 0) return;
     double v[1] = {0.0};
-    for (int t = threadIdx.x; t < n_tiles; t += kBlock) v[0] += partials[t];
+    for (int t = threadIdx.x; t < s.n_tiles; t += kBlock) v[0] += partials[s.tile_start + t];
     block_sum<1>(v, red);
-    if (threadIdx.x == 0) {
-        cs->poplik_logz = zout[1];
-        cs->poplik_out = v[0] - static_cast<double>(n) * zout[1];
-    }
+    if (threadIdx.x == 0) pout[2 * ds + 1] = v[0] - static_cast<double>(s.n) * pout[2 * ds];
 }
 
 // ---------------------------------------------------------------------------
@@ -556,12 +667,17 @@ __global__ void gauss_legendre_kernel(double *t_out, double *w_out, int nq)
 // h(r) = 3 r^2 / rmax^3 and eta(F) = Phi((F - F_th) / sigma_F) (eq 5.10),
 // written in s = ln u, u = (r / rmax)^3, so that h dr = e^s ds, over
 // s in [-60, 0] with the same n-point rule (the part below e^-60 is dropped).
-__global__ void eps_table_kernel(const double *t, const double *w, double *qx, double *qw, double *qeps,
-                                 const Statics *st)
+__global__ void eps_table_kernel(const double *t, const double *w, double *qx_all, double *qw_all, double *qeps_all,
+                                 const Statics *st_all, const int32_t *which)
 {
+    const int ds = blockIdx.y;
+    if (!which[ds]) return;
+    const Statics *st = st_all + ds;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int nq = st->nq;
     if (j >= nq) return;
+    double *qx = qx_all + static_cast<int64_t>(ds) * nq, *qw = qw_all + static_cast<int64_t>(ds) * nq;
+    double *qeps = qeps_all + static_cast<int64_t>(ds) * nq;
     const double fth = st->mc[0], sigf = st->mc[1], rmax = st->mc[2], lnl0 = st->mc[3];
     const double lo = lnl0 - 30.0, hi = lnl0 + log(40.0);
     // nodes ascend in x: t descends with the node index

@@ -42,19 +42,24 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     fields = [f for f, _ in hbm.Config._fields_]
     bfields = [f for f, _ in hbm.Buffers._fields_]
+    pfields = [f for f, _ in hbm.PoolConfig._fields_]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hbm.h"', "int main(void){",
-             'printf("%zu %zu\\n", sizeof(hbm_config), sizeof(hbm_buffers));']
+             'printf("%zu %zu %zu\\n", sizeof(hbm_config), sizeof(hbm_buffers), sizeof(hbm_pool_config));']
     lines += [f'printf("%zu\\n", offsetof(hbm_config, {f}));' for f in fields]
     lines += [f'printf("%zu\\n", offsetof(hbm_buffers, {f}));' for f in bfields]
+    lines += [f'printf("%zu\\n", offsetof(hbm_pool_config, {f}));' for f in pfields]
     lines += ["return 0;}"]
     src.write_text("\n".join(lines))
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert vals[0] == ctypes.sizeof(hbm.Config) and vals[1] == ctypes.sizeof(hbm.Buffers)
-    offs = vals[2:]
-    assert offs[: len(fields)] == [getattr(hbm.Config, f).offset for f in fields]
-    assert offs[len(fields):] == [getattr(hbm.Buffers, f).offset for f in bfields]
+    assert vals[2] == ctypes.sizeof(hbm.PoolConfig)
+    offs = vals[3:]
+    nf, nb = len(fields), len(bfields)
+    assert offs[:nf] == [getattr(hbm.Config, f).offset for f in fields]
+    assert offs[nf:nf + nb] == [getattr(hbm.Buffers, f).offset for f in bfields]
+    assert offs[nf + nb:] == [getattr(hbm.PoolConfig, f).offset for f in pfields]
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

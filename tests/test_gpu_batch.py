@@ -1,0 +1,196 @@
+"""GPU: batched and pooled datasets through the C ABI.
+
+A dataset's chain depends only on its data, configuration and seed, so a
+dataset advanced inside a batch (init_batch) or a continuously refilled pool
+(create_pool / load_datasets / unload_dataset) must reproduce, bit for bit,
+the chain of the same dataset run alone (whose parity with the FP64 oracle
+is checked in test_gpu_parity.py).  The population log-likelihood of every
+slot is also checked against the oracle directly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+FTH = 389.75   # threshold of the reference luminosity function (skips per-dataset calibration)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_08026_amd as h
+    h.lib()
+    return h
+
+
+def _alone(hbm, wl, cycles, plain=False):
+    s = hbm.Sampler(wl, max_cycles=max(cycles, 1))
+    if plain:
+        for _ in range(cycles):
+            s.ram_sweep(1)
+            s.theta_step()
+    else:
+        s.run_cycles(cycles)
+    tr, chi = s.theta_trace(), s.state()[0]
+    s.close()
+    return tr, chi
+
+
+def _lf_set(n_sets, seed0, n_lo, n_hi):
+    rng = np.random.default_rng(seed0)
+    ns = np.round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), n_sets))).astype(int)
+    return [synth.gamma_lf_1d(n=int(n), seed=seed0 + j, fth=FTH) for j, n in enumerate(ns)]
+
+
+def test_batch_matches_each_dataset_alone(hbm):
+    wls = _lf_set(6, 700, 90, 3000) + [synth.gamma_lf_1d(n=256, seed=799, fth=FTH)]
+    _say(f"batch of {len(wls)} LF datasets, N={[w.n for w in wls]}, 80 cycles (graph)")
+    b = hbm.Batch(wls, max_cycles=80)
+    b.run_cycles(80)
+    for j, w in enumerate(wls):
+        tr, chi = _alone(hbm, w, 80)
+        assert np.array_equal(b.theta_trace(j), tr), j
+        assert np.array_equal(b.latents(j), chi), j
+    b.close()
+
+
+def test_batch_plain_calls_nn3d(hbm):
+    wls = [synth.normal_normal_3d(n=n, seed=s) for n, s in ((300, 5), (1000, 6), (77, 7))]
+    _say("batch of 3 NN3D datasets, 30 plain sweep + theta-step cycles")
+    b = hbm.Batch(wls, max_cycles=30)
+    for _ in range(30):
+        rates = b.ram_sweep(1, rate=True)
+        assert rates.shape == (3,) and np.all((rates >= 0) & (rates <= 1))
+        acc = b.theta_step()
+        assert set(acc.tolist()) <= {0, 1}
+    for j, w in enumerate(wls):
+        tr, chi = _alone(hbm, w, 30, plain=True)
+        assert np.array_equal(b.theta_trace(j), tr), j
+        assert np.array_equal(b.latents(j), chi), j
+    b.close()
+
+
+def test_batch_pop_loglik_matches_oracle(hbm):
+    wls = _lf_set(4, 900, 300, 5000)
+    _say(f"batch pop_loglik, N={[w.n for w in wls]}")
+    b = hbm.Batch(wls, max_cycles=20)
+    b.run_cycles(20)
+    thetas = np.array([w.theta_true for w in wls]) + np.array([0.01, -0.02])
+    got = b.pop_loglik(thetas)
+    for j, w in enumerate(wls):
+        o = oracle.Oracle(w)
+        chi = b.latents(j)
+        ref = o.pop_loglik(thetas[j], chi)
+        scale = np.sum(np.abs(o.pop_terms(thetas[j], chi)))
+        assert abs(got[j] - ref) <= 1e-6 * scale + 1e-12 * w.n, (j, got[j], ref)
+    b.close()
+
+
+def test_pool_jobs_match_alone_runs(hbm):
+    """Continuous batching: jobs admitted as space frees, stopped by their
+    budgets on the device and retired; each job's samples equal its run alone."""
+    wls = _lf_set(7, 1100, 200, 2500)
+    budgets = [40, 70, 33, 90, 50, 21, 64]
+    _say(f"pool: 7 jobs N={[w.n for w in wls]} budgets={budgets}, 3 slots, capacity 4608")
+    pool = hbm.Pool(hbm.HBM_GAMMA_LF_1D, capacity=4608, n_slots=3, max_cycles=100)
+    pending = list(range(len(wls)))
+    done = {}
+    where = {}
+    rounds = 0
+    while pending or pool.resident:
+        while pending:
+            j = pending[0]
+            if not pool.fits(wls[j].n):
+                break
+            slot = pool.admit([wls[j]], [budgets[j]])[0]
+            assert slot is not None
+            where[slot] = j
+            pending.pop(0)
+        assert pool.resident, "a job larger than the empty pool"
+        pool.run_cycles(16)
+        rounds += 1
+        for slot in pool.finished():
+            j = where.pop(slot)
+            info = pool.info(slot)
+            assert info["n_theta"] == budgets[j] and info["k"] == budgets[j]
+            chi = pool.latents(slot)
+            done[j] = (pool.retire(slot), chi)
+        assert rounds < 100
+    assert sorted(done) == list(range(len(wls)))
+    for j, w in enumerate(wls):
+        tr, chi = _alone(hbm, w, budgets[j])
+        assert np.array_equal(done[j][0], tr), j
+        assert np.array_equal(done[j][1], chi), j
+    pool.close()
+
+
+def test_pool_rejects_bad_loads(hbm):
+    _say("pool: invalid placements and slots are rejected, the pool stays usable")
+    w = synth.gamma_lf_1d(n=300, seed=3, fth=FTH)
+    pool = hbm.Pool(hbm.HBM_GAMMA_LF_1D, capacity=1024, n_slots=2, max_cycles=10)
+    cfg = hbm.make_config(w, max_cycles=10)
+    th0 = np.array([w.theta0])
+    with pytest.raises(hbm.HbmError, match="multiple of 256"):
+        hbm.load_datasets(pool.ctx, [0], [100], [cfg], th0)
+    with pytest.raises(hbm.HbmError, match="slot out of range"):
+        hbm.load_datasets(pool.ctx, [5], [0], [cfg], th0)
+    with pytest.raises(hbm.HbmError, match="budget"):
+        hbm.load_datasets(pool.ctx, [0], [0], [cfg], th0, [11])
+    with pytest.raises(hbm.HbmError, match="capacity"):
+        hbm.load_datasets(pool.ctx, [0], [768], [cfg], th0)
+    (slot,) = pool.admit([w], [10])
+    other = 1 - slot
+    with pytest.raises(hbm.HbmError, match="overlaps"):
+        hbm.load_datasets(pool.ctx, [other], [pool.resident[slot][0]], [cfg], th0)
+    with pytest.raises(hbm.HbmError, match="already holds"):
+        hbm.load_datasets(pool.ctx, [slot], [512], [cfg], th0)
+    pool.run_cycles(10)
+    assert pool.finished() == [slot]
+    tr = pool.retire(slot)
+    ref, _ = _alone(hbm, w, 10)
+    assert np.array_equal(tr, ref)
+    with pytest.raises(hbm.HbmError, match="no dataset"):
+        hbm.get_stats(pool.ctx, slot)
+    pool.close()
+
+
+@pytest.mark.parametrize("make", [lambda: synth.gamma_lf_1d(n=5000, seed=71, fth=FTH),
+                                  lambda: synth.normal_normal_3d(n=1500, seed=8)], ids=["lf1d", "nn3d"])
+def test_launch_shape_does_not_change_the_chain(hbm, make):
+    wl = make()
+    _say(f"launch shapes 1/2/4 tiles per workgroup, {wl.name} N={wl.n}")
+    ref, ref_chi = _alone(hbm, wl, 70)
+    for tpw in (2, 4):
+        s = hbm.Sampler(wl, max_cycles=70)
+        s.set_launch(tpw)
+        s.run_cycles(70)
+        assert np.array_equal(s.theta_trace(), ref), tpw
+        assert np.array_equal(s.state()[0], ref_chi), tpw
+        s.close()
+
+
+def test_autotune_batch_keeps_chains(hbm):
+    wls = _lf_set(5, 1300, 300, 4000)
+    _say(f"autotune on a batch N={[w.n for w in wls]}")
+    b = hbm.Batch(wls, max_cycles=3 * (32 + 8) + 10)
+    pick, us = b.autotune(8)
+    assert pick in (1, 2, 4) and np.all(us > 0)
+    b.run_cycles(10)
+    for j, w in enumerate(wls):
+        tr, chi = _alone(hbm, w, 3 * (32 + 8) + 10)
+        assert np.array_equal(b.theta_trace(j), tr), j
+        assert np.array_equal(b.latents(j), chi), j
+    b.close()
