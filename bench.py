@@ -43,7 +43,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="gamma_lf_1d",
                     choices=["gamma_lf_1d", "gamma_lf_color_3d", "normal_normal_1d", "normal_normal_3d",
-                             "gamma_lf_batch256"])
+                             "gamma_lf_batch256", "serving"])
+    ap.add_argument("--horizon", type=float, default=60.0, help="serving: seconds of Poisson arrivals")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
+    ap.add_argument("--sat-jobs", type=int, default=200, help="serving: jobs in the saturation run")
     ap.add_argument("--seq-steps", type=int, default=200,
                     help="batch workload: cycles timed per dataset in the one-dataset-per-launch comparison")
     ap.add_argument("--job-sweeps", type=int, default=2000, help="batch workload: sweeps that make one job")
@@ -151,6 +154,77 @@ def bench_batch(args, torch, synth, hbm):
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(args, torch, synth, hbm):
+    """Poisson arrivals of luminosity-function jobs served by continuous batching.
+
+    Three runs on one pool: (1) real-time arrivals at --rate for --horizon s
+    (latency percentiles), (2) a saturation run with --sat-jobs jobs present
+    at t = 0 (capacity in jobs/hour), (3) the saturation jobs one after
+    another, each alone in its own context (the one-job-per-launch sampler),
+    whose theta traces must equal those from the mix bit for bit.
+    """
+    from paper_2105_08026_amd import serve as sv
+
+    fth = synth.calibrate_threshold(np.random.default_rng(1), 0.7, 5e10, 4000.0, 0.3)
+
+    def make(job):
+        return synth.gamma_lf_1d(n=job.n, seed=job.seed, fth=fth)
+
+    def jobs_of(arr):
+        return [sv.Job(i, t, seed, n, sw) for i, (t, seed, n, sw) in enumerate(arr)]
+
+    pool = hbm.Pool(hbm.HBM_GAMMA_LF_1D, capacity=1 << 22, n_slots=128, max_cycles=5000, device="cuda:0")
+    ex = sv.PoolExecutor(pool, make, chunk=32)
+    # warm-up: graph capture and first-touch of the pool
+    sv.serve(jobs_of([(0.0, 1, 2000, 64), (0.0, 2, 50000, 96)]), ex, prefetch=False)
+
+    live = jobs_of(synth.serving_arrivals(rate=args.rate, horizon_s=args.horizon, seed=4))
+    res = sv.serve(live, ex)
+    print(f"poisson: {len(live)} jobs, p50 {res['p50_s']*1e3:.1f} ms, p99 {res['p99_s']*1e3:.1f} ms, "
+          f"mean resident {res['mean_resident']:.2f}", file=sys.stderr, flush=True)
+
+    sat_src = synth.serving_arrivals(rate=1e6, horizon_s=1.0, seed=7, job_seed0=50000)[:args.sat_jobs]
+    sat = jobs_of([(0.0, seed, n, sw) for _, seed, n, sw in sat_src])
+    wls = {j.id: make(j) for j in sat}
+    res_sat = sv.serve(sat, ex, make=lambda j: wls[j.id], prefetch=False)
+    print(f"saturation: {len(sat)} jobs in {res_sat['wall_s']:.2f} s, mean resident {res_sat['mean_resident']:.1f}",
+          file=sys.stderr, flush=True)
+    pool.close()
+
+    seq, same = 0.0, 0
+    traces = {j.id: j.trace for j in res_sat["jobs"]}
+    for j in sat:
+        s = hbm.Sampler(wls[j.id], device="cuda:0", max_cycles=j.sweeps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.run_cycles(j.sweeps)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t1
+        same += int(np.array_equal(s.theta_trace(), traces[j.id]))
+        s.close()
+    jph_sat = 3600.0 * len(sat) / res_sat["wall_s"]
+    jph_seq = 3600.0 * len(sat) / seq
+    out = {
+        "metric": METRIC, "value": jph_sat, "unit": "jobs/hour", "n_gpus": 1, "steps": len(sat), "warmup": 2,
+        "ms_per_step": 1e3 * res_sat["wall_s"] / len(sat), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded gamma-LF jobs, N log-uniform on [1e3, 3e5], budgets in {1000, 2000, 5000})",
+        "config": {"workload": "serving", "rate_per_s": args.rate, "horizon_s": args.horizon,
+                   "pool_objects": 1 << 22, "pool_slots": 128, "chunk_cycles": 32},
+        "poisson": {"jobs": len(live), "p50_s": res["p50_s"], "p99_s": res["p99_s"], "mean_s": res["mean_s"],
+                    "jobs_per_hour": res["jobs_per_hour"], "mean_resident": res["mean_resident"],
+                    "gpu_busy_frac": res["busy_s"] / res["wall_s"], "wait_for_inputs_s": res["wait_for_inputs_s"]},
+        "saturation": {"jobs": len(sat), "wall_s": res_sat["wall_s"], "jobs_per_hour": jph_sat,
+                       "p50_s": res_sat["p50_s"], "p99_s": res_sat["p99_s"],
+                       "mean_resident": res_sat["mean_resident"]},
+        "sequential": {"jobs_per_hour": jph_seq, "wall_s": seq},
+        "served_vs_sequential": jph_sat / jph_seq,
+        "alone_vs_mix_identical": f"{same}/{len(sat)}",
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -165,6 +239,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "gamma_lf_batch256":
         bench_batch(args, torch, synth, hbm)
+        return
+    if args.workload == "serving":
+        bench_serving(args, torch, synth, hbm)
         return
     make = {"gamma_lf_1d": (synth.gamma_lf_1d, 300_000), "gamma_lf_color_3d": (synth.gamma_lf_3d, 1_000_000),
             "normal_normal_1d": (synth.normal_normal_1d, 300_000), "normal_normal_3d": (synth.normal_normal_3d, 300_000)}

@@ -19,6 +19,7 @@ import numpy as np
 import torch  # imported first so the library binds to torch's HIP runtime
 
 from .build import LIB_PATH
+from .serve import TileAllocator
 
 HBM_OK, HBM_EINVAL, HBM_ENOMEM, HBM_EHIP, HBM_EDOMAIN, HBM_ESTATE, HBM_ENOSPACE = 0, -1, -2, -3, -4, -5, -6
 HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_3D = 1, 2, 3, 4
@@ -485,34 +486,31 @@ class Pool(_Chains):
         pc.n_quad, pc.capacity, pc.max_cycles, pc.snap_rows = n_quad, cap, max_cycles, 0
         self.pool_config, self.n_slots, self.max_cycles = pc, n_slots, max_cycles
         self.free_slots = list(range(n_slots - 1, -1, -1))
-        self.tiles = np.full(cap // TILE, -1, dtype=np.int64)     # slot owning each tile
+        self.alloc = TileAllocator(cap // TILE)                     # slot owning each tile
         self.resident = {}                                          # slot -> (obj_start, n)
+        self.left = {}                                              # slot -> theta steps still to run
         torch.cuda.synchronize(self.device)
         with torch.cuda.device(self.device):
             self.ctx = create_pool(pc, self.buffers, self.stream.cuda_stream)
 
-    def _find_tiles(self, nt: int):
-        run = 0
-        for t in range(self.tiles.size):
-            run = run + 1 if self.tiles[t] < 0 else 0
-            if run == nt:
-                return t - nt + 1
-        return None
+    @property
+    def tiles(self) -> np.ndarray:
+        return self.alloc.owner
 
     def fits(self, n: int) -> bool:
-        return bool(self.free_slots) and self._find_tiles(-(-n // TILE)) is not None
+        return bool(self.free_slots) and self.alloc.find(-(-n // TILE)) is not None
 
     def admit(self, wls, budgets, **cfg_kw):
         """Loads the workloads that fit, in order, and returns their slots (None where one did not fit)."""
         slots, starts, cfgs, th0, bud, placed = [], [], [], [], [], []
         for w, b in zip(wls, budgets):
             nt = -(-w.n // TILE)
-            t0 = self._find_tiles(nt) if self.free_slots else None
+            t0 = self.alloc.find(nt) if self.free_slots else None
             if t0 is None:
                 placed.append(None)
                 continue
             slot = self.free_slots.pop()
-            self.tiles[t0:t0 + nt] = slot
+            self.alloc.take(t0, nt, slot)
             o = t0 * TILE
             slots.append(slot)
             starts.append(o)
@@ -521,6 +519,7 @@ class Pool(_Chains):
             bud.append(b)
             placed.append(slot)
             self.resident[slot] = (o, w.n)
+            self.left[slot] = b if b > 0 else float("inf")
         if slots:
             # data and starting latents at their positions, then one load call
             with torch.no_grad():
@@ -537,9 +536,15 @@ class Pool(_Chains):
         return placed
 
     def _release(self, slot: int):
-        self.tiles[self.tiles == slot] = -1
+        self.alloc.release(slot)
         self.resident.pop(slot, None)
+        self.left.pop(slot, None)
         self.free_slots.append(slot)
+
+    def run_cycles(self, n: int, use_graph: bool = True):
+        run_cycles(self.ctx, n, use_graph)
+        for s in self.left:
+            self.left[s] -= n
 
     def retire(self, slot: int) -> np.ndarray:
         """Returns the slot's theta trace and frees the slot."""
@@ -552,8 +557,8 @@ class Pool(_Chains):
         return slot_info(self.ctx, slot)
 
     def finished(self):
-        """Resident slots whose budget is spent (host bookkeeping, no device read)."""
-        return [s for s in self.resident if not slot_info(self.ctx, s)["active"]]
+        """Resident slots whose budget is spent (the device stops them at exactly that cycle)."""
+        return [s for s, left in self.left.items() if left <= 0]
 
     def theta_trace(self, slot: int) -> np.ndarray:
         n = n_theta_samples(self.ctx, slot)

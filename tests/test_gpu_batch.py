@@ -125,7 +125,7 @@ def test_pool_jobs_match_alone_runs(hbm):
         for slot in pool.finished():
             j = where.pop(slot)
             info = pool.info(slot)
-            assert info["n_theta"] == budgets[j] and info["k"] == budgets[j]
+            assert info["n_theta"] == budgets[j] and info["k"] == budgets[j] and not info["active"]
             chi = pool.latents(slot)
             done[j] = (pool.retire(slot), chi)
         assert rounds < 100
@@ -194,3 +194,24 @@ def test_autotune_batch_keeps_chains(hbm):
         assert np.array_equal(b.theta_trace(j), tr), j
         assert np.array_equal(b.latents(j), chi), j
     b.close()
+
+
+def test_request_loop_results_same_alone_and_in_the_mix(hbm):
+    """The serving loop over the GPU pool: jobs arriving over time, admitted
+    by memory, batched continuously; each job's theta trace equals its run alone."""
+    from paper_2105_08026_amd import serve as sv
+    specs = [(0.00, 3100, 900, 96), (0.01, 3101, 2600, 160), (0.02, 3102, 300, 64),
+             (0.05, 3103, 1700, 128), (0.08, 3104, 2500, 64), (0.20, 3105, 700, 32)]
+    jobs = [sv.Job(i, t, seed, n, sw) for i, (t, seed, n, sw) in enumerate(specs)]
+    _say(f"request loop: {len(jobs)} jobs into a 4096-object, 3-slot pool")
+
+    def make(job):
+        return synth.gamma_lf_1d(n=job.n, seed=job.seed, fth=FTH)
+
+    pool = hbm.Pool(hbm.HBM_GAMMA_LF_1D, capacity=4096, n_slots=3, max_cycles=200)
+    res = sv.serve(jobs, sv.PoolExecutor(pool, make, chunk=16))
+    pool.close()
+    assert len(res["jobs"]) == len(jobs) and res["p99_s"] >= res["p50_s"] > 0
+    for j in res["jobs"]:
+        tr, _ = _alone(hbm, make(j), j.sweeps)
+        assert np.array_equal(j.trace, tr), j.id
