@@ -52,17 +52,78 @@ def parse():
     ap.add_argument("--job-sweeps", type=int, default=2000, help="batch workload: sweeps that make one job")
     ap.add_argument("--n", type=int, default=None, help="objects (default: 300,000; 1,000,000 for the 3-D catalog)")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--launch-shape", default="auto", choices=["auto", "1", "2", "4"],
+                    help="tiles per sweep workgroup; auto runs the autotuner during burn-in")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers 20 times (calibration run for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
 
-def cpu_baseline(wl, seconds: float):
-    """The oracle as it stands, timed on the host on a bounded sample of the workload."""
+KERNEL_SOURCES = ("device.h", "models.h", "kernels.h")
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2105_08026_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, n: int):
+    """HBM bytes per sweep-kernel launch from the committed rocprofv3 counter
+    summary for this workload, or None when the summary is missing or was
+    taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{workload}_n{n}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("| ") and line.count("|") == 3:
+                key, val = [c.strip() for c in line.strip().strip("|").split("|")]
+                vals[key] = val
+    if vals.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    fetch = float(vals["fetch_bytes_per_launch"]) / float(vals["copy_fetch_scale"])
+    write = float(vals["write_bytes_per_launch"]) / float(vals["copy_write_scale"])
+    return {"bytes_per_launch": fetch + write, "source": os.path.relpath(path, ROOT)}
+
+
+def accuracy_vs_oracle(wl, s, o):
+    """Errors of this run's FP32/FP64 results against the FP64 oracle, evaluated
+    at the GPU's own points: one more (traced) sweep at the current theta gives
+    log pi_i at X and at the proposal Y for every object; then the population
+    log-likelihood at the resulting latents."""
+    theta, _, _ = s.theta()
+    chi0 = s.state()[0]
+    tr = s.trace_sweep()
+    lx = o.log_post(theta, chi0)
+    ly = o.log_post(theta, tr[3:3 + wl.d])
+    fin = np.isfinite(ly) & np.isfinite(tr[1])
+    rel_x = np.abs(tr[0] - lx) / np.maximum(1.0, np.abs(lx))
+    rel_y = np.abs(tr[1][fin] - ly[fin]) / np.maximum(1.0, np.abs(ly[fin]))
+    chi1 = s.state()[0]
+    pl = s.pop_loglik(theta)
+    ref = o.pop_loglik(theta, chi1)
+    scale = float(np.sum(np.abs(o.pop_terms(theta, chi1))))
+    return {"objects": wl.n, "log_density_max_rel_err": float(max(rel_x.max(), rel_y.max())),
+            "log_density_median_rel_err": float(np.median(np.concatenate([rel_x, rel_y]))),
+            "pop_loglik_abs_err": abs(pl - ref), "pop_loglik_err_rel_to_sum_abs_terms": abs(pl - ref) / scale,
+            "theta": theta.tolist()}
+
+
+def cpu_baseline(wl, seconds: float, sampler=None):
+    """The oracle as it stands, timed on the host on a bounded sample of the
+    workload (and, given the GPU sampler, the accuracy of its results)."""
     import oracle
 
     oracle.build(force=False)
     o = oracle.Oracle(wl)
+    acc = accuracy_vs_oracle(wl, sampler, o) if sampler is not None else None
     st = o.initial_state()
     o.run(st, 2)                                  # first touch of the arrays
     done, t0 = 0, time.perf_counter()
@@ -70,8 +131,9 @@ def cpu_baseline(wl, seconds: float):
         o.run(st, 5)
         done += 5
     dt = time.perf_counter() - t0
-    return {"value": wl.n * done / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{done} full MWG cycles of the N={wl.n} catalog ({dt:.1f} s, FP64, OpenMP over objects)"}
+    out = {"value": wl.n * done / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{done} full MWG cycles of the N={wl.n} catalog ({dt:.1f} s, FP64, OpenMP over objects)"}
+    return out, acc
 
 
 def cpu_baseline_batch(wls, seconds: float):
@@ -238,6 +300,16 @@ def main():
     import paper_2105_08026_amd as hbm
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a plain device-to-device copy of known size: the reference for scaling
+        # the FETCH_SIZE / WRITE_SIZE counters of the sampler's kernels
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 20}), flush=True)
+        return
     if args.workload == "gamma_lf_batch256":
         bench_batch(args, torch, synth, hbm)
         return
@@ -253,8 +325,12 @@ def main():
     s = hbm.Sampler(wl, device="cuda:0", max_cycles=total)
     use_graph = not args.no_graph
 
-    # burn-in: the launch-shape autotuner's cycles, then plain warm-up cycles
-    pick, tuned = s.autotune(trial)
+    # burn-in: the launch-shape autotuner's cycles (or a fixed shape), then plain warm-up cycles
+    if args.launch_shape == "auto":
+        pick, tuned = s.autotune(trial)
+    else:
+        pick, tuned = int(args.launch_shape), [None, None, None]
+        s.set_launch(pick)
     s.run_cycles(args.warmup, use_graph=use_graph)
     torch.cuda.synchronize()
 
@@ -284,6 +360,7 @@ def main():
     updates = wl.n * args.steps / wall
     bpu = BYTES_PER_UPDATE[wl.name]
     achieved = bpu * wl.n / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    traffic = measured_traffic(wl.name, wl.n)
     out = {
         "metric": METRIC,
         "value": updates,
@@ -305,14 +382,18 @@ def main():
         "breakdown_ms": {"step": 1e3 * wall / args.steps, "sweep_kernel": kern_ms,
                          "step_with_event_timing": 1e3 * wall_ev / args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": (traffic["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9) if traffic else None,
+                     "traffic_bytes_per_launch": traffic["bytes_per_launch"] if traffic else None,
+                     "algorithmic_bytes_per_launch": bpu * wl.n, "traffic_source": traffic["source"] if traffic else
+                     "no counter summary for the current kernel sources",
                      "kernel": f"sweep_kernel<{wl.name}>", "bytes_per_update": bpu,
                      "launches_timed": n_launch},
         "accept_rate_last_sweep": stats["n_acc"] / wl.n,
         "theta_last": th[-1].tolist(),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"], out["accuracy_vs_oracle"] = cpu_baseline(wl, args.cpu_seconds, sampler=s)
     s.close()
     print(json.dumps(out), flush=True)
 

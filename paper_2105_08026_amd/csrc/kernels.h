@@ -218,37 +218,49 @@ __device__ __forceinline__ double block_log_z(const double *zc, const double *qx
     return log(v[0]);
 }
 
-// ---------------------------------------------------------------------------
-// The sweep.  Workgroups 0 .. n_ds-1 are side workgroups, one per dataset:
-// ln Z at its pending proposal and every FP64 value of its theta step that
-// the objects do not decide.  Every other workgroup updates one tile of 256
-// objects of one dataset and writes the tile's FP64 partial sums.  No
-// workgroup waits on another: the epilogue kernel that follows on the
-// stream reduces the partials.
-// ---------------------------------------------------------------------------
-// One object's RAM step (steps (a)-(e) of the sweep) and its contributions
-// to the tile sums; returns whether the move was accepted.
+// The per-dataset scalars a tile needs, read together right after the
+// tile's dataset is known (one round of scalar loads, not a chain).
+template <typename T>
+struct TileView {
+    int64_t k;                 // sweep being done
+    int64_t obj_start, n;
+    int64_t snap_cap;
+    uint32_t key0, key1;
+    int32_t thin;
+    int32_t active;
+    T eta, astar;
+};
+
+template <class M>
+__device__ __forceinline__ TileView<typename M::T> tile_view(const SweepArgs<typename M::T> &a, int ds)
+{
+    using T = typename M::T;
+    const CycleState &c = a.cs[ds];
+    const Statics &s = a.st[ds];
+    return TileView<T>{c.k + 1, s.obj_start, s.n, s.snap_cap, s.key0, s.key1, s.thin, c.active,
+                       static_cast<T>(c.eta_next), static_cast<T>(s.alpha_star)};
+}
+
+// One object's RAM step and its contributions to the tile sums, from the
+// object's state already loaded into registers; returns whether the move
+// was accepted.  i: position in the packed arrays; il: index within its
+// dataset (the random-number counter).
 template <class M, bool kTrace>
-__device__ __forceinline__ bool update_object(const SweepArgs<typename M::T> &a, int ds, int64_t il, double *v)
+__device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, int ds, const TileView<typename M::T> &tv,
+                                            int64_t il, int64_t i, typename M::T *x, typename M::T *S, uint32_t nacc,
+                                            const typename M::Obj &o, double *v)
 {
     using T = typename M::T;
     constexpr int D = M::D, NC = M::NC;
     const CycleState *cs = a.cs + ds;
     const Statics &st = a.st[ds];
-    const int64_t i = st.obj_start + il;             // object in the packed arrays
     const int64_t n = a.n_total;
-    const int64_t k = cs->k + 1;
+    const int64_t k = tv.k;
     const T *kc = kc_of<T>(const_cast<CycleState *>(cs));
-    const T eta = static_cast<T>(cs->eta_next);
-    const T astar = static_cast<T>(st.alpha_star);
-    T x[D], S[NC], U[D], y[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) x[j] = a.chi[j * n + i];
-#pragma unroll
-    for (int e = 0; e < NC; ++e) S[e] = a.chol[e * n + i];
-    uint32_t nacc = a.acc[i];
-    const typename M::Obj o = M::load(a.dd, i, n);
-    const Block4 b = philox(static_cast<uint32_t>(il), static_cast<uint32_t>(k), 0u, 0u, st.key0, st.key1);
+    const T eta = tv.eta;
+    const T astar = tv.astar;
+    T U[D], y[D];
+    const Block4 b = philox(static_cast<uint32_t>(il), static_cast<uint32_t>(k), 0u, 0u, tv.key0, tv.key1);
     normals<T, D>(b, U);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -285,9 +297,9 @@ __device__ __forceinline__ bool update_object(const SweepArgs<typename M::T> &a,
 #pragma unroll
         for (int j = 0; j < D; ++j) a.trace[(3 + j) * n + i] = y[j];
     }
-    if (a.snaps != nullptr && st.thin > 0 && k % st.thin == 0) {
-        const int64_t snap = k / st.thin - 1;
-        if (snap < st.snap_cap) {
+    if (a.snaps != nullptr && tv.thin > 0 && k % tv.thin == 0) {
+        const int64_t snap = k / tv.thin - 1;
+        if (snap < tv.snap_cap) {
 #pragma unroll
             for (int j = 0; j < D; ++j) a.snaps[(snap * D + j) * n + i] = x[j];
         }
@@ -336,14 +348,43 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         return;
     }
 
+    using T = typename M::T;
+    constexpr int D = M::D, NC = M::NC;
     const int g0 = (static_cast<int>(blockIdx.x) - a.n_ds) * TPW;     // first tile
+    // A dataset's objects start on a tile boundary, so position i of tile g
+    // is g * 256 + lane whatever the dataset.  The objects' state is loaded
+    // before the tile's dataset is looked up, so the loads overlap the table
+    // and state lookups; every position below n_total lies inside the
+    // caller's buffers (positions between datasets are read, never written).
+    T xs[TPW][D], Ss[TPW][NC];
+    uint32_t na[TPW];
+    typename M::Obj os[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
+        if (g0 + u < a.n_tiles_total && i < a.n_total) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) xs[u][j] = a.chi[j * a.n_total + i];
+#pragma unroll
+            for (int e = 0; e < NC; ++e) Ss[u][e] = a.chol[e * a.n_total + i];
+            na[u] = a.acc[i];
+            os[u] = M::load(a.dd, i, a.n_total);
+        }
+    }
     int dss[TPW];
+    TileView<T> tv[TPW];
     bool any = false;
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
         const int g = g0 + u;
-        int ds = (g < a.n_tiles_total) ? a.tile_ds[g] : -1;
-        if (ds >= 0 && !a.cs[ds].active) ds = -1;     // no epilogue reads this tile
+        // a one-slot context needs no table: the object range check below suffices
+        int ds = (g >= a.n_tiles_total) ? -1 : (a.n_ds == 1 ? 0 : a.tile_ds[g]);
+        tv[u] = tile_view<M>(a, ds < 0 ? 0 : ds);      // slot 0 always exists
+        // issue every scalar load of the view now, as one round (the compiler
+        // would otherwise chain them behind the branches below)
+        asm volatile("" ::"s"(tv[u].k), "s"(tv[u].obj_start), "s"(tv[u].n), "s"(tv[u].key0), "s"(tv[u].key1),
+                     "s"(tv[u].active));
+        if (ds >= 0 && !tv[u].active) ds = -1;          // no epilogue reads this tile
         dss[u] = ds;
         any = any || ds >= 0;
     }
@@ -356,8 +397,10 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         accepted[u] = false;
         const int ds = dss[u];
         if (ds < 0) continue;
-        const int64_t il = static_cast<int64_t>(g0 + u - a.st[ds].tile_start) * kBlock + threadIdx.x;
-        if (il < a.st[ds].n) accepted[u] = update_object<M, kTrace>(a, ds, il, v + 2 * u);
+        const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
+        const int64_t il = i - tv[u].obj_start;
+        if (il >= 0 && il < tv[u].n)
+            accepted[u] = step_object<M, kTrace>(a, ds, tv[u], il, i, xs[u], Ss[u], na[u], os[u], v + 2 * u);
     }
     // accepted moves: one ballot per wavefront and tile
 #pragma unroll
@@ -399,12 +442,13 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
     __shared__ Precomp pc;
     __shared__ double red[3][kWavesPerBlock];
     const int ds = blockIdx.x;
-    if (!a.cs[ds].active) return;
     const Statics &st = a.st[ds];
-    const int32_t t0 = st.tile_start, nt = st.n_tiles, ntt = a.n_tiles_total;
+    // read together: the flag and the tile range
+    const int32_t active = a.cs[ds].active, t0 = st.tile_start, nt = st.n_tiles, ntt = a.n_tiles_total;
+    if (!active) return;
     // tile partials of this dataset, structure of arrays [3][n_tiles_total]
     double v[3] = {0.0, 0.0, 0.0};
-#pragma unroll 4
+#pragma unroll 8
     for (int t = threadIdx.x; t < nt; t += kBlock) {
         v[0] += a.partials[t0 + t];
         v[1] += a.partials[ntt + t0 + t];
