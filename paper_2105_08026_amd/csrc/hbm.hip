@@ -218,6 +218,9 @@ struct Ops {
         e.theta_trace = c->theta_trace;
         e.trace_stride = c->pool.max_cycles;
         e.n_tiles_total = c->n_tiles;
+        e.single = c->n_slots == 1;
+        e.single_t0 = c->slots[0].tile_start;
+        e.single_nt = c->slots[0].loaded ? c->slots[0].n_tiles : 0;
         return e;
     }
 
@@ -485,6 +488,19 @@ hbm_status drain_timing(CtxImpl *c)
     return HBM_OK;
 }
 
+// A one-slot context bakes its slot's tile range into the kernel
+// arguments; a captured graph is dropped when that range changes.
+hbm_status drop_graph(CtxImpl *c)
+{
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
+    if (c->graph) HIPCHK(c, hipGraphDestroy(c->graph));
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_len = 0;
+    return HBM_OK;
+}
+
 hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, void *hip_stream, CtxImpl **out)
 {
     ModelInfo mi;
@@ -683,6 +699,7 @@ hbm_status load(CtxImpl *c, int32_t count, const int32_t *slots, const int64_t *
         return fail(c, HBM_EDOMAIN, msg);
     }
     c->h_tile_ds.swap(owner);
+    if (c->n_slots == 1 && (s = drop_graph(c)) != HBM_OK) return s;
     for (int32_t q = 0; q < count; ++q) {
         Slot &sl = c->slots[slots[q]];
         sl = Slot{};
@@ -748,6 +765,7 @@ hbm_status unload_dataset(hbm_ctx *ctx, int32_t slot)
                                  sizeof(zero_n), hipMemcpyHostToDevice, c->stream));
         if ((s = put_field<int32_t>(c, slot, offsetof(CycleState, active), 0)) != HBM_OK) return s;
         sl = Slot{};
+        if (c->n_slots == 1 && (s = drop_graph(c)) != HBM_OK) return s;
         return HBM_OK;
     });
 }
@@ -1109,12 +1127,8 @@ hbm_status set_launch(hbm_ctx *ctx, int32_t tiles_per_group)
         if (tiles_per_group != 1 && tiles_per_group != 2 && tiles_per_group != 4)
             return fail(c, HBM_EINVAL, "tiles_per_group must be 1, 2 or 4");
         if (tiles_per_group == c->tpw) return HBM_OK;
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
-        if (c->graph) HIPCHK(c, hipGraphDestroy(c->graph));
-        c->graph_exec = nullptr;
-        c->graph = nullptr;
-        c->graph_len = 0;
+        hbm_status st = drop_graph(c);
+        if (st != HBM_OK) return st;
         c->tpw = tiles_per_group;
         return HBM_OK;
     });

@@ -430,6 +430,8 @@ struct EpiArgs {
     double *theta_trace;       // [n_ds][trace_stride][p]
     int64_t trace_stride;
     int32_t n_tiles_total;
+    // one-slot contexts: the slot's tile range, so the partial loads need no lookup
+    int32_t single, single_t0, single_nt;
 };
 
 // Epilogue of a sweep, one workgroup per dataset: fixed-order reduction of
@@ -443,9 +445,10 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
     __shared__ double red[3][kWavesPerBlock];
     const int ds = blockIdx.x;
     const Statics &st = a.st[ds];
-    // read together: the flag and the tile range
-    const int32_t active = a.cs[ds].active, t0 = st.tile_start, nt = st.n_tiles, ntt = a.n_tiles_total;
-    if (!active) return;
+    const int32_t t0 = a.single ? a.single_t0 : st.tile_start, nt = a.single ? a.single_nt : st.n_tiles;
+    const int32_t ntt = a.n_tiles_total;
+    // Every load is issued before the dataset's flag is looked at (it arrives
+    // with the staged state); the values of a dataset that is off are unused.
     // tile partials of this dataset, structure of arrays [3][n_tiles_total]
     double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll 8
@@ -460,6 +463,7 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
         for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
     }
     stage_in(c, a.cs + ds);              // its barrier also publishes pc
+    if (!c.active) return;               // uniform: read from LDS after the barrier
     block_sum<3>(v, red);
     if (threadIdx.x == 0) {
         finish_sweep<M>(c, st, v, pc.zraw, pc);
