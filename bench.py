@@ -133,6 +133,16 @@ def cpu_baseline(wl, seconds: float, sampler=None):
     dt = time.perf_counter() - t0
     out = {"value": wl.n * done / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
            "sample": f"{done} full MWG cycles of the N={wl.n} catalog ({dt:.1f} s, FP64, OpenMP over objects)"}
+    # the same on one core, for a quarter of the time
+    cores = oracle.num_threads()
+    oracle.set_num_threads(1)
+    done1, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < seconds / 4:
+        o.run(st, 1)
+        done1 += 1
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
+    out["one_core"] = {"value": wl.n * done1 / dt1, "unit": "updates/s", "cycles": done1, "seconds": dt1}
     return out, acc
 
 

@@ -256,6 +256,21 @@ HBM_API hbm_status set_theta(hbm_ctx *ctx, int32_t slot, const double *theta, co
  * [3 + d][C].  Synchronous. */
 HBM_API hbm_status ram_sweep_trace(hbm_ctx *ctx, void *trace);
 
+/* Checkpoint and resume of the library-held state: every slot's theta
+ * chain (theta, S_theta, the pending proposal and its constants, the sweep
+ * and theta-step counters, budgets) and its theta trace.  The latent
+ * buffers are the caller's: save and restore them alongside.  get_state
+ * with blob NULL returns the size in *size; a *size that is too small gives
+ * HBM_ENOSPACE with the size needed; not allowed while a ram_sweep waits for
+ * its theta_step (HBM_ESTATE).  set_state needs a context of the same shape
+ * (model, slots, capacity, max_cycles) holding datasets at the same
+ * positions (e.g. created by the same init_chains / init_batch / loads);
+ * the datasets' data and configuration are not part of the blob.  A chain
+ * resumed this way continues exactly as the saved one would have.
+ * Synchronous. */
+HBM_API hbm_status get_state(hbm_ctx *ctx, void *blob, size_t *size);
+HBM_API hbm_status set_state(hbm_ctx *ctx, const void *blob, size_t size);
+
 /* Statistics of a slot's last sweep and theta step: out[0] sum log f(chi; theta),
  * out[1] sum of per-object log f differences at theta', out[2] ln Z(theta),
  * out[3] ln Z(theta'), out[4] Delta of the last theta step, out[5] its

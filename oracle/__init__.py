@@ -62,6 +62,8 @@ def lib(path: str = None):
         L.orc_log_post.argtypes = [P, P, P, P]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.argtypes = [i32]
+        L.orc_set_num_threads.restype = None
         L.orc_sweep.argtypes = [P, i64, P, P, P, P, P]
         L.orc_theta_proposal.argtypes = [P, i64, P, P, P]
         L.orc_theta_step.argtypes = [P, i64, P, P, P, P]
@@ -108,6 +110,10 @@ def variates(seed: int, ctr, lib_path: str = None):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int):
+    lib().orc_set_num_threads(int(n))
 
 
 def gauss_legendre(n: int, a: float, b: float, lib_path: str = None):

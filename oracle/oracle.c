@@ -371,6 +371,15 @@ int orc_num_threads(void)
 #endif
 }
 
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_dims(const orc_ctx *c, int *d, int *p, int *m)
 {
     *d = c->d;

@@ -54,6 +54,7 @@ orc_ctx *orc_new(int model, int64_t n, const double *data, const double *consts,
 void orc_free(orc_ctx *c);
 int orc_dims(const orc_ctx *c, int *d, int *p, int *m);
 int orc_num_threads(void);   /* threads the latent sweep uses */
+void orc_set_num_threads(int n);   /* sets it (timing on one core) */
 
 /* log member likelihood and log population density of object i at x[d]. */
 void orc_log_terms(const orc_ctx *c, int64_t i, const double *x, const double *theta,

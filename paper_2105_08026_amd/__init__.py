@@ -27,8 +27,8 @@ HBM_FP64, HBM_FP32 = 1, 2
 
 EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
             "ram_sweep", "pop_loglik", "theta_step", "run_cycles", "get_samples", "get_theta", "set_theta",
-            "ram_sweep_trace", "get_stats", "set_launch", "autotune", "kernel_timing", "read_kernel_timing",
-            "last_error", "destroy_chains")
+            "ram_sweep_trace", "get_state", "set_state", "get_stats", "set_launch", "autotune", "kernel_timing",
+            "read_kernel_timing", "last_error", "destroy_chains")
 
 TILE = 256   # objects per tile: datasets in a pool start on multiples of this
 
@@ -94,6 +94,8 @@ def lib():
             "set_theta": [P, i32, P, P, i64],
             "ram_sweep_trace": [P, P],
             "get_stats": [P, i32, P],
+            "get_state": [P, P, P],
+            "set_state": [P, P, ctypes.c_size_t],
             "set_launch": [P, i32],
             "autotune": [P, i32, P, P],
             "kernel_timing": [P, i32],
@@ -232,6 +234,20 @@ def set_theta(ctx, theta, chol_theta, k: int, slot: int = 0):
 
 def ram_sweep_trace(ctx, trace_ptr: int):
     _check(lib().ram_sweep_trace(ctx, ctypes.c_void_p(trace_ptr)), ctx)
+
+
+def get_state(ctx) -> bytes:
+    """The library-held chain state of every slot (see set_state)."""
+    n = ctypes.c_size_t()
+    _check(lib().get_state(ctx, None, ctypes.byref(n)), ctx)
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().get_state(ctx, buf, ctypes.byref(n)), ctx)
+    return buf.raw[: n.value]
+
+
+def set_state(ctx, blob: bytes):
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(lib().set_state(ctx, buf, len(blob)), ctx)
 
 
 def get_stats(ctx, slot: int = 0) -> dict:
@@ -398,6 +414,16 @@ class Sampler(_Chains):
         torch.cuda.synchronize(self.device)
         return (self.chi.double().cpu().numpy(), self.chol.double().cpu().numpy(),
                 self.acc.cpu().numpy().view(np.uint32))
+
+    def checkpoint(self):
+        """(library state blob, chi, chol, acc) from which `restore` resumes the chain exactly."""
+        blob = get_state(self.ctx)
+        return (blob, *self.state())
+
+    def restore(self, ckpt):
+        blob, chi, chol, acc = ckpt
+        self.load_state(chi, chol, acc)
+        set_state(self.ctx, blob)
 
     def load_state(self, chi, chol, acc):
         """Overwrite the latent buffers from host arrays (lockstep replay)."""

@@ -135,6 +135,8 @@ hbm_status hip_fail(CtxImpl *c, hipError_t e, const char *what)
 
 int32_t tiles_for(int64_t n) { return static_cast<int32_t>((n + kBlock - 1) / kBlock); }
 
+bool single(const CtxImpl *c);
+
 // Events that time one sweep-kernel launch.
 hipEvent_t take_event(CtxImpl *c)
 {
@@ -185,27 +187,36 @@ struct Ops {
             c->ev_pending.push_back(e0);
             c->ev_pending.push_back(e1);
         }
-        if (trace) launch_sweep<true, 1>(c, grid, a, e0, e1);
-        else if (tpw == 4) launch_sweep<false, 4>(c, grid, a, e0, e1);
-        else if (tpw == 2) launch_sweep<false, 2>(c, grid, a, e0, e1);
-        else launch_sweep<false, 1>(c, grid, a, e0, e1);
+        const bool one = single(c);
+        if (trace) launch_sweep<true, 1, false>(c, grid, a, e0, e1);
+        else if (one && tpw == 4) launch_sweep<false, 4, true>(c, grid, a, e0, e1);
+        else if (one && tpw == 2) launch_sweep<false, 2, true>(c, grid, a, e0, e1);
+        else if (one) launch_sweep<false, 1, true>(c, grid, a, e0, e1);
+        else if (tpw == 4) launch_sweep<false, 4, false>(c, grid, a, e0, e1);
+        else if (tpw == 2) launch_sweep<false, 2, false>(c, grid, a, e0, e1);
+        else launch_sweep<false, 1, false>(c, grid, a, e0, e1);
         LAUNCHCHK(c, "sweep_kernel");
         const EpiArgs e = epi_args(c);
-        if (full)
-            hipLaunchKernelGGL((epilogue_kernel<M, true>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, e);
+        if (full && one)
+            hipLaunchKernelGGL((epilogue_kernel<M, true, true>), dim3(1), dim3(kBlock), 0, c->stream, e);
+        else if (full)
+            hipLaunchKernelGGL((epilogue_kernel<M, true, false>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, e);
+        else if (one)
+            hipLaunchKernelGGL((epilogue_kernel<M, false, true>), dim3(1), dim3(kBlock), 0, c->stream, e);
         else
-            hipLaunchKernelGGL((epilogue_kernel<M, false>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, e);
+            hipLaunchKernelGGL((epilogue_kernel<M, false, false>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, e);
         LAUNCHCHK(c, "epilogue_kernel");
         return HBM_OK;
     }
 
-    template <bool kTrace, int TPW>
+    template <bool kTrace, int TPW, bool kSingle>
     static void launch_sweep(CtxImpl *c, dim3 grid, const SweepArgs<T> &a, hipEvent_t e0, hipEvent_t e1)
     {
         if (e0)
-            hipExtLaunchKernelGGL((sweep_kernel<M, kTrace, TPW>), grid, dim3(kBlock), 0, c->stream, e0, e1, 0, a);
+            hipExtLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle>), grid, dim3(kBlock), 0, c->stream, e0, e1,
+                                  0, a);
         else
-            hipLaunchKernelGGL((sweep_kernel<M, kTrace, TPW>), grid, dim3(kBlock), 0, c->stream, a);
+            hipLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle>), grid, dim3(kBlock), 0, c->stream, a);
     }
 
     static EpiArgs epi_args(CtxImpl *c)
@@ -218,9 +229,6 @@ struct Ops {
         e.theta_trace = c->theta_trace;
         e.trace_stride = c->pool.max_cycles;
         e.n_tiles_total = c->n_tiles;
-        e.single = c->n_slots == 1;
-        e.single_t0 = c->slots[0].tile_start;
-        e.single_nt = c->slots[0].loaded ? c->slots[0].n_tiles : 0;
         return e;
     }
 
@@ -488,8 +496,15 @@ hbm_status drain_timing(CtxImpl *c)
     return HBM_OK;
 }
 
-// A one-slot context bakes its slot's tile range into the kernel
-// arguments; a captured graph is dropped when that range changes.
+// One dataset covering every position of a one-slot context (the
+// init_chains case): the launches take the table-free kernel variants.
+bool single(const CtxImpl *c)
+{
+    return c->n_slots == 1 && c->slots[0].loaded && c->slots[0].obj_start == 0 && c->slots[0].n == c->cap;
+}
+
+// A one-slot context picks its kernel variants from its slot's placement;
+// a captured graph is dropped when that changes.
 hbm_status drop_graph(CtxImpl *c)
 {
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1098,6 +1113,134 @@ hbm_status ram_sweep_trace(hbm_ctx *ctx, void *trace)
             }
         if ((st = read_all(c)) != HBM_OK) return st;
         return check_flags(c);
+    });
+}
+
+namespace {
+
+// Checkpoint blob: header, one record per slot, every slot's device
+// theta-chain state, then every slot's theta trace rows.
+constexpr uint64_t kStateMagic = 0x4554415453424d48ull;   // "HBMSTATE"
+
+struct StateHeader {
+    uint64_t magic;
+    uint32_t version;
+    int32_t model;
+    int32_t n_slots;
+    int32_t p;
+    int64_t cap;
+    int64_t max_cycles;
+    int64_t state_size;        // sizeof(CycleState)
+    int64_t bytes;             // whole blob
+};
+
+struct SlotRecord {
+    int32_t loaded, active, sums_ready, thin;
+    int64_t n, obj_start, k, n_theta, budget, trace_cap, snap_cap;
+};
+
+size_t state_bytes(const CtxImpl *c)
+{
+    size_t b = sizeof(StateHeader) + (sizeof(SlotRecord) + sizeof(CycleState)) * c->n_slots;
+    for (const Slot &sl : c->slots) b += sizeof(double) * c->p * (sl.loaded ? sl.n_theta : 0);
+    return b;
+}
+
+}  // namespace
+
+hbm_status get_state(hbm_ctx *ctx, void *blob, size_t *size)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (!size) return fail(c, HBM_EINVAL, "size must be non-NULL");
+        for (const Slot &sl : c->slots)
+            if (sl.sums_ready) return fail(c, HBM_ESTATE, "a ram_sweep is waiting for its theta_step");
+        const size_t need = state_bytes(c);
+        if (!blob) {
+            *size = need;
+            return HBM_OK;
+        }
+        if (*size < need) {
+            *size = need;
+            return fail(c, HBM_ENOSPACE, "state buffer too small");
+        }
+        hbm_status st = read_all(c);
+        if (st != HBM_OK) return st;
+        char *out = static_cast<char *>(blob);
+        StateHeader h{kStateMagic, 1u, c->pool.model, c->n_slots, c->p, c->cap, c->pool.max_cycles,
+                      static_cast<int64_t>(sizeof(CycleState)), static_cast<int64_t>(need)};
+        std::memcpy(out, &h, sizeof(h));
+        out += sizeof(h);
+        for (const Slot &sl : c->slots) {
+            SlotRecord r{sl.loaded, sl.active, sl.sums_ready, sl.thin, sl.n, sl.obj_start, sl.k, sl.n_theta,
+                         sl.budget, sl.trace_cap, sl.snap_cap};
+            std::memcpy(out, &r, sizeof(r));
+            out += sizeof(r);
+        }
+        std::memcpy(out, c->h_cs.data(), sizeof(CycleState) * c->n_slots);
+        out += sizeof(CycleState) * c->n_slots;
+        for (int32_t j = 0; j < c->n_slots; ++j) {
+            const Slot &sl = c->slots[j];
+            if (!sl.loaded || sl.n_theta == 0) continue;
+            const size_t bytes = sizeof(double) * c->p * sl.n_theta;
+            HIPCHK(c, hipMemcpy(out, c->theta_trace + static_cast<size_t>(j) * c->pool.max_cycles * c->p, bytes,
+                                hipMemcpyDeviceToHost));
+            out += bytes;
+        }
+        *size = need;
+        return HBM_OK;
+    });
+}
+
+hbm_status set_state(hbm_ctx *ctx, const void *blob, size_t size)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (!blob || size < sizeof(StateHeader)) return fail(c, HBM_EINVAL, "state blob missing or truncated");
+        StateHeader h;
+        std::memcpy(&h, blob, sizeof(h));
+        if (h.magic != kStateMagic || h.version != 1u) return fail(c, HBM_EINVAL, "not a state blob of this library");
+        if (h.model != c->pool.model || h.n_slots != c->n_slots || h.p != c->p || h.cap != c->cap ||
+            h.max_cycles != c->pool.max_cycles || h.state_size != static_cast<int64_t>(sizeof(CycleState)) ||
+            h.bytes != static_cast<int64_t>(size))
+            return fail(c, HBM_EINVAL, "state blob is for a differently shaped context");
+        const char *in = static_cast<const char *>(blob) + sizeof(h);
+        std::vector<SlotRecord> recs(c->n_slots);
+        std::memcpy(recs.data(), in, sizeof(SlotRecord) * c->n_slots);
+        in += sizeof(SlotRecord) * c->n_slots;
+        size_t need = sizeof(StateHeader) + (sizeof(SlotRecord) + sizeof(CycleState)) * c->n_slots;
+        for (int32_t j = 0; j < c->n_slots; ++j) {
+            const SlotRecord &r = recs[j];
+            const Slot &sl = c->slots[j];
+            if (r.loaded != static_cast<int32_t>(sl.loaded) || (r.loaded && (r.n != sl.n || r.obj_start != sl.obj_start)))
+                return fail(c, HBM_EINVAL, "slot " + std::to_string(j) + " holds a different dataset placement");
+            if (r.loaded && (r.n_theta < 0 || r.n_theta > sl.trace_cap || r.k < 0))
+                return fail(c, HBM_EINVAL, "slot " + std::to_string(j) + ": counters out of range");
+            need += r.loaded ? sizeof(double) * c->p * r.n_theta : 0;
+        }
+        if (need != size) return fail(c, HBM_EINVAL, "state blob size does not match its contents");
+        std::vector<CycleState> cs(c->n_slots);
+        std::memcpy(cs.data(), in, sizeof(CycleState) * c->n_slots);
+        in += sizeof(CycleState) * c->n_slots;
+        HIPCHK(c, hipMemcpyAsync(c->cs, cs.data(), sizeof(CycleState) * c->n_slots, hipMemcpyHostToDevice, c->stream));
+        for (int32_t j = 0; j < c->n_slots; ++j) {
+            const SlotRecord &r = recs[j];
+            if (!r.loaded || r.n_theta == 0) continue;
+            const size_t bytes = sizeof(double) * c->p * r.n_theta;
+            HIPCHK(c, hipMemcpyAsync(c->theta_trace + static_cast<size_t>(j) * c->pool.max_cycles * c->p, in, bytes,
+                                     hipMemcpyHostToDevice, c->stream));
+            in += bytes;
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int32_t j = 0; j < c->n_slots; ++j) {
+            Slot &sl = c->slots[j];
+            const SlotRecord &r = recs[j];
+            if (!r.loaded) continue;
+            sl.active = r.active != 0;
+            sl.sums_ready = r.sums_ready != 0;
+            sl.k = r.k;
+            sl.n_theta = r.n_theta;
+            sl.budget = r.budget;
+        }
+        return HBM_OK;
     });
 }
 

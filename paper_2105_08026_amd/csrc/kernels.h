@@ -317,7 +317,10 @@ __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, i
 // another: the epilogue kernel that follows on the stream reduces the
 // partials.
 // ---------------------------------------------------------------------------
-template <class M, bool kTrace, int TPW>
+// kSingle: the context holds one dataset covering every position (object i
+// of the dataset at position i), so tiles need no table and no per-dataset
+// placement.
+template <class M, bool kTrace, int TPW, bool kSingle>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> a)
 {
     __shared__ double red[2 * TPW][kWavesPerBlock];
@@ -377,13 +380,18 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
         const int g = g0 + u;
-        // a one-slot context needs no table: the object range check below suffices
-        int ds = (g >= a.n_tiles_total) ? -1 : (a.n_ds == 1 ? 0 : a.tile_ds[g]);
-        tv[u] = tile_view<M>(a, ds < 0 ? 0 : ds);      // slot 0 always exists
+        int ds;
+        if constexpr (kSingle) {
+            ds = (g < a.n_tiles_total) ? 0 : -1;
+            tv[u] = tile_view<M>(a, 0);
+        } else {
+            ds = (g < a.n_tiles_total) ? a.tile_ds[g] : -1;
+            tv[u] = tile_view<M>(a, ds < 0 ? 0 : ds);      // slot 0 always exists
+        }
         // issue every scalar load of the view now, as one round (the compiler
         // would otherwise chain them behind the branches below)
         asm volatile("" ::"s"(tv[u].k), "s"(tv[u].obj_start), "s"(tv[u].n), "s"(tv[u].key0), "s"(tv[u].key1),
-                     "s"(tv[u].active));
+                     "s"(tv[u].active), "s"(tv[u].eta));
         if (ds >= 0 && !tv[u].active) ds = -1;          // no epilogue reads this tile
         dss[u] = ds;
         any = any || ds >= 0;
@@ -398,9 +406,10 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         const int ds = dss[u];
         if (ds < 0) continue;
         const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
-        const int64_t il = i - tv[u].obj_start;
-        if (il >= 0 && il < tv[u].n)
-            accepted[u] = step_object<M, kTrace>(a, ds, tv[u], il, i, xs[u], Ss[u], na[u], os[u], v + 2 * u);
+        const int64_t il = kSingle ? i : i - tv[u].obj_start;
+        if (kSingle ? (i < a.n_total) : (il >= 0 && il < tv[u].n))
+            accepted[u] = step_object<M, kTrace>(a, kSingle ? 0 : ds, tv[u], il, i, xs[u], Ss[u], na[u], os[u],
+                                                 v + 2 * u);
     }
     // accepted moves: one ballot per wavefront and tile
 #pragma unroll
@@ -430,23 +439,21 @@ struct EpiArgs {
     double *theta_trace;       // [n_ds][trace_stride][p]
     int64_t trace_stride;
     int32_t n_tiles_total;
-    // one-slot contexts: the slot's tile range, so the partial loads need no lookup
-    int32_t single, single_t0, single_nt;
 };
 
 // Epilogue of a sweep, one workgroup per dataset: fixed-order reduction of
 // the dataset's tile partials, bookkeeping, then (kFull) the theta step,
 // then the proposal for the next sweep.
-template <class M, bool kFull>
+template <class M, bool kFull, bool kSingle>
 __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
     __shared__ double red[3][kWavesPerBlock];
-    const int ds = blockIdx.x;
+    const int ds = kSingle ? 0 : static_cast<int>(blockIdx.x);
     const Statics &st = a.st[ds];
-    const int32_t t0 = a.single ? a.single_t0 : st.tile_start, nt = a.single ? a.single_nt : st.n_tiles;
     const int32_t ntt = a.n_tiles_total;
+    const int32_t t0 = kSingle ? 0 : st.tile_start, nt = kSingle ? ntt : st.n_tiles;
     // Every load is issued before the dataset's flag is looked at (it arrives
     // with the staged state); the values of a dataset that is off are unused.
     // tile partials of this dataset, structure of arrays [3][n_tiles_total]

@@ -215,3 +215,50 @@ def test_request_loop_results_same_alone_and_in_the_mix(hbm):
     for j in res["jobs"]:
         tr, _ = _alone(hbm, make(j), j.sweeps)
         assert np.array_equal(j.trace, tr), j.id
+
+
+@pytest.mark.parametrize("make", [lambda: synth.gamma_lf_1d(n=3000, seed=72, fth=FTH),
+                                  lambda: synth.normal_normal_3d(n=700, seed=9)], ids=["lf1d", "nn3d"])
+def test_checkpoint_resume_continues_exactly(hbm, make):
+    wl = make()
+    _say(f"checkpoint after 40 cycles, resume in a new context, 37 more: {wl.name} N={wl.n}")
+    a = hbm.Sampler(wl, max_cycles=100)
+    a.run_cycles(40)
+    ck = a.checkpoint()
+    a.run_cycles(37)
+    ref_tr, ref_chi = a.theta_trace(), a.state()[0]
+    a.close()
+    b = hbm.Sampler(wl, max_cycles=100)
+    b.restore(ck)
+    assert b.theta()[2] == 40 and hbm.n_theta_samples(b.ctx) == 40
+    b.run_cycles(37)
+    assert np.array_equal(b.theta_trace(), ref_tr)
+    assert np.array_equal(b.state()[0], ref_chi)
+    other = hbm.Sampler(synth.gamma_lf_1d(n=2000, seed=73, fth=FTH), max_cycles=100)
+    with pytest.raises(hbm.HbmError, match="differently shaped|different dataset"):
+        hbm.set_state(other.ctx, ck[0])
+    other.close()
+    b.close()
+
+
+def test_batch_checkpoint_resume(hbm):
+    wls = _lf_set(4, 1500, 300, 3000)
+    _say(f"batch checkpoint/resume, N={[w.n for w in wls]}")
+    a = hbm.Batch(wls, max_cycles=90)
+    a.run_cycles(33)
+    blob = hbm.get_state(a.ctx)
+    torch.cuda.synchronize()
+    bufs = [t.clone() for t in (a.chi, a.chol, a.acc)]
+    a.run_cycles(50)
+    ref = [a.theta_trace(j) for j in range(len(wls))]
+    b = hbm.Batch(wls, max_cycles=90)
+    with torch.no_grad():
+        for dst, src in zip((b.chi, b.chol, b.acc), bufs):
+            dst.copy_(src)
+    torch.cuda.synchronize()
+    hbm.set_state(b.ctx, blob)
+    b.run_cycles(50)
+    for j in range(len(wls)):
+        assert np.array_equal(b.theta_trace(j), ref[j]), j
+    a.close()
+    b.close()
