@@ -248,7 +248,7 @@ __device__ __forceinline__ TileView<typename M::T> tile_view(const SweepArgs<typ
 template <class M, bool kTrace>
 __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, int ds, const TileView<typename M::T> &tv,
                                             int64_t il, int64_t i, typename M::T *x, typename M::T *S, uint32_t nacc,
-                                            const typename M::Obj &o, double *v)
+                                            const typename M::Obj &o, double *v, bool valid = true)
 {
     using T = typename M::T;
     constexpr int D = M::D, NC = M::NC;
@@ -282,13 +282,14 @@ __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, i
     }
     const Eval<T> en = accept ? ey : ex;
     ram_adapt<T, D>(S, U, eta * (alpha - astar));
+    v[0] = valid ? static_cast<double>(en.lf) : 0.0;
+    v[1] = valid ? static_cast<double>(M::dlf(o, x, en, kc, st)) : 0.0;
+    if (!valid) return false;
 #pragma unroll
     for (int j = 0; j < D; ++j) a.chi[j * n + i] = x[j];
 #pragma unroll
     for (int e = 0; e < NC; ++e) a.chol[e * n + i] = S[e];
     a.acc[i] = nacc;
-    v[0] = static_cast<double>(en.lf);
-    v[1] = static_cast<double>(M::dlf(o, x, en, kc, st));
     if (!(ex.lpv > neg_inf)) atomicOr(&a.cs[ds].flags, kFlagNonFiniteState);
     if (kTrace) {
         a.trace[i] = ex.lp;
@@ -326,7 +327,10 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
     __shared__ double red[2 * TPW][kWavesPerBlock];
     __shared__ uint32_t nacc_w[TPW][kWavesPerBlock];
 
-    if (static_cast<int>(blockIdx.x) < a.n_ds) {
+    const int n_side = kSingle ? 1 : a.n_ds;
+    // one round of kernel-argument loads for both paths
+    if (kSingle) asm volatile("" ::"s"(a.chi), "s"(a.chol), "s"(a.acc), "s"(a.dd), "s"(a.n_total));
+    if (static_cast<int>(blockIdx.x) < n_side) {
         const int ds = blockIdx.x;
         CycleState *cs = a.cs + ds;
         if (!cs->active) return;
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
 
     using T = typename M::T;
     constexpr int D = M::D, NC = M::NC;
-    const int g0 = (static_cast<int>(blockIdx.x) - a.n_ds) * TPW;     // first tile
+    const int g0 = (static_cast<int>(blockIdx.x) - n_side) * TPW;     // first tile
     // A dataset's objects start on a tile boundary, so position i of tile g
     // is g * 256 + lane whatever the dataset.  The objects' state is loaded
     // before the tile's dataset is looked up, so the loads overlap the table
@@ -362,20 +366,28 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
     T xs[TPW][D], Ss[TPW][NC];
     uint32_t na[TPW];
     typename M::Obj os[TPW];
+    TileView<T> tv[TPW];
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
-        const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
-        if (g0 + u < a.n_tiles_total && i < a.n_total) {
+        // positions past the end read the last position instead (unused): no
+        // branch, so the loads issue with the kernel arguments they need
+        int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
+        i = i < a.n_total ? i : a.n_total - 1;
 #pragma unroll
-            for (int j = 0; j < D; ++j) xs[u][j] = a.chi[j * a.n_total + i];
+        for (int j = 0; j < D; ++j) xs[u][j] = a.chi[j * a.n_total + i];
 #pragma unroll
-            for (int e = 0; e < NC; ++e) Ss[u][e] = a.chol[e * a.n_total + i];
-            na[u] = a.acc[i];
-            os[u] = M::load(a.dd, i, a.n_total);
-        }
+        for (int e = 0; e < NC; ++e) Ss[u][e] = a.chol[e * a.n_total + i];
+        na[u] = a.acc[i];
+        os[u] = M::load(a.dd, i, a.n_total);
+    }
+    if constexpr (kSingle) {
+        // the one dataset's scalars, in one round behind the object loads
+        tv[0] = tile_view<M>(a, 0);
+        asm volatile("" ::"s"(tv[0].k), "s"(tv[0].key0), "s"(tv[0].key1), "s"(tv[0].active), "s"(tv[0].eta));
+#pragma unroll
+        for (int u = 1; u < TPW; ++u) tv[u] = tv[0];
     }
     int dss[TPW];
-    TileView<T> tv[TPW];
     bool any = false;
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
@@ -383,34 +395,45 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         int ds;
         if constexpr (kSingle) {
             ds = (g < a.n_tiles_total) ? 0 : -1;
-            tv[u] = tile_view<M>(a, 0);
         } else {
             ds = (g < a.n_tiles_total) ? a.tile_ds[g] : -1;
             tv[u] = tile_view<M>(a, ds < 0 ? 0 : ds);      // slot 0 always exists
+            // issue every scalar load of the view now, as one round (the
+            // compiler would otherwise chain them behind the branches below)
+            asm volatile("" ::"s"(tv[u].k), "s"(tv[u].obj_start), "s"(tv[u].n), "s"(tv[u].key0),
+                         "s"(tv[u].key1), "s"(tv[u].active), "s"(tv[u].eta));
         }
-        // issue every scalar load of the view now, as one round (the compiler
-        // would otherwise chain them behind the branches below)
-        asm volatile("" ::"s"(tv[u].k), "s"(tv[u].obj_start), "s"(tv[u].n), "s"(tv[u].key0), "s"(tv[u].key1),
-                     "s"(tv[u].active), "s"(tv[u].eta));
         if (ds >= 0 && !tv[u].active) ds = -1;          // no epilogue reads this tile
         dss[u] = ds;
         any = any || ds >= 0;
     }
-    if (!any) return;
     double v[2 * TPW];
     bool accepted[TPW];
+    if constexpr (kSingle) {
+        // no exit between the loads and the arithmetic (the compiler would
+        // otherwise move the loads behind it): every lane computes, and only
+        // objects of the dataset store
 #pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-        v[2 * u] = v[2 * u + 1] = 0.0;
-        accepted[u] = false;
-        const int ds = dss[u];
-        if (ds < 0) continue;
-        const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
-        const int64_t il = kSingle ? i : i - tv[u].obj_start;
-        if (kSingle ? (i < a.n_total) : (il >= 0 && il < tv[u].n))
-            accepted[u] = step_object<M, kTrace>(a, kSingle ? 0 : ds, tv[u], il, i, xs[u], Ss[u], na[u], os[u],
-                                                 v + 2 * u);
+        for (int u = 0; u < TPW; ++u) {
+            const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
+            accepted[u] = step_object<M, kTrace>(a, 0, tv[u], i, i, xs[u], Ss[u], na[u], os[u], v + 2 * u,
+                                                 dss[u] >= 0 && i < a.n_total);
+        }
+    } else {
+        if (!any) return;
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            v[2 * u] = v[2 * u + 1] = 0.0;
+            accepted[u] = false;
+            const int ds = dss[u];
+            if (ds < 0) continue;
+            const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
+            const int64_t il = i - tv[u].obj_start;
+            if (il >= 0 && il < tv[u].n)
+                accepted[u] = step_object<M, kTrace>(a, ds, tv[u], il, i, xs[u], Ss[u], na[u], os[u], v + 2 * u);
+        }
     }
+    if (!any) return;           // (kSingle) the dataset is off: nothing to publish
     // accepted moves: one ballot per wavefront and tile
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
@@ -456,13 +479,28 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
     const int32_t t0 = kSingle ? 0 : st.tile_start, nt = kSingle ? ntt : st.n_tiles;
     // Every load is issued before the dataset's flag is looked at (it arrives
     // with the staged state); the values of a dataset that is off are unused.
-    // tile partials of this dataset, structure of arrays [3][n_tiles_total]
+    // tile partials of this dataset, structure of arrays [3][n_tiles_total]:
+    // lane t adds tiles t, t + 256, t + 512, ... in that order; the loads of
+    // up to 8 such tiles are issued together before any is added
     double v[3] = {0.0, 0.0, 0.0};
-#pragma unroll 8
-    for (int t = threadIdx.x; t < nt; t += kBlock) {
-        v[0] += a.partials[t0 + t];
-        v[1] += a.partials[ntt + t0 + t];
-        v[2] += a.partials[2 * ntt + t0 + t];
+    for (int base = 0; base < nt; base += 8 * kBlock) {
+        double q[3][8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int t = base + m * kBlock + threadIdx.x;
+            const bool in = t < nt;
+            q[0][m] = in ? a.partials[t0 + t] : 0.0;
+            q[1][m] = in ? a.partials[ntt + t0 + t] : 0.0;
+            q[2][m] = in ? a.partials[2 * ntt + t0 + t] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            if (base + m * kBlock + static_cast<int>(threadIdx.x) < nt) {
+                v[0] += q[0][m];
+                v[1] += q[1][m];
+                v[2] += q[2][m];
+            }
+        }
     }
     {
         const uint64_t *src = reinterpret_cast<const uint64_t *>(a.side + ds);
