@@ -56,6 +56,8 @@ def lib(path: str = None):
         L.orc_log_Z.restype = d
         L.orc_eps.argtypes = [P, d]
         L.orc_eps.restype = d
+        L.orc_bb1_log_norm.argtypes = [d, d, d]
+        L.orc_bb1_log_norm.restype = d
         L.orc_pop_sum.argtypes = [P, P, P]
         L.orc_pop_sum.restype = d
         L.orc_pop_terms.argtypes = [P, P, P, P]
@@ -106,6 +108,11 @@ def variates(seed: int, ctr, lib_path: str = None):
     z = np.zeros(4)
     lib(lib_path).orc_variates(ctypes.c_uint64(seed), _ptr(c), _ptr(u), _ptr(z))
     return u, z
+
+
+def bb1_log_norm(beta: float, ln_l: float, ln_u: float, lib_path: str = None) -> float:
+    """ln C(beta, u, l) of the break-by-one luminosity PDF."""
+    return float(lib(lib_path).orc_bb1_log_norm(beta, ln_l, ln_u))
 
 
 def num_threads() -> int:

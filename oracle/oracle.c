@@ -138,6 +138,36 @@ static double log_gamma_lum(double x, double beta, double ln_lstar)
     return a * (x - ln_lstar) - exp(x - ln_lstar) - lgamma(a);
 }
 
+/* Normaliser C(beta, u, l) of the break-by-one PDF (Appendix C):
+ * 1 / (Gamma(beta + 1) (1 - (1 + u/l)^-(beta+1))) for beta != -1 and
+ * 1 / ln(1 + u/l) at beta = -1.  For -2 < beta < -1 both factors of the
+ * first form are negative.  Returned as ln C. */
+double orc_bb1_log_norm(double beta, double ln_l, double ln_u)
+{
+    double q = 1.0 + exp(ln_u - ln_l);
+    double a = beta + 1.0;
+    if (a == 0.0)
+        return -log(log(q));
+    double g = tgamma(a);
+    double f = -expm1(-a * log(q));   /* 1 - q^-a */
+    return -log(g * f);
+}
+
+/* Break-by-one luminosity PDF (Sec. 5.1 and Appendix C),
+ * f(L) = C / u (1 - e^{-L/l}) (L/u)^beta e^{-L/u}, expressed in x = ln L
+ * (times the Jacobian L). */
+static double log_bb1_lum(double x, double beta, double ln_l, double ln_u)
+{
+    return orc_bb1_log_norm(beta, ln_l, ln_u) + (beta + 1.0) * (x - ln_u) + log(-expm1(-exp(x - ln_l)))
+           - exp(x - ln_u);
+}
+
+/* Flux-dependent measurement error sigma(F) = sqrt(sigma0^2 + (alpha F)^2) (eq 5.8). */
+static double bb1_sigma(const orc_ctx *c, double flux)
+{
+    return sqrt(c->consts[1] * c->consts[1] + c->consts[2] * flux * c->consts[2] * flux);
+}
+
 void orc_log_terms(const orc_ctx *c, int64_t i, const double *x, const double *theta,
                    double *log_meas, double *log_pop)
 {
@@ -174,6 +204,15 @@ void orc_log_terms(const orc_ctx *c, int64_t i, const double *x, const double *t
         double resid = (x[2] - theta[2] - theta[3] * x[0]) / s;
         *log_pop = log_gamma_lum(x[0], theta[0], theta[1]) + log_h
                    - 0.5 * resid * resid - log(s) - 0.5 * LOG_2PI;
+        break;
+    }
+    case ORC_BB1: {
+        /* Fhat_i ~ N(F, sigma(F)^2), F = exp(x - k_i) (the member likelihood is
+         * the sampling density of Fhat, with its 1/sigma(F)); theta = (beta, ln l, ln u). */
+        double fhat = col0[i], k = col1[i];
+        double flux = exp(x[0] - k), sig = bb1_sigma(c, flux);
+        *log_meas = -0.5 * ((fhat - flux) / sig) * ((fhat - flux) / sig) - log(sig);
+        *log_pop = log_bb1_lum(x[0], theta[0], theta[1], theta[2]);
         break;
     }
     case ORC_NN3D: {
@@ -215,14 +254,22 @@ double orc_log_prior(const orc_ctx *c, const double *theta)
         return -log(1.0 + theta[0] * theta[0]);
     case ORC_NN3D:
         return 0.0;
+    case ORC_BB1:
+        /* truncated Cauchy on -2 < beta < 0, flat in l, flat in ln u, l < u
+         * (eq 5.5); as a density in (beta, ln l, ln u) that is l / (1 + beta^2). */
+        if (!(theta[0] > -2.0 && theta[0] < 0.0) || !(theta[1] < theta[2]))
+            return -INFINITY;
+        return theta[1] - log(1.0 + theta[0] * theta[0]);
     }
     return NAN;
 }
 
-/* Detection efficiency eta(F) = Phi((F - F_th) / sigma_F) (eq 5.10). */
+/* Detection efficiency eta(F) = Phi((F - F_th) / sigma) (eq 5.10), with
+ * sigma = sigma_F for the gamma models and sigma(F) for the BB1 model. */
 static double detect_eff(const orc_ctx *c, double flux)
 {
-    double zz = (flux - c->consts[0]) / c->consts[1];
+    double sig = c->model == ORC_BB1 ? bb1_sigma(c, flux) : c->consts[1];
+    double zz = (flux - c->consts[0]) / sig;
     return 0.5 * erfc(-zz / sqrt(2.0));
 }
 
@@ -234,9 +281,12 @@ double orc_eps(const orc_ctx *c, double x)
 {
     if (c->nq <= 0)
         return NAN;
-    double rmax = c->consts[2], lum = exp(x), sum = 0.0;
+    /* BB1 catalogs measure distance in units of rmax and flux in units of
+     * L / rmax^2: the flux at u is L u^(-2/3). */
+    double scale = c->model == ORC_BB1 ? 1.0 : 4.0 * M_PI * c->consts[2] * c->consts[2];
+    double lum = exp(x), sum = 0.0;
     for (int l = 0; l < c->nq; l++) {
-        double flux = lum / (4.0 * M_PI * rmax * rmax * exp(2.0 * c->qt[l] / 3.0));
+        double flux = lum / (scale * exp(2.0 * c->qt[l] / 3.0));
         sum += c->qv[l] * exp(c->qt[l]) * detect_eff(c, flux);
     }
     return sum;
@@ -250,8 +300,11 @@ double orc_log_Z(const orc_ctx *c, const double *theta)
     if (c->nq <= 0)
         return 0.0;
     double z = 0.0;
-    for (int j = 0; j < c->nq; j++)
-        z += c->qw[j] * exp(log_gamma_lum(c->qx[j], theta[0], theta[1])) * c->qeps[j];
+    for (int j = 0; j < c->nq; j++) {
+        double lf = c->model == ORC_BB1 ? log_bb1_lum(c->qx[j], theta[0], theta[1], theta[2])
+                                        : log_gamma_lum(c->qx[j], theta[0], theta[1]);
+        z += c->qw[j] * exp(lf) * c->qeps[j];
+    }
     return log(z);
 }
 
@@ -303,6 +356,7 @@ orc_ctx *orc_new(int model, int64_t n, const double *data, const double *consts,
     case ORC_LF1D: c->d = 1; c->p = 2; c->m = 2; break;
     case ORC_LF3D: c->d = 3; c->p = 5; c->m = 3; break;
     case ORC_NN3D: c->d = 3; c->p = 3; c->m = 3; break;
+    case ORC_BB1: c->d = 1; c->p = 3; c->m = 2; break;
     default: free(c); return NULL;
     }
     c->data = malloc(sizeof(double) * (size_t)c->m * (size_t)n);
@@ -313,7 +367,7 @@ orc_ctx *orc_new(int model, int64_t n, const double *data, const double *consts,
     c->gamma = gamma;
     c->alpha_star_theta = alpha_star_theta;
     c->adapt_theta = adapt_theta;
-    c->nq = (model == ORC_LF1D || model == ORC_LF3D) ? nq : 0;
+    c->nq = (model == ORC_LF1D || model == ORC_LF3D || model == ORC_BB1) ? nq : 0;
     if (c->nq > 0) {
         c->qx = malloc(sizeof(double) * c->nq);
         c->qw = malloc(sizeof(double) * c->nq);
@@ -321,8 +375,14 @@ orc_ctx *orc_new(int model, int64_t n, const double *data, const double *consts,
         c->qt = malloc(sizeof(double) * c->nq);
         c->qv = malloc(sizeof(double) * c->nq);
         orc_gauss_legendre(c->nq, -60.0, 0.0, c->qt, c->qv);
-        double lnl0 = c->consts[3];
-        orc_gauss_legendre(c->nq, lnl0 - 30.0, lnl0 + log(40.0), c->qx, c->qw);
+        if (model == ORC_BB1) {
+            /* from 80 e-folds below the break l (the PDF falls only as
+             * L^(beta+2) there) to 40 u, at the reference l and u */
+            orc_gauss_legendre(c->nq, c->consts[3] - 80.0, c->consts[4] + log(40.0), c->qx, c->qw);
+        } else {
+            double lnl0 = c->consts[3];
+            orc_gauss_legendre(c->nq, lnl0 - 30.0, lnl0 + log(40.0), c->qx, c->qw);
+        }
         for (int j = 0; j < c->nq; j++)
             c->qeps[j] = orc_eps(c, c->qx[j]);
     }

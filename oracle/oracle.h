@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-enum { ORC_NN1D = 1, ORC_LF1D = 2, ORC_LF3D = 3, ORC_NN3D = 4 };
+enum { ORC_NN1D = 1, ORC_LF1D = 2, ORC_LF3D = 3, ORC_NN3D = 4, ORC_BB1 = 5 };
 
 typedef struct orc_ctx orc_ctx;
 
@@ -62,6 +62,7 @@ void orc_log_terms(const orc_ctx *c, int64_t i, const double *x, const double *t
 double orc_log_prior(const orc_ctx *c, const double *theta);
 double orc_log_Z(const orc_ctx *c, const double *theta);
 double orc_eps(const orc_ctx *c, double x);   /* detection efficiency of ln L = x */
+double orc_bb1_log_norm(double beta, double ln_l, double ln_u);   /* ln C of the break-by-one PDF */
 /* sum_i log f(chi_i; theta), serial in object order.  chi: [d][n]. */
 double orc_pop_sum(const orc_ctx *c, const double *theta, const double *chi);
 /* out[i] = log l_i(pts_i) + log f(pts_i; theta), pts [d][n]. */

@@ -17,4 +17,6 @@ from .workloads import (  # noqa: F401
     gamma_lf_batch,
     serving_arrivals,
     calibrate_threshold,
+    bb1_lf,
+    bb1_sample,
 )

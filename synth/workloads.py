@@ -9,7 +9,7 @@ Data follow the simulation designs of the paper: the heteroscedastic
 normal-normal benchmark (Sec. 3, eqs 3.1-3.4) and the luminosity-function
 study with a thinned (flux-selected) population (Sec. 4-5, eqs 4.2-4.4 and
 5.10), with the gamma luminosity PDF that the BB1 model reduces to as l -> 0
-(Appendix B).  Quantities are dimensionless.  Where an array feeds a
+(Appendix B), and the paper's own break-by-one (BB1) case study (Sec. 5).  Quantities are dimensionless.  Where an array feeds a
 single-precision sampler it is stored already rounded to float32, so both
 sides see bit-identical inputs.
 """
@@ -27,12 +27,14 @@ NORMAL_NORMAL_1D = 1
 GAMMA_LF_1D = 2
 GAMMA_LF_COLOR_3D = 3
 NORMAL_NORMAL_3D = 4
+BB1_LF = 5
 
 MODEL_NAMES = {
     NORMAL_NORMAL_1D: "normal_normal_1d",
     GAMMA_LF_1D: "gamma_lf_1d",
     GAMMA_LF_COLOR_3D: "gamma_lf_color_3d",
     NORMAL_NORMAL_3D: "normal_normal_3d",
+    BB1_LF: "bb1_lf",
 }
 
 # Index of each model constant inside the 16-slot constant vector.
@@ -280,3 +282,65 @@ def serving_arrivals(rate: float = 20.0, horizon_s: float = 600.0, seed: int = 4
         jobs.append((t, job_seed0 + j, n, sweeps))
         j += 1
     return jobs
+
+
+def bb1_sample(rng, count: int, beta: float, l: float, u: float) -> np.ndarray:
+    """Draws from the break-by-one PDF f(L) ~ (1 - e^{-L/l}) (L/u)^beta e^{-L/u}.
+
+    Writing 1 - e^{-L/l} as the integral of L e^{-L s} over s in [0, 1/l]
+    makes f a mixture of gamma laws: s has density proportional to
+    (1/u + s)^-(beta+2) on [0, 1/l] (drawn by inverting its CDF) and
+    L | s ~ Gamma(beta + 2, scale 1 / (1/u + s)).  Valid for -2 < beta.
+    """
+    g = beta + 2.0
+    a, b = 1.0 / u, 1.0 / l
+    q = rng.random(count)
+    if abs(g - 1.0) < 1e-12:
+        s = a * np.exp(q * math.log((a + b) / a)) - a
+    else:
+        lo, hi = a ** (1.0 - g), (a + b) ** (1.0 - g)
+        s = (lo + q * (hi - lo)) ** (1.0 / (1.0 - g)) - a
+    return rng.gamma(g, 1.0 / (a + s))
+
+
+def bb1_lf(n: int = 100_000, seed: int = 6, beta: float = -1.5, l: float = 0.01, u: float = 1.0,
+           alpha: float = 0.01, nu: float = 5.0, fth: float = 20.0, chunk: int = 4_000_000) -> Workload:
+    """The paper's break-by-one luminosity-function study (Sec. 5), dimensionless.
+
+    Luminosities in units of the reference upper scale, distances in units of
+    rmax (density 3 r^2 on (0, 1]), fluxes F = L / r^2 in units of the
+    fiducial flux u / (4 pi rmax^2).  Fhat ~ N(F, sigma(F)^2) with
+    sigma(F) = sqrt(sigma0^2 + (alpha F)^2); an object is detected when
+    Fhat > F_th, the threshold at nu times its own error,
+    F_th = nu sigma0 / sqrt(1 - nu^2 alpha^2).  sigma0 is set so that F_th = fth
+    (20: a source of 20 u at rmax is just detectable).  Objects are drawn
+    from the whole population until n are detected.  Data (float32): Fhat
+    and k = ln r^2, so F = exp(chi - k) for chi = ln L.  theta = (beta, ln l, ln u).
+    """
+    rng = np.random.default_rng(seed)
+    sigma0 = fth * math.sqrt(1.0 - nu * nu * alpha * alpha) / nu
+    keep_f, keep_r, keep_l, keep_fl = [], [], [], []
+    have = 0
+    while have < n:
+        lum = bb1_sample(rng, chunk, beta, l, u)
+        r = rng.random(chunk) ** (1.0 / 3.0)
+        flux = lum / (r * r)
+        fhat = flux + np.sqrt(sigma0 * sigma0 + (alpha * flux) ** 2) * rng.standard_normal(chunk)
+        sel = fhat > fth
+        keep_f.append(fhat[sel]); keep_r.append(r[sel]); keep_l.append(lum[sel]); keep_fl.append(flux[sel])
+        have += int(sel.sum())
+    fhat = np.concatenate(keep_f)[:n]
+    r = np.concatenate(keep_r)[:n]
+    lum = np.concatenate(keep_l)[:n]
+    fhat32 = fhat.astype(np.float32)
+    k32 = np.log(r * r).astype(np.float32)
+    data = np.stack([fhat32, k32])
+    chi0 = (k32.astype(np.float64) + np.log(fhat32.astype(np.float64))).astype(np.float32)
+    c = _consts(c0=fth, c1=sigma0, c2=alpha, c3=math.log(l), c4=math.log(u))
+    theta = np.array([beta, math.log(l), math.log(u)])
+    return Workload(
+        model=BB1_LF, n=n, d=1, p=3, precision="f32",
+        data=data, consts=c, theta_true=theta.copy(), theta0=theta.copy(),
+        theta_chol0=np.diag([0.02, 0.05, 0.02]), chi0=chi0.astype(np.float64)[None, :], seed=seed,
+        alpha_star=0.44, truth={"lum": lum, "r": r},
+    )

@@ -159,6 +159,52 @@ def pin_selection_in_theta_step(path, rr):
     return abs(info["delta"] - ref) < 1e-8 and abs(o.log_Z(wl.theta_true) - math.log(0.3)) < 0.05
 
 
+def _bb1_oracle(path):
+    return oracle.Oracle(synth.bb1_lf(n=20, seed=12, chunk=400_000), lib_path=path)
+
+
+def pin_bb1_normalisation(path, rr):
+    o = _bb1_oracle(path)
+    pts = [-500, -200, -60, -20, -10, -5, -2, 0, 2, 5]
+    for th in ([-1.5, math.log(0.01), 0.0], [-0.5, math.log(0.2), math.log(2.0)]):
+        f = lambda x: math.exp(o.log_terms(0, [x], th)[1])
+        tot = sum(integrate.quad(f, a, b, limit=400, epsabs=0, epsrel=1e-12)[0] for a, b in zip(pts, pts[1:]))
+        if not abs(tot - 1.0) < 1e-8:
+            return False
+    return True
+
+
+def pin_bb1_member_likelihood(path, rr):
+    o = _bb1_oracle(path)
+    wl = o.wl
+    s0, alpha = wl.consts[1], wl.consts[2]
+    fhat, k = float(wl.data[0][3]), float(wl.data[1][3])
+    for x in (k + math.log(fhat) - 0.05, k + math.log(fhat) + 0.2):
+        flux = math.exp(x - k)
+        ref = stats.norm.logpdf(fhat, flux, math.sqrt(s0 ** 2 + (alpha * flux) ** 2)) + 0.5 * math.log(2 * math.pi)
+        if abs(o.log_terms(3, [x], wl.theta_true)[0] - ref) > 1e-12:
+            return False
+    return True
+
+
+def pin_bb1_efficiency(path, rr):
+    o = _bb1_oracle(path)
+    fth, s0, alpha = o.wl.consts[0], o.wl.consts[1], o.wl.consts[2]
+    lum = 3.0
+    integrand = lambda r: 3 * r * r * stats.norm.cdf((lum / (r * r) - fth) / math.sqrt(s0 ** 2 + (alpha * lum / (r * r)) ** 2))
+    r_th = math.sqrt(lum / fth)
+    ref = integrate.quad(integrand, 0, 1, points=[0.5 * r_th, r_th, 1.5 * r_th], limit=400, epsabs=1e-15,
+                         epsrel=1e-11)[0]
+    return abs(o.eps(math.log(lum)) - ref) <= 1e-7 * ref
+
+
+def pin_bb1_prior(path, rr):
+    o = _bb1_oracle(path)
+    a, b = [-1.5, math.log(0.01), 0.0], [-0.4, math.log(0.2), math.log(3.0)]
+    ref = (math.log(0.2) - math.log(1.16)) - (math.log(0.01) - math.log(3.25))
+    return abs((o.log_prior(b) - o.log_prior(a)) - ref) < 1e-13 and o.log_prior([-1.0, 0.5, 0.4]) == -math.inf
+
+
 MUTATIONS = [
     ("philox multiplier", "0xD2511F53u", "0xD2511F57u", pin_philox),
     ("philox key bump", "k1 += weyl1;", "k1 += weyl0;", pin_philox),
@@ -180,6 +226,18 @@ MUTATIONS = [
      pin_acceptance_fixed_point),
     ("tau prior dropped", "        return theta[1];", "        return 0.0;", pin_theta_given_chi),
     ("selection term dropped", "- (double)c->n * orc_log_Z(c, prop);", ";", pin_selection_in_theta_step),
+    ("bb1 jacobian dropped", "return orc_bb1_log_norm(beta, ln_l, ln_u) + (beta + 1.0) * (x - ln_u)",
+     "return orc_bb1_log_norm(beta, ln_l, ln_u) + beta * (x - ln_u)", pin_bb1_normalisation),
+    ("bb1 break factor", "log(-expm1(-exp(x - ln_l)))", "log(-expm1(-exp(ln_l - x)))", pin_bb1_normalisation),
+    ("bb1 normaliser sign", "return -log(g * f);", "return log(g * f);", pin_bb1_normalisation),
+    ("bb1 normaliser ratio", "double q = 1.0 + exp(ln_u - ln_l);", "double q = 1.0 + exp(ln_l - ln_u);",
+     pin_bb1_normalisation),
+    ("bb1 sigma(F) normaliser dropped", "*log_meas = -0.5 * ((fhat - flux) / sig) * ((fhat - flux) / sig) - log(sig);",
+     "*log_meas = -0.5 * ((fhat - flux) / sig) * ((fhat - flux) / sig);", pin_bb1_member_likelihood),
+    ("bb1 constant error in the efficiency", "double sig = c->model == ORC_BB1 ? bb1_sigma(c, flux) : c->consts[1];",
+     "double sig = c->consts[1];", pin_bb1_efficiency),
+    ("bb1 prior l factor", "return theta[1] - log(1.0 + theta[0] * theta[0]);",
+     "return -theta[1] - log(1.0 + theta[0] * theta[0]);", pin_bb1_prior),
 ]
 
 
