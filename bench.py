@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # counter.  1-D LF (FP32): 4+4+4+12 read, 12 written; 3-D LF (FP32):
 # 12+24+4+24 read, 40 written; 1-D normal-normal (FP64): 8+8+4+16 read, 20
 # written; 3-D normal-normal (FP64): 24+48+4+24 read, 76 written.
-BYTES_PER_UPDATE = {"gamma_lf_1d": 36, "normal_normal_1d": 56, "gamma_lf_color_3d": 104, "normal_normal_3d": 176}
+BYTES_PER_UPDATE = {"gamma_lf_1d": 36, "normal_normal_1d": 56, "gamma_lf_color_3d": 104, "normal_normal_3d": 176,
+                    "bb1_lf": 36}
 
 
 def parse():
@@ -43,14 +44,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="gamma_lf_1d",
                     choices=["gamma_lf_1d", "gamma_lf_color_3d", "normal_normal_1d", "normal_normal_3d",
-                             "gamma_lf_batch256", "serving"])
+                             "bb1_lf", "gamma_lf_batch256", "serving"])
     ap.add_argument("--horizon", type=float, default=60.0, help="serving: seconds of Poisson arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--sat-jobs", type=int, default=200, help="serving: jobs in the saturation run")
     ap.add_argument("--seq-steps", type=int, default=200,
                     help="batch workload: cycles timed per dataset in the one-dataset-per-launch comparison")
     ap.add_argument("--job-sweeps", type=int, default=2000, help="batch workload: sweeps that make one job")
-    ap.add_argument("--n", type=int, default=None, help="objects (default: 300,000; 1,000,000 for the 3-D catalog)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="objects (default: 300,000; 1,000,000 for the 3-D catalog; 100,000 for BB1)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--launch-shape", default="auto", choices=["auto", "1", "2", "4"],
                     help="tiles per sweep workgroup; auto runs the autotuner during burn-in")
@@ -327,7 +329,8 @@ def main():
         bench_serving(args, torch, synth, hbm)
         return
     make = {"gamma_lf_1d": (synth.gamma_lf_1d, 300_000), "gamma_lf_color_3d": (synth.gamma_lf_3d, 1_000_000),
-            "normal_normal_1d": (synth.normal_normal_1d, 300_000), "normal_normal_3d": (synth.normal_normal_3d, 300_000)}
+            "normal_normal_1d": (synth.normal_normal_1d, 300_000), "normal_normal_3d": (synth.normal_normal_3d, 300_000),
+            "bb1_lf": (synth.bb1_lf, 100_000)}
     gen, n_default = make[args.workload]
     wl = gen(n=args.n or n_default)
     trial = 64
@@ -385,7 +388,7 @@ def main():
         "dtype": "f32" if wl.precision == "f32" else "f64",
         "data": f"synthetic (seeded {wl.name} catalog)",
         "config": {"workload": wl.name, "n_objects": wl.n, "latent_dim": wl.d, "theta_dim": wl.p,
-                   "selection_quadrature_nodes": 512 if wl.model in (2, 3) else 0, "graph": use_graph,
+                   "selection_quadrature_nodes": 512 if wl.model in (2, 3, 5) else 0, "graph": use_graph,
                    "sweeps_per_step": 1, "tiles_per_workgroup": pick},
         "autotune_us_per_cycle": {"1": tuned[0], "2": tuned[1], "4": tuned[2]},
         "gibbs_sweeps_per_s": args.steps / wall,

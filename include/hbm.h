@@ -92,14 +92,24 @@ typedef int32_t hbm_status;
  *  HBM_NORMAL_NORMAL_3D (the paper's Sec. 3 instance): chi in R^3,
  *      chi ~ MVN(mu, C_pop), y_ij ~ N(chi_ij, sigma_j^2), C_pop and sigma
  *      known; theta = mu, flat prior.  FP64.
+ *  HBM_BB1_LF (the paper's Sec. 5 case study, Appendix C): chi = ln L;
+ *      data (Fhat_i, k_i = ln r_i^2) with L in units of a reference scale,
+ *      r in units of rmax and F = L / r^2; theta = (beta, ln l, ln u),
+ *      f(L) = C / u (1 - e^{-L/l}) (L/u)^beta e^{-L/u} (break-by-one PDF);
+ *      Fhat ~ N(F, sigma0^2 + (alpha F)^2) with its normaliser; selection
+ *      by Fhat > F_th; prior l / (1 + beta^2) in (beta, ln l, ln u) on
+ *      -2 < beta < 0, l < u (eq 5.5).  FP32.
  * model_consts: LF models [0] F_th, [1] sigma_F, [2] rmax, [3] centre ln L0
  * of the ln L quadrature interval [ln L0 - 30, ln L0 + ln 40], [4] f_r,
  * [5] sigma_c.  NN3D: [0..5] lower triangle of C_pop (row-major),
- * [6..8] sigma_j.  NN1D: unused. */
+ * [6..8] sigma_j.  NN1D: unused.  BB1: [0] F_th, [1] sigma0, [2] alpha,
+ * [3] ln l and [4] ln u of a reference PDF (the selection quadrature runs
+ * over ln L in [ln l - 80, ln u + ln 40]). */
 #define HBM_NORMAL_NORMAL_1D  1
 #define HBM_GAMMA_LF_1D       2
 #define HBM_GAMMA_LF_COLOR_3D 3
 #define HBM_NORMAL_NORMAL_3D  4
+#define HBM_BB1_LF            5
 
 #define HBM_FP64 1
 #define HBM_FP32 2

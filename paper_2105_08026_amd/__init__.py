@@ -22,7 +22,7 @@ from .build import LIB_PATH
 from .serve import TileAllocator
 
 HBM_OK, HBM_EINVAL, HBM_ENOMEM, HBM_EHIP, HBM_EDOMAIN, HBM_ESTATE, HBM_ENOSPACE = 0, -1, -2, -3, -4, -5, -6
-HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_3D = 1, 2, 3, 4
+HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_3D, HBM_BB1_LF = 1, 2, 3, 4, 5
 HBM_FP64, HBM_FP32 = 1, 2
 
 EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
@@ -37,6 +37,7 @@ _MODEL_DIMS = {  # model -> (d, p, m, precision)
     HBM_GAMMA_LF_1D: (1, 2, 2, HBM_FP32),
     HBM_GAMMA_LF_COLOR_3D: (3, 5, 3, HBM_FP32),
     HBM_NORMAL_NORMAL_3D: (3, 3, 3, HBM_FP64),
+    HBM_BB1_LF: (1, 3, 2, HBM_FP32),
 }
 
 

@@ -283,8 +283,8 @@ struct Ops {
         hipLaunchKernelGGL((init_chain_kernel<M>), dim3(c->n_tiles), dim3(kBlock), 0, c->stream,
                            static_cast<T *>(c->buf.chol), c->buf.acc, c->st, c->tile_ds, c->which, c->cap);
         LAUNCHCHK(c, "init_chain_kernel");
-        if (M::kSelection) {
-            hipLaunchKernelGGL(eps_table_kernel, dim3((c->nq + 63) / 64, c->n_slots), dim3(64), 0, c->stream, c->ref_t,
+        if constexpr (M::kSelection) {
+            hipLaunchKernelGGL((eps_table_kernel<M>), dim3((c->nq + 63) / 64, c->n_slots), dim3(64), 0, c->stream, c->ref_t,
                                c->ref_w, c->qx, c->qw, c->qeps, c->st, c->which);
             LAUNCHCHK(c, "eps_table_kernel");
         }
@@ -328,11 +328,15 @@ bool model_info(int model, ModelInfo *mi)
     case HBM_GAMMA_LF_1D: *mi = {LF1D::D, LF1D::P, LF1D::M, LF1D::MD, HBM_FP32, Ops<LF1D>::table()}; return true;
     case HBM_GAMMA_LF_COLOR_3D: *mi = {LF3D::D, LF3D::P, LF3D::M, LF3D::MD, HBM_FP32, Ops<LF3D>::table()}; return true;
     case HBM_NORMAL_NORMAL_3D: *mi = {NN3D::D, NN3D::P, NN3D::M, NN3D::MD, HBM_FP64, Ops<NN3D>::table()}; return true;
+    case HBM_BB1_LF: *mi = {BB1::D, BB1::P, BB1::M, BB1::MD, HBM_FP32, Ops<BB1>::table()}; return true;
     default: return false;
     }
 }
 
-bool has_selection(int model) { return model == HBM_GAMMA_LF_1D || model == HBM_GAMMA_LF_COLOR_3D; }
+bool has_selection(int model)
+{
+    return model == HBM_GAMMA_LF_1D || model == HBM_GAMMA_LF_COLOR_3D || model == HBM_BB1_LF;
+}
 
 hbm_status usable(CtxImpl *c)
 {
@@ -428,7 +432,12 @@ hbm_status validate_dataset(CtxImpl *c, const hbm_config *cfg, const double *the
         return fail(c, HBM_EINVAL, "eta_exponent must lie in (1/2, 1]");
     if (!(cfg->s0 > 0.0) || !std::isfinite(cfg->s0)) return fail(c, HBM_EINVAL, "s0 must be positive");
     if (cfg->thin_chi < 0 || cfg->max_cycles < 0) return fail(c, HBM_EINVAL, "thin_chi and max_cycles must be >= 0");
-    if (has_selection(cfg->model)) {
+    if (cfg->model == HBM_BB1_LF) {
+        const double *mc = cfg->model_consts;
+        if (!(mc[0] > 0.0) || !(mc[1] > 0.0) || !(mc[2] >= 0.0) || !std::isfinite(mc[3]) || !std::isfinite(mc[4]) ||
+            !(mc[3] < mc[4]))
+            return fail(c, HBM_EINVAL, "BB1 model constants need F_th, sigma0 > 0, alpha >= 0 and finite ln l < ln u");
+    } else if (has_selection(cfg->model)) {
         const double *mc = cfg->model_consts;
         if (!(mc[0] > 0.0) || !(mc[1] > 0.0) || !(mc[2] > 0.0) || !std::isfinite(mc[3]))
             return fail(c, HBM_EINVAL, "LF model constants need F_th, sigma_F, rmax > 0 and a finite ln L0");

@@ -202,18 +202,17 @@ __device__ void theta_mh(CycleState &c, const Statics &s, double *theta_trace, d
     if (c.budget > 0 && c.n_theta >= c.budget) c.active = 0;
 }
 
-// ln Z(theta) + lnGamma(beta + 1) = ln sum_j w_j f_x(x_j; theta) Gamma(beta + 1) eps_j
-// over the fixed ln L rule (the normaliser of the gamma law is applied by
-// the caller); every lane of one workgroup takes nodes tid, tid + 256, ...
-// Valid in thread 0.
+// ln of the selection quadrature sum_j w_j g(x_j; theta) eps_j over the fixed
+// ln L rule, where g is the luminosity PDF in x = ln L without its
+// normaliser (the model's zlog; the normaliser is applied by the caller
+// through logz_shift); every lane of one workgroup takes nodes tid,
+// tid + 256, ...  Valid in thread 0.
+template <class M>
 __device__ __forceinline__ double block_log_z(const double *zc, const double *qx, const double *qw,
                                               const double *qeps, int nq, double (*red)[kWavesPerBlock])
 {
     double v[1] = {0.0};
-    for (int j = threadIdx.x; j < nq; j += kBlock) {
-        const double t = qx[j] - zc[1];
-        v[0] += qw[j] * exp(zc[0] * t - exp(t)) * qeps[j];
-    }
+    for (int j = threadIdx.x; j < nq; j += kBlock) v[0] += qw[j] * exp(M::zlog(zc, qx[j])) * qeps[j];
     block_sum<1>(v, red);
     return log(v[0]);
 }
@@ -341,10 +340,12 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         double judged[kMaxP];
         for (int r = 0; r < M::P; ++r) judged[r] = cs->prop[r];
         double zraw = 0.0;
-        if (M::kSelection && valid) {
-            double zc[2] = {cs->zc_prop[0], cs->zc_prop[1]};
-            const int64_t qo = static_cast<int64_t>(ds) * a.nq;
-            zraw = block_log_z(zc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, zred);
+        if constexpr (M::kSelection) {
+            if (valid) {
+                double zc[4] = {cs->zc_prop[0], cs->zc_prop[1], cs->zc_prop[2], cs->zc_prop[3]};
+                const int64_t qo = static_cast<int64_t>(ds) * a.nq;
+                zraw = block_log_z<M>(zc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, zred);
+            }
         }
         precompute<M>(sd, cs->k + 1, judged, valid, st);
         if (threadIdx.x == 0) sd.zraw = zraw;
@@ -563,11 +564,13 @@ __global__ __launch_bounds__(kBlock) void set_theta_kernel(CycleState *cs_all, c
     // the judged-proposal slots of pc carry theta itself here
     precompute<M>(pc, c.k, c.theta, ok, st);
     double lz = 0.0;
-    if (M::kSelection && ok) {
-        double zc[2];
-        M::z_consts(c.theta, zc);
-        const int64_t qo = static_cast<int64_t>(ds) * nq;
-        lz = block_log_z(zc, qx + qo, qw + qo, qeps + qo, nq, red);
+    if constexpr (M::kSelection) {
+        if (ok) {
+            double zc[4];
+            M::z_consts(c.theta, zc);
+            const int64_t qo = static_cast<int64_t>(ds) * nq;
+            lz = block_log_z<M>(zc, qx + qo, qw + qo, qeps + qo, nq, red);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -673,11 +676,11 @@ __global__ __launch_bounds__(kBlock) void poplik_kernel(PopArgs<typename M::T> a
         double ag[2];
         M::aux(th, ag);
         double lz = 0.0;
-        if (M::kSelection) {
-            double zc[2];
+        if constexpr (M::kSelection) {
+            double zc[4];
             M::z_consts(th, zc);
             const int64_t qo = static_cast<int64_t>(ds) * a.nq;
-            lz = block_log_z(zc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, red) - M::logz_shift(ag);
+            lz = block_log_z<M>(zc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, red) - M::logz_shift(ag);
         }
         if (threadIdx.x == 0) a.pout[2 * ds] = lz;
         return;
@@ -760,6 +763,7 @@ __global__ void gauss_legendre_kernel(double *t_out, double *w_out, int nq)
 // h(r) = 3 r^2 / rmax^3 and eta(F) = Phi((F - F_th) / sigma_F) (eq 5.10),
 // written in s = ln u, u = (r / rmax)^3, so that h dr = e^s ds, over
 // s in [-60, 0] with the same n-point rule (the part below e^-60 is dropped).
+template <class M>
 __global__ void eps_table_kernel(const double *t, const double *w, double *qx_all, double *qw_all, double *qeps_all,
                                  const Statics *st_all, const int32_t *which)
 {
@@ -771,19 +775,18 @@ __global__ void eps_table_kernel(const double *t, const double *w, double *qx_al
     if (j >= nq) return;
     double *qx = qx_all + static_cast<int64_t>(ds) * nq, *qw = qw_all + static_cast<int64_t>(ds) * nq;
     double *qeps = qeps_all + static_cast<int64_t>(ds) * nq;
-    const double fth = st->mc[0], sigf = st->mc[1], rmax = st->mc[2], lnl0 = st->mc[3];
-    const double lo = lnl0 - 30.0, hi = lnl0 + log(40.0);
+    double lo, hi;
+    M::quad_interval(*st, &lo, &hi);
     // nodes ascend in x: t descends with the node index
     const double x = 0.5 * (lo + hi) - 0.5 * (hi - lo) * t[j];
     qx[j] = x;
     qw[j] = 0.5 * (hi - lo) * w[j];
-    const double lum_scaled = exp(x) / (4.0 * 3.14159265358979323846 * rmax * rmax);
+    // flux of luminosity e^x at the survey edge; at u = (r / rmax)^3 = e^s it is u^(-2/3) times that
+    const double edge_flux = exp(x) / M::edge_area(*st);
     double acc = 0.0;
     for (int l = 0; l < nq; ++l) {
         const double s = -30.0 - 30.0 * t[l];
-        const double flux = lum_scaled * exp(-2.0 * s / 3.0);
-        const double eta = 0.5 * erfc(-(flux - fth) / (sigf * 1.4142135623730950488));
-        acc += 30.0 * w[l] * exp(s) * eta;
+        acc += 30.0 * w[l] * exp(s) * M::detect(edge_flux * exp(-2.0 * s / 3.0), *st);
     }
     qeps[j] = acc;
 }

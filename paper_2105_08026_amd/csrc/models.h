@@ -20,11 +20,16 @@
 //   log_prior(th)       log prior density in the theta coordinates
 //   derive_kc(th, tp, a, s, kc)  per-sweep constants in the per-object precision
 //                       from the current theta (with its aux a) and the proposal tp
-//   dlf_const(th, tp, a, ap)     the object-independent part of
-//                       log f(chi; tp) - log f(chi; th), added N times
+//   dlf_const(th, tp, a, ap)     minus the object-independent part of
+//                       log f(chi; tp) - log f(chi; th), subtracted N times
 //   z_consts(tp, zc), logz_shift(ap)  quadrature constants of ln Z; the
 //                       quadrature sum omits exp(-shift) and the shift is
 //                       subtracted afterwards
+//   zlog(zc, x)         (selection models) log of the luminosity PDF in
+//                       x = ln L without its normaliser, from z_consts
+//   quad_interval, edge_area, detect  (selection models) the ln L range of
+//                       the selection quadrature, 4 pi rmax^2 in the data's
+//                       units, and the detection efficiency of a flux
 //   eval, dlf           per-object log densities and the per-object part of
 //                       the log f change, in the per-object precision
 #pragma once
@@ -256,6 +261,23 @@ struct LF1D {
         zc[1] = tp[1];
     }
     __device__ static double logz_shift(const double *ap) { return ap[0]; }
+    __device__ static double zlog(const double *zc, double x)
+    {
+        const double t = x - zc[1];
+        return zc[0] * t - exp(t);
+    }
+    // ln L from 30 e-folds below the reference ln L0 to 40 L0
+    __device__ static void quad_interval(const Statics &s, double *lo, double *hi)
+    {
+        *lo = s.mc[3] - 30.0;
+        *hi = s.mc[3] + log(40.0);
+    }
+    __device__ static double edge_area(const Statics &s) { return 4.0 * 3.14159265358979323846 * s.mc[2] * s.mc[2]; }
+    // eta(F) = Phi((F - F_th) / sigma_F)
+    __device__ static double detect(double flux, const Statics &s)
+    {
+        return 0.5 * erfc(-(flux - s.mc[0]) / (s.mc[1] * 1.4142135623730950488));
+    }
     __device__ static double dlf_const(const double *th, const double *tp, const double *a, const double *ap)
     {
         return gamma_dconst(th, tp, a, ap);
@@ -341,6 +363,10 @@ struct LF3D {
     __device__ static double log_prior(const double *th) { return in_support(th) ? -log1p(th[0] * th[0]) : -HUGE_VAL; }
     __device__ static void z_consts(const double *tp, double *zc) { LF1D::z_consts(tp, zc); }
     __device__ static double logz_shift(const double *ap) { return ap[0]; }
+    __device__ static double zlog(const double *zc, double x) { return LF1D::zlog(zc, x); }
+    __device__ static void quad_interval(const Statics &s, double *lo, double *hi) { LF1D::quad_interval(s, lo, hi); }
+    __device__ static double edge_area(const Statics &s) { return LF1D::edge_area(s); }
+    __device__ static double detect(double flux, const Statics &s) { return LF1D::detect(flux, s); }
     __device__ static double dlf_const(const double *th, const double *tp, const double *a, const double *ap)
     {
         return gamma_dconst(th, tp, a, ap) + (ap[1] - a[1]);
@@ -385,6 +411,144 @@ struct LF3D {
         const float dg = kc[4] * e.q - e.eq * kc[5];
         const float du = e.res * kc[13] - (kc[11] + kc[12] * x[0]) * kc[14];
         return dg - 0.5f * du * (2.0f * e.u + du);
+    }
+};
+
+// ===========================================================================
+// Break-by-one luminosity function (Sec. 5, Appendix C), flux-limited, known
+// distances; chi = ln L; theta = (beta, ln l, ln u).  Units: L in units of a
+// reference scale, distances in units of rmax, F = L / r^2, so k_i = ln r_i^2.
+//   f(L) = C / u (1 - e^{-L/l}) (L/u)^beta e^{-L/u},
+//   C = 1 / (Gamma(beta + 1) (1 - (1 + u/l)^-(beta+1))), or 1 / ln(1 + u/l) at beta = -1;
+//   log f in chi: ln C + (beta + 1)(chi - ln u) + ln(1 - e^{-L/l}) - e^{chi - ln u}.
+//   log l_i(chi) = -z^2 / 2 - ln sigma(F), z = (Fhat - F) / sigma(F),
+//   sigma(F) = sqrt(sigma0^2 + (alpha F)^2)  (the sampling density of Fhat, eq 5.8).
+// Prior: -2 < beta < 0 truncated Cauchy, flat in l, flat in ln u, l < u; as
+// a density in (beta, ln l, ln u) that is l / (1 + beta^2) (eq 5.5).
+// Derived data per object: Fhat, centre c = ln(r^2 Fhat) in float and its
+// residual e.  Statics mc: [0] F_th, [1] sigma0, [2] alpha, [3] ln l and
+// [4] ln u of the reference PDF (they fix the quadrature range); mf:
+// [0] sigma0^2, [1] alpha^2.  aux: [0] ln C.
+// kc: [0] beta + 1, [1] ln u head, [2] its tail, [3] ln l head, [4] its tail,
+//     [5] ln C, [6] expm1(ln u - ln u'), [7] expm1(ln l - ln l'), [8] beta' - beta.
+// The object-dependent part of log f' - log f is
+//   (beta' - beta) q - e^q [6] + ln((1 - e^{-x'}) / (1 - e^{-x})),  q = chi - ln u,
+// x = L / l, x' = x (1 + [7]); the rest, (beta' + 1)(ln u - ln u') + ln C' - ln C,
+// is object-independent (dlf_const returns its negative).
+// ===========================================================================
+__device__ __forceinline__ double bb1_ln_norm(double beta, double ln_l, double ln_u)
+{
+    const double ln_q = log1p(exp(ln_u - ln_l));
+    const double a = beta + 1.0;
+    if (a == 0.0) return -log(ln_q);
+    // Gamma(a) and 1 - q^-a = -expm1(-a ln q) share their sign
+    return -(log(fabs(tgamma(a))) + log(fabs(expm1(-a * ln_q))));
+}
+
+struct BB1 {
+    using T = float;
+    static constexpr int D = 1, NC = 1, M = 2, MD = 3, P = 3, MODEL = 5;
+    static constexpr bool kSelection = true;
+    struct Obj {
+        float fh, c, e;
+    };
+
+    __device__ static void derive_statics(Statics &s)
+    {
+        s.mf[0] = static_cast<float>(s.mc[1] * s.mc[1]);
+        s.mf[1] = static_cast<float>(s.mc[2] * s.mc[2]);
+    }
+    __device__ static void derive_obj(const T *data, T *dd, int64_t i, int64_t n, const Statics &)
+    {
+        const double fhat = data[i], k = data[n + i];
+        const double centre = k + log(fhat);
+        const float c = static_cast<float>(centre);
+        dd[i] = static_cast<float>(fhat);
+        dd[n + i] = c;
+        dd[2 * n + i] = static_cast<float>(centre - static_cast<double>(c));
+    }
+    __device__ static Obj load(const T *dd, int64_t i, int64_t n) { return Obj{dd[i], dd[n + i], dd[2 * n + i]}; }
+    __device__ static void aux(const double *th, double *a)
+    {
+        a[0] = bb1_ln_norm(th[0], th[1], th[2]);
+        a[1] = 0.0;
+    }
+    __device__ static bool in_support(const double *th) { return th[0] > -2.0 && th[0] < 0.0 && th[1] < th[2]; }
+    __device__ static double log_prior(const double *th) { return in_support(th) ? th[1] - log1p(th[0] * th[0]) : -HUGE_VAL; }
+    __device__ static void z_consts(const double *tp, double *zc)
+    {
+        zc[0] = tp[0] + 1.0;
+        zc[1] = tp[2];
+        zc[2] = tp[1];
+        zc[3] = 0.0;
+    }
+    // the quadrature sum carries no ln C: ln Z = ln sum + ln C
+    __device__ static double logz_shift(const double *ap) { return -ap[0]; }
+    __device__ static double zlog(const double *zc, double x)
+    {
+        return zc[0] * (x - zc[1]) + log(-expm1(-exp(x - zc[2]))) - exp(x - zc[1]);
+    }
+    // ln L from 80 e-folds below the reference l (the PDF falls only as
+    // L^(beta+2) there) to 40 times the reference u
+    __device__ static void quad_interval(const Statics &s, double *lo, double *hi)
+    {
+        *lo = s.mc[3] - 80.0;
+        *hi = s.mc[4] + log(40.0);
+    }
+    __device__ static double edge_area(const Statics &) { return 1.0; }
+    // eta(F) = Phi((F - F_th) / sigma(F))
+    __device__ static double detect(double flux, const Statics &s)
+    {
+        const double sig = sqrt(s.mc[1] * s.mc[1] + s.mc[2] * s.mc[2] * flux * flux);
+        return 0.5 * erfc(-(flux - s.mc[0]) / (sig * 1.4142135623730950488));
+    }
+    __device__ static double dlf_const(const double *th, const double *tp, const double *a, const double *ap)
+    {
+        return (tp[0] + 1.0) * (tp[2] - th[2]) + (a[0] - ap[0]);
+    }
+    __device__ static void derive_kc(const double *th, const double *tp, const double *a, const Statics &, T *kc)
+    {
+        const float uh = static_cast<float>(th[2]), lh = static_cast<float>(th[1]);
+        kc[0] = static_cast<float>(th[0] + 1.0);
+        kc[1] = uh;
+        kc[2] = static_cast<float>(th[2] - static_cast<double>(uh));
+        kc[3] = lh;
+        kc[4] = static_cast<float>(th[1] - static_cast<double>(lh));
+        kc[5] = static_cast<float>(a[0]);
+        kc[6] = static_cast<float>(expm1(th[2] - tp[2]));
+        kc[7] = static_cast<float>(expm1(th[1] - tp[1]));
+        kc[8] = static_cast<float>(tp[0] - th[0]);
+    }
+    __device__ static Eval<T> eval(const Obj &o, const T *x, const T *kc, const Statics &s)
+    {
+        Eval<T> e;
+        // member likelihood around the object's centre: F = Fhat e^d
+        const float d = (x[0] - o.c) - o.e;
+        const float em = expm1f(d);
+        const float flux = o.fh + o.fh * em;
+        const float var = s.mf[0] + s.mf[1] * flux * flux;
+        const float z = o.fh * em;
+        const float lm = -0.5f * (z * z) / var - 0.5f * logf(var);
+        // population term
+        e.q = (x[0] - kc[1]) - kc[2];
+        e.eq = expf(e.q);
+        e.res = expf((x[0] - kc[3]) - kc[4]);          // x = L / l
+        const float brk = logf(-expm1f(-e.res));
+        const float g = kc[0] * e.q + brk - e.eq;
+        e.lpv = lm + g;
+        e.lf = g + kc[5];
+        e.lp = lm + e.lf;
+        e.u = 0.0f;
+        return e;
+    }
+    __device__ static T dlf(const Obj &, const T *, const Eval<T> &e, const T *kc, const Statics &)
+    {
+        // ln((1 - e^{-x'}) / (1 - e^{-x})) = log1p((e^{-x} - e^{-x'}) / (1 - e^{-x}))
+        const float x = e.res, dx = x * kc[7];                 // x' - x
+        const float den = -expm1f(-x);
+        const float num = (dx > -60.0f) ? expf(-x) * -expm1f(-dx) : expf(-x) - expf(-(x + dx));
+        const float brk = (den > 0.0f) ? log1pf(num / den) : log1pf(kc[7]);
+        return kc[8] * e.q - e.eq * kc[6] + brk;
     }
 };
 

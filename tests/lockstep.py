@@ -92,9 +92,18 @@ def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
     # rejected moves keep the latent bit for bit
     rej = same & ~acc_o
     assert np.array_equal(chi1[:, rej], chi0[:, rej])
-    # accepted moves land on the proposal
+    # accepted moves land on the proposal Y = X + S U.  Its error is set by
+    # the operands, not by Y (a latent near zero can cancel): the rounding of
+    # X and the single-precision normals' absolute error, which scales with
+    # the Box-Muller radius (at most sqrt(-2 ln 2^-24) = 5.77) times the row
+    # of S
     accd = same & acc_o
-    ulp = np.spacing(np.abs(st.chi[:, accd]).astype(np.float32 if prec == "f32" else np.float64)).astype(np.float64)
+    rows = np.zeros((d, chol0.shape[1]))
+    for r in range(d):
+        for q in range(r + 1):
+            rows[r] += np.abs(chol0[r * (r + 1) // 2 + q])
+    size = np.maximum(np.abs(chi0[:, accd]), 5.77 * rows[:, accd])
+    ulp = np.spacing(size.astype(np.float32 if prec == "f32" else np.float64)).astype(np.float64)
     err = np.abs(chi1[:, accd] - st.chi[:, accd])
     chi_err = float((err / np.maximum(ulp, 1e-300)).max()) if err.size else 0.0
     assert chi_err <= tol["chi_ulps"], ("latent", chi_err)
@@ -121,7 +130,7 @@ def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
     theta1, cth1, _ = sampler.theta()
     d_g, d_o = stats["delta"], info["delta"]
     # FP64 selection normalisers of the two sides agree to ~1e-13 relative
-    has_sel = orc.wl.model in (2, 3)
+    has_sel = orc.wl.model in (2, 3, 5)
     theta_tol = tol["theta_rel"] * max(1.0, scale) + (1e-12 * sampler.n if has_sel else 0.0)
     near_theta = False
     if np.isfinite(d_o):

@@ -1,0 +1,116 @@
+"""GPU parity of the break-by-one (BB1) luminosity-function model (Sec. 5, Appendix C).
+
+Lockstep sweeps and theta steps against the FP64 oracle (tests/lockstep.py),
+the population log-likelihood, posterior moments of a free run against the
+oracle's, a batch of BB1 catalogs against each run alone, and the paper's
+case-study pattern: posterior means of (beta, ln l, ln u) within a few
+posterior standard deviations of the truth.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import batch_means
+from lockstep import lockstep_step
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2105_08026_amd as h
+    h.lib()
+    return h
+
+
+@pytest.mark.parametrize("n", [3001, 257])
+def test_bb1_lockstep(hbm, n):
+    _say(f"bb1 lockstep: N={n}")
+    wl = synth.bb1_lf(n=n, seed=61, chunk=1_000_000)
+    s = hbm.Sampler(wl, max_cycles=200)
+    o = oracle.Oracle(wl)
+    worst = 0.0
+    for step in range(40):
+        r = lockstep_step(s, o, "f32")
+        worst = max(worst, r.max_rel_lpx, r.max_rel_lpy)
+        if step % 10 == 0:
+            _say(f"  step {step}: max rel lp err {worst:.2e} near-ties {r.near_ties} "
+                 f"dtheta {r.theta_delta_gpu - r.theta_delta_orc:.2e}")
+
+
+def test_bb1_pop_loglik(hbm):
+    wl = synth.bb1_lf(n=4000, seed=62, chunk=1_000_000)
+    _say(f"bb1 pop_loglik N={wl.n}")
+    s = hbm.Sampler(wl, max_cycles=50)
+    s.run_cycles(20)
+    chi, _, _ = s.state()
+    o = oracle.Oracle(wl)
+    for th in ([-1.5, math.log(0.01), 0.0], [-1.45, math.log(0.012), 0.03], [-1.0, math.log(0.02), -0.1]):
+        got = s.pop_loglik(th)
+        ref = o.pop_loglik(th, chi)
+        scale = np.sum(np.abs(o.pop_terms(th, chi)))
+        assert abs(got - ref) <= 1e-6 * scale + 1e-12 * wl.n, (th, got, ref)
+
+
+def test_bb1_free_run_posterior_moments(hbm):
+    _say("bb1 free run: posterior theta moments vs oracle within MCSE")
+    wl = synth.bb1_lf(n=400, seed=63, chunk=1_000_000)
+    m = 30000
+    s = hbm.Sampler(wl, max_cycles=m)
+    s.run_cycles(m)
+    tg = s.theta_trace()[m // 5:]
+    o = oracle.Oracle(wl)
+    st = o.initial_state()
+    to, _ = o.run(st, m)
+    to = to[m // 5:]
+    for j in range(3):
+        mg, sg = batch_means(tg[:, j])
+        mo, so = batch_means(to[:, j])
+        z = abs(mg - mo) / math.hypot(sg, so)
+        _say(f"  theta[{j}] gpu {mg:.5f}±{sg:.5f} oracle {mo:.5f}±{so:.5f} z={z:.2f}")
+        assert z < 3.0
+
+
+def test_bb1_batch_matches_alone(hbm):
+    wls = [synth.bb1_lf(n=n, seed=64 + j, chunk=1_000_000) for j, n in enumerate((700, 1900))]
+    _say("bb1 batch of 2 vs alone, 60 cycles")
+    b = hbm.Batch(wls, max_cycles=60)
+    b.run_cycles(60)
+    for j, w in enumerate(wls):
+        s = hbm.Sampler(w, max_cycles=60)
+        s.run_cycles(60)
+        assert np.array_equal(b.theta_trace(j), s.theta_trace()), j
+        assert np.array_equal(b.latents(j), s.state()[0]), j
+        s.close()
+    b.close()
+
+
+def test_bb1_case_study_recovers_truth(hbm):
+    """The pattern of the paper's case study: with a large flux-limited BB1
+    catalog the posterior means sit within a few posterior standard
+    deviations of the true (beta, ln l, ln u)."""
+    wl = synth.bb1_lf(n=20000, seed=65)
+    _say(f"bb1 case study N={wl.n}: 40000 cycles")
+    m = 40000
+    s = hbm.Sampler(wl, max_cycles=m)
+    s.run_cycles(m)
+    th = s.theta_trace()[m // 2:]
+    assert np.all(np.isfinite(th))
+    for j, name in enumerate(("beta", "ln l", "ln u")):
+        mean, sd = th[:, j].mean(), th[:, j].std()
+        z = abs(mean - wl.theta_true[j]) / sd
+        _say(f"  {name}: posterior {mean:.4f} ± {sd:.4f}, truth {wl.theta_true[j]:.4f}, z={z:.2f}")
+        assert z < 4.0
