@@ -62,6 +62,8 @@ def lib(path: str = None):
         L.orc_pop_sum.restype = d
         L.orc_pop_terms.argtypes = [P, P, P, P]
         L.orc_log_post.argtypes = [P, P, P, P]
+        L.orc_marginal_terms.argtypes = [P, P, P]
+        L.orc_marginal_terms.restype = i32
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = i32
         L.orc_set_num_threads.argtypes = [i32]
@@ -219,6 +221,18 @@ class Oracle:
         out = np.zeros(self.n)
         self._L.orc_log_post(self._h, _ptr(th), _ptr(x), _ptr(out))
         return out
+
+    def marginal_terms(self, theta) -> np.ndarray:
+        """Per object: ln of the integral over chi of l_i(chi) f(chi; theta) (1-D latents)."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        out = np.zeros(self.n)
+        if self._L.orc_marginal_terms(self._h, _ptr(th), _ptr(out)) != 0:
+            raise ValueError("oracle: marginal likelihood needs a 1-D latent")
+        return out
+
+    def marginal_loglik(self, theta) -> float:
+        """sum_i ln int l_i f dchi - N ln Z(theta): the latent-free log-likelihood of theta."""
+        return float(np.sum(self.marginal_terms(theta))) - self.n * self.log_Z(theta)
 
     def pop_loglik(self, theta, chi) -> float:
         """sum_i log f(chi_i; theta) - N log Z(theta)."""

@@ -342,6 +342,69 @@ void orc_pop_terms(const orc_ctx *c, const double *theta, const double *chi, dou
 }
 
 /* ===================================================================== */
+/* Marginal likelihood of a 1-D latent by composite Gauss-Legendre panels */
+/* ===================================================================== */
+static double log_joint(const orc_ctx *c, int64_t i, double x, const double *theta)
+{
+    double lm, lp;
+    orc_log_terms(c, i, &x, theta, &lm, &lp);
+    return lm + lp;
+}
+
+/* Composite 20-point Gauss-Legendre rule of exp(g - shift) over [a, b] cut
+ * into panels no wider than h. */
+static double gl_composite(const orc_ctx *c, int64_t i, const double *theta, double shift, double a, double b,
+                           double h, const double *t20, const double *w20)
+{
+    if (!(b > a))
+        return 0.0;
+    int np = (int)ceil((b - a) / h);
+    double width = (b - a) / np, sum = 0.0;
+    for (int q = 0; q < np; q++) {
+        double lo = a + q * width, mid = lo + 0.5 * width;
+        for (int j = 0; j < 20; j++)
+            sum += 0.5 * width * w20[j] * exp(log_joint(c, i, mid + 0.5 * width * t20[j], theta) - shift);
+    }
+    return sum;
+}
+
+int orc_marginal_terms(const orc_ctx *c, const double *theta, double *out)
+{
+    if (c->d != 1)
+        return -1;
+    const double *col0 = c->data, *col1 = c->data + c->n;
+    double t20[20], w20[20];
+    orc_gauss_legendre(20, -1.0, 1.0, t20, w20);
+    for (int64_t i = 0; i < c->n; i++) {
+        /* where the integrand lives: the peak of the member likelihood (the
+         * datum) with its width in chi, or for the normal-normal model the
+         * exact peak and width of the product */
+        double centre, width;
+        if (c->model == ORC_NN1D) {
+            double y = col0[i], sig = col1[i], tau = exp(theta[1]);
+            double prec = 1.0 / (sig * sig) + 1.0 / (tau * tau);
+            centre = (y / (sig * sig) + theta[0] / (tau * tau)) / prec;
+            width = 1.0 / sqrt(prec);
+        } else {
+            double fhat = col0[i];
+            double sig = c->model == ORC_BB1 ? bb1_sigma(c, fhat) : c->consts[1];
+            centre = log(fhat) + col1[i];
+            width = fmin(sig / fhat, 1.0);
+        }
+        double shift = log_joint(c, i, centre, theta);
+        /* fine panels (a quarter width) within 40 widths of the peak, panels
+         * of 0.25 in chi out to 200 below and 15 above it */
+        double lo = centre - 40.0 * width, hi = centre + 40.0 * width;
+        double h_fine = fmin(0.25 * width, 0.25);
+        double total = gl_composite(c, i, theta, shift, centre - 200.0, lo, 0.25, t20, w20)
+                       + gl_composite(c, i, theta, shift, lo, hi, h_fine, t20, w20)
+                       + gl_composite(c, i, theta, shift, hi, centre + 15.0, 0.25, t20, w20);
+        out[i] = shift + log(total);
+    }
+    return 0;
+}
+
+/* ===================================================================== */
 /* Construction                                                           */
 /* ===================================================================== */
 orc_ctx *orc_new(int model, int64_t n, const double *data, const double *consts,

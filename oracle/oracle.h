@@ -70,6 +70,15 @@ void orc_log_post(const orc_ctx *c, const double *theta, const double *pts, doub
 /* out[i] = log f(chi_i; theta). */
 void orc_pop_terms(const orc_ctx *c, const double *theta, const double *chi, double *out);
 
+/* Per-object marginal likelihood of 1-D latents (models with d = 1):
+ * out[i] = ln of the integral over chi of exp(log l_i(chi) + log f(chi; theta)),
+ * with log l_i as in orc_log_terms (its constants included), by composite
+ * 20-point Gauss-Legendre panels, fine near the member likelihood's peak
+ * (Sec. 6 proposes marginalising low-dimensional latents by quadrature).
+ * The marginal log-likelihood of theta is sum_i out[i] - n ln Z(theta).
+ * Returns -1 for d > 1. */
+int orc_marginal_terms(const orc_ctx *c, const double *theta, double *out);
+
 /* One RAM sweep k (1-based) of every object at fixed theta.
  * chi [d][n], chol [d(d+1)/2][n] (packed lower, row-major), acc [n].
  * trace (nullable) [n][5]: lp_x, lp_y, ln_u, accepted, alpha. */

@@ -205,6 +205,30 @@ def pin_bb1_prior(path, rr):
     return abs((o.log_prior(b) - o.log_prior(a)) - ref) < 1e-13 and o.log_prior([-1.0, 0.5, 0.4]) == -math.inf
 
 
+def pin_marginal_nn1d(path, rr):
+    o = oracle.Oracle(synth.normal_normal_1d(n=50, seed=5), lib_path=path)
+    y, sig = o.wl.data
+    for mu, tau in ((0.1, 0.8), (5.0, 1e-3), (-2.0, 30.0)):
+        v = sig * sig + tau * tau
+        ref = np.log(sig / np.sqrt(v)) - (y - mu) ** 2 / (2.0 * v)
+        if np.max(np.abs(o.marginal_terms([mu, math.log(tau)]) - ref)) > 1e-12:
+            return False
+    return True
+
+
+def pin_marginal_bb1(path, rr):
+    o = _bb1_oracle(path)
+    th = [-1.5, math.log(0.01), 0.0]
+    i = int(np.argmin(o.wl.data[0]))
+    fhat, k = float(o.wl.data[0][i]), float(o.wl.data[1][i])
+    peak = math.log(fhat) + k
+    shift = sum(o.log_terms(i, [peak], th))
+    pts = [peak - 400, peak - 60, peak - 10, peak - 1, peak, peak + 1, peak + 15]
+    ref = shift + math.log(sum(integrate.quad(lambda x: math.exp(sum(o.log_terms(i, [x], th)) - shift), a, b,
+                                              limit=400, epsabs=0, epsrel=1e-13)[0] for a, b in zip(pts, pts[1:])))
+    return abs(o.marginal_terms(th)[i] - ref) < 1e-10
+
+
 MUTATIONS = [
     ("philox multiplier", "0xD2511F53u", "0xD2511F57u", pin_philox),
     ("philox key bump", "k1 += weyl1;", "k1 += weyl0;", pin_philox),
@@ -238,6 +262,12 @@ MUTATIONS = [
      "double sig = c->consts[1];", pin_bb1_efficiency),
     ("bb1 prior l factor", "return theta[1] - log(1.0 + theta[0] * theta[0]);",
      "return -theta[1] - log(1.0 + theta[0] * theta[0]);", pin_bb1_prior),
+    ("marginal scale not restored", "out[i] = shift + log(total);", "out[i] = log(total);", pin_marginal_nn1d),
+    ("marginal panel half-width", "sum += 0.5 * width * w20[j]", "sum += width * w20[j]", pin_marginal_nn1d),
+    ("marginal normal-normal centre", "centre = (y / (sig * sig) + theta[0] / (tau * tau)) / prec;",
+     "centre = y;", pin_marginal_nn1d),
+    ("marginal tail panel dropped", "double total = gl_composite(c, i, theta, shift, centre - 200.0, lo, 0.25, t20, w20)",
+     "double total = 0.0 * gl_composite(c, i, theta, shift, centre - 200.0, lo, 0.25, t20, w20)", pin_marginal_bb1),
 ]
 
 
