@@ -218,6 +218,28 @@ HBM_API hbm_status ram_sweep(hbm_ctx *ctx, int32_t n_sweeps, double *out_accept_
  * Synchronous. */
 HBM_API hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out);
 
+/* Marginal log-likelihood of theta with every object's latent integrated
+ * out by quadrature instead of sampled (Sec. 6 proposes this for objects
+ * with low-dimensional latents; conditional independence makes the N
+ * integrals independent):
+ *   out[j] = sum_i ln int l_i(chi) f(chi; theta_j) dchi - N ln Z(theta_j),
+ * with f the model's population density in chi and ln l_i the member
+ * log-likelihood as the sampler uses it: -z^2/2 for the normal-normal and
+ * gamma LF models (z the datum's residual in its standard errors), and
+ * -z^2/2 - ln sigma(F) for BB1; Z is the selection normaliser of
+ * flux-limited catalogs (1 otherwise).  Models with a 1-D
+ * latent only (normal-normal 1-D, gamma LF 1-D, BB1).  FP64 throughout.
+ * slot: a loaded slot; its data are read from the context's data buffer.
+ * theta: [n_theta][p] host, 1 <= n_theta <= 65535; out: [n_theta] host.
+ * terms (nullable): DEVICE buffer of n_theta * N doubles receiving the
+ * per-object log integrals, row j for theta_j.  Does not touch the chains.
+ * HBM_EDOMAIN when some theta_j lies where the population density does not
+ * exist (gamma LF: beta <= -1; BB1: beta <= -2); HBM_EINVAL for models with
+ * latents of higher dimension.  Grows a device scratch area on first use
+ * and when n_theta * N grows.  Synchronous. */
+HBM_API hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const double *theta, double *out,
+                                   double *terms);
+
 /* One Metropolis-Hastings step on theta of every active slot, for the
  * sweep just done: the
  * pending proposal theta' = theta + S_theta z (z from block (0, k, 1, b)) is
@@ -302,9 +324,9 @@ HBM_API hbm_status set_launch(hbm_ctx *ctx, int32_t tiles_per_group);
  * [3] microseconds per cycle for shapes 1, 2, 4.  Synchronous. */
 HBM_API hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t *out_tiles_per_group, double out_us[3]);
 
-/* Per-launch duration of the sweep kernel: when enabled, every sweep-kernel
- * launch carries a start and a stop hipEvent that the runtime records from
- * the dispatch itself (hipExtLaunchKernel), and run_cycles issues plain
+/* Per-launch duration of the sweep and marginal kernels: when enabled, every
+ * launch of either carries a start and a stop hipEvent that the runtime
+ * records from the dispatch itself (hipExtLaunchKernel), and run_cycles issues plain
  * launches instead of replaying its graph.  read returns the launches timed
  * and their mean duration in ms and resets the counters.  Synchronous read. */
 HBM_API hbm_status kernel_timing(hbm_ctx *ctx, int32_t enable);

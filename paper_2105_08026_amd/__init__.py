@@ -26,7 +26,7 @@ HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_
 HBM_FP64, HBM_FP32 = 1, 2
 
 EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
-            "ram_sweep", "pop_loglik", "theta_step", "run_cycles", "get_samples", "get_theta", "set_theta",
+            "ram_sweep", "pop_loglik", "marginal_loglik", "theta_step", "run_cycles", "get_samples", "get_theta", "set_theta",
             "ram_sweep_trace", "get_state", "set_state", "get_stats", "set_launch", "autotune", "kernel_timing",
             "read_kernel_timing", "last_error", "destroy_chains")
 
@@ -88,6 +88,7 @@ def lib():
             "slot_info": [P, i32, P],
             "ram_sweep": [P, i32, P],
             "pop_loglik": [P, P, P],
+            "marginal_loglik": [P, i32, i32, P, P, P],
             "theta_step": [P, P],
             "run_cycles": [P, i64, i32],
             "get_samples": [P, i32, i64, i64, P, P, P],
@@ -190,6 +191,18 @@ def pop_loglik(ctx, thetas) -> np.ndarray:
     out = np.zeros(th.shape[0])
     _check(lib().pop_loglik(ctx, _ptr(th), _ptr(out)), ctx)
     return out
+
+
+def marginal_loglik(ctx, slot: int, thetas, n: int, terms: bool = False, device=None):
+    """thetas: [n_theta][p]; returns [n_theta] latent-free log-likelihoods and,
+    with terms=True, also the [n_theta][n] per-object log integrals."""
+    th = _arr(thetas)
+    if th.ndim == 1:
+        th = th.reshape(1, -1)
+    out = np.zeros(th.shape[0])
+    tb = torch.empty((th.shape[0], n), dtype=torch.float64, device=device) if terms else None
+    _check(lib().marginal_loglik(ctx, slot, th.shape[0], _ptr(th), _ptr(out), tb.data_ptr() if terms else None), ctx)
+    return (out, tb.cpu().numpy()) if terms else out
 
 
 def theta_step(ctx, n_slots: int = 1) -> np.ndarray:
@@ -388,6 +401,10 @@ class Sampler(_Chains):
     def pop_loglik(self, theta) -> float:
         return float(pop_loglik(self.ctx, np.asarray(theta, dtype=np.float64).reshape(1, -1))[0])
 
+    def marginal_loglik(self, thetas, terms: bool = False):
+        """Latent-free log-likelihood at each row of thetas (1-D latents only)."""
+        return marginal_loglik(self.ctx, 0, thetas, self.n, terms, self.device)
+
     def theta(self):
         return get_theta(self.ctx, self.p)
 
@@ -477,6 +494,9 @@ class Batch(_Chains):
 
     def pop_loglik(self, thetas) -> np.ndarray:
         return pop_loglik(self.ctx, thetas)
+
+    def marginal_loglik(self, j: int, thetas, terms: bool = False):
+        return marginal_loglik(self.ctx, j, thetas, self.wls[j].n, terms, self.device)
 
     def theta(self, j: int):
         return get_theta(self.ctx, self.p, j)

@@ -13,6 +13,7 @@
 // datasets come and go.
 #include "hbm.h"
 #include "kernels.h"
+#include "marginal.h"
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -41,6 +42,8 @@ struct Launch {
     hbm_status (*prepare)(CtxImpl *);         // slots flagged in c->which
     hbm_status (*check_init)(CtxImpl *);      // slots flagged in c->which
     hbm_status (*quadrature)(CtxImpl *);      // reference Gauss-Legendre rule
+    hbm_status (*marginal)(CtxImpl *, int32_t slot, int32_t n_theta, const double *theta, double *out,
+                           double *partials, double *terms);   // device arguments
 };
 
 // Host mirror of one slot.  Every field follows from the calls made, so the
@@ -89,7 +92,12 @@ struct CtxImpl {
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t graph_len = 0;
-    // per-launch timing of the sweep kernel
+    // marginal likelihood: node tables (datum rule, then product rule) and a
+    // scratch area grown on demand for theta, results and partial sums
+    double2 *marg_rule = nullptr;
+    double *marg_buf = nullptr;
+    size_t marg_bytes = 0;
+    // per-launch timing of the sweep and marginal kernels
     bool timing = false;
     std::vector<hipEvent_t> ev_free, ev_pending;
     int64_t timed_launches = 0;
@@ -149,6 +157,16 @@ hipEvent_t take_event(CtxImpl *c)
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
+
+// Workgroups of the marginal kernel for n objects (kMargLanes lanes each).
+int32_t marg_blocks(int64_t n)
+{
+    constexpr int64_t per = kBlock / kMargLanes;
+    return static_cast<int32_t>((n + per - 1) / per);
+}
+
+constexpr int kMargShapeNodes = 2 * MargRuleShape::kCore + MargRuleShape::kGraded + MargRuleShape::kTail;
+constexpr int kMargProductNodes = 2 * MargRuleProduct::kCore;
 
 template <class M>
 struct Ops {
@@ -309,9 +327,46 @@ struct Ops {
         return HBM_OK;
     }
 
+    static hbm_status marginal(CtxImpl *c, int32_t slot, int32_t n_theta, const double *theta, double *out,
+                               double *partials, double *terms)
+    {
+        if constexpr (HasMarg<M>::value) {
+            using R = typename Marg<M>::R;
+            MargArgs a;
+            a.data = c->buf.data;
+            a.rule = c->marg_rule + (R::kGraded > 0 ? 0 : kMargShapeNodes);
+            a.theta = theta;
+            a.partials = partials;
+            a.terms = terms;
+            a.st = c->st + slot;
+            a.cap = c->cap;
+            a.n_blocks = marg_blocks(c->slots[slot].n);
+            const dim3 grid(static_cast<unsigned>(a.n_blocks), static_cast<unsigned>(n_theta));
+            if (c->timing) {
+                hipEvent_t e0 = take_event(c), e1 = take_event(c);
+                if (!e0 || !e1) return fail(c, HBM_ENOMEM, "hipEventCreate failed");
+                c->ev_pending.push_back(e0);
+                c->ev_pending.push_back(e1);
+                hipExtLaunchKernelGGL((marginal_kernel<M>), grid, dim3(kBlock), 0, c->stream, e0, e1, 0, a);
+            } else {
+                hipLaunchKernelGGL((marginal_kernel<M>), grid, dim3(kBlock), 0, c->stream, a);
+            }
+            LAUNCHCHK(c, "marginal_kernel");
+            const int64_t qo = static_cast<int64_t>(slot) * c->nq;
+            hipLaunchKernelGGL((marginal_finish_kernel<M>), dim3(static_cast<unsigned>(n_theta)), dim3(kBlock), 0,
+                               c->stream, theta, partials, a.n_blocks, c->st + slot, c->qx + qo, c->qw + qo,
+                               c->qeps + qo, c->nq, out);
+            LAUNCHCHK(c, "marginal_finish_kernel");
+            return HBM_OK;
+        } else {
+            (void)slot; (void)n_theta; (void)theta; (void)out; (void)partials; (void)terms;
+            return fail(c, HBM_EINVAL, "the marginal likelihood needs a model with a 1-D latent");
+        }
+    }
+
     static const Launch *table()
     {
-        static const Launch t{&sweep, &theta, &set_theta, &poplik, &prepare, &check_init, &quadrature};
+        static const Launch t{&sweep, &theta, &set_theta, &poplik, &prepare, &check_init, &quadrature, &marginal};
         return &t;
     }
 };
@@ -411,7 +466,7 @@ void release(CtxImpl *c)
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
     void *ptrs[] = {c->dd, c->partials, c->pout, c->theta_in, c->side, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
-                    c->cs, c->st, c->theta_trace, c->tile_ds, c->which};
+                    c->cs, c->st, c->theta_trace, c->tile_ds, c->which, c->marg_rule, c->marg_buf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete static_cast<hbm_ctx *>(c);
@@ -755,6 +810,75 @@ void after_theta_steps(Slot &s, int64_t n)
     if (s.budget > 0 && s.n_theta >= s.budget) s.active = false;
 }
 
+// Gauss-Legendre nodes and weights on [-1, 1] (host, FP64): Newton's method
+// on P_n from the asymptotic root guesses, P_n by the three-term recurrence.
+void host_gauss_legendre(int n, double *t, double *w)
+{
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < n; ++j) {
+        double x = std::cos(pi * (j + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int l = 1; l < n; ++l) {
+                const double p2 = ((2.0 * l + 1.0) * x * p1 - l * p0) / (l + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        t[j] = x;
+        w[j] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+// Node tables of the marginal likelihood (the layouts marginal.h documents).
+hbm_status ensure_marg_rule(CtxImpl *c)
+{
+    if (c->marg_rule) return HBM_OK;
+    std::vector<double2> r(kMargShapeNodes + kMargProductNodes);
+    double t[64], w[64];
+    using S = MargRuleShape;
+    host_gauss_legendre(S::kCore, t, w);
+    for (int q = 0; q < 2 * S::kCore; ++q) r[q] = double2{t[q % S::kCore], w[q % S::kCore]};
+    // graded panels from the top: 4 of width 0.25, 8 of 0.5, 8 of 1
+    constexpr int kPerPanel = 8;
+    host_gauss_legendre(kPerPanel, t, w);
+    double top = 0.0;
+    int q = 2 * S::kCore;
+    for (int panel = 0; panel < S::kGraded / kPerPanel; ++panel) {
+        const double width = panel < 4 ? 0.25 : panel < 12 ? 0.5 : 1.0;
+        for (int j = 0; j < kPerPanel; ++j)
+            r[q++] = double2{top + 0.5 * width * (1.0 - t[j]), 0.5 * width * w[j]};
+        top += width;
+    }
+    if (std::fabs(top - S::kDepth) > 1e-12) return fail(c, HBM_EINVAL, "marginal rule: graded panels miss the depth");
+    host_gauss_legendre(S::kTail, t, w);
+    for (int j = 0; j < S::kTail; ++j) r[q++] = double2{std::log(0.5 * (1.0 + t[j])), 0.5 * w[j]};
+    host_gauss_legendre(MargRuleProduct::kCore, t, w);
+    for (int j = 0; j < kMargProductNodes; ++j)
+        r[q++] = double2{t[j % MargRuleProduct::kCore], w[j % MargRuleProduct::kCore]};
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(double2) * r.size()) != hipSuccess) return fail(c, HBM_ENOMEM, "hipMalloc: marginal rule");
+    c->marg_rule = static_cast<double2 *>(p);
+    HIPCHK(c, hipMemcpyAsync(c->marg_rule, r.data(), sizeof(double2) * r.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HBM_OK;
+}
+
+// Values of theta at which the population density exists: the gamma law
+// needs beta + 1 > 0 and BB1 beta + 2 > 0 (its lower tail integrable).
+bool marg_density_ok(int model, const double *th)
+{
+    switch (model) {
+    case HBM_GAMMA_LF_1D: return th[0] > -1.0;
+    case HBM_BB1_LF: return th[0] > -2.0;
+    default: return true;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -948,6 +1072,43 @@ hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out)
         HIPCHK(c, hipMemcpyAsync(po.data(), c->pout, sizeof(double) * po.size(), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (int32_t j = 0; j < c->n_slots; ++j) out[j] = c->slots[j].loaded ? po[2 * j + 1] : static_cast<double>(NAN);
+        return HBM_OK;
+    });
+}
+
+hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const double *theta, double *out,
+                           double *terms)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        hbm_status st = check_slot(c, slot, true);
+        if (st != HBM_OK) return st;
+        if (c->d != 1) return fail(c, HBM_EINVAL, "the marginal likelihood needs a model with a 1-D latent");
+        if (n_theta < 1 || n_theta > 65535) return fail(c, HBM_EINVAL, "n_theta must be in [1, 65535]");
+        if (!theta || !out) return fail(c, HBM_EINVAL, "theta and out must be non-NULL");
+        for (int64_t j = 0; j < static_cast<int64_t>(n_theta) * c->p; ++j)
+            if (!std::isfinite(theta[j])) return fail(c, HBM_EINVAL, "theta must be finite");
+        for (int32_t j = 0; j < n_theta; ++j)
+            if (!marg_density_ok(c->pool.model, theta + static_cast<size_t>(j) * c->p))
+                return fail(c, HBM_EDOMAIN, "theta outside the domain of the population density");
+        if ((st = ensure_marg_rule(c)) != HBM_OK) return st;
+        const int64_t nb = marg_blocks(c->slots[slot].n);
+        const size_t n_th = static_cast<size_t>(n_theta) * c->p, n_part = static_cast<size_t>(n_theta) * nb;
+        const size_t need = sizeof(double) * (n_th + n_theta + n_part);
+        if (need > c->marg_bytes) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (c->marg_buf) HIPCHK(c, hipFree(c->marg_buf));
+            c->marg_buf = nullptr;
+            c->marg_bytes = 0;
+            void *p = nullptr;
+            if (hipMalloc(&p, need) != hipSuccess) return fail(c, HBM_ENOMEM, "hipMalloc: marginal scratch");
+            c->marg_buf = static_cast<double *>(p);
+            c->marg_bytes = need;
+        }
+        double *d_theta = c->marg_buf, *d_out = d_theta + n_th, *d_part = d_out + n_theta;
+        HIPCHK(c, hipMemcpyAsync(d_theta, theta, sizeof(double) * n_th, hipMemcpyHostToDevice, c->stream));
+        if ((st = c->ops->marginal(c, slot, n_theta, d_theta, d_out, d_part, terms)) != HBM_OK) return st;
+        HIPCHK(c, hipMemcpyAsync(out, d_out, sizeof(double) * n_theta, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
         return HBM_OK;
     });
 }
