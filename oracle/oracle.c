@@ -393,12 +393,30 @@ int orc_marginal_terms(const orc_ctx *c, const double *theta, double *out)
         }
         double shift = log_joint(c, i, centre, theta);
         /* fine panels (a quarter width) within 40 widths of the peak, panels
-         * of 0.25 in chi out to 200 below and 15 above it */
+         * of 0.25 in chi out to 200 below and 15 above it (above the datum
+         * the member likelihood falls faster than any normal in chi) */
         double lo = centre - 40.0 * width, hi = centre + 40.0 * width;
         double h_fine = fmin(0.25 * width, 0.25);
         double total = gl_composite(c, i, theta, shift, centre - 200.0, lo, 0.25, t20, w20)
                        + gl_composite(c, i, theta, shift, lo, hi, h_fine, t20, w20)
                        + gl_composite(c, i, theta, shift, hi, centre + 15.0, 0.25, t20, w20);
+        /* further down in unit panels: far below the datum and below the
+         * population's own features (ln L*, ln l, ln u, mu) the integrand
+         * only falls, as a power of L, which for BB1 near beta = -2 is
+         * slow; stop at the first panel there that adds < 1e-17 of the total */
+        double feature = centre;
+        if (c->model == ORC_NN1D)
+            feature = fmin(feature, theta[0]);
+        else
+            feature = fmin(feature, theta[1]);
+        if (c->model == ORC_BB1)
+            feature = fmin(feature, theta[2]);
+        for (double top = centre - 200.0; top > -1e6; top -= 1.0) {
+            double add = gl_composite(c, i, theta, shift, top - 1.0, top, 1.0, t20, w20);
+            total += add;
+            if (top < feature - 40.0 && !(add > 1e-17 * total))
+                break;
+        }
         out[i] = shift + log(total);
     }
     return 0;

@@ -68,7 +68,7 @@ def _thetas(wl):
     if wl.model == synth.GammaLF1D:
         return [t0, t0 + [0.05, -0.1], [-0.9, t0[1] + 1.0], [-0.05, t0[1] - 1.5], [-0.5, t0[1] - 3.0]]
     return [t0, t0 + [0.1, 0.2, -0.1], [-1.2, t0[1] + 0.5, t0[2] + 0.2], [-0.1, t0[1] + 1.0, t0[2] - 0.3],
-            [-1.8, t0[1] - 1.0, t0[2] + 0.5], [-1.5, t0[1], t0[2] - 2.0]]
+            [-1.8, t0[1] - 1.0, t0[2] + 0.5], [-1.5, t0[1], t0[2] - 2.0], [-1.95, t0[1], t0[2]]]
 
 
 WORKLOADS = {

@@ -135,3 +135,19 @@ def test_three_d_latents_are_refused():
     o = oracle.Oracle(synth.normal_normal_3d(n=8))
     with pytest.raises(ValueError):
         o.marginal_terms([0.0, 0.0, 0.0])
+
+
+def test_bb1_slow_power_tail(bb1):
+    """Near beta = -2 the luminosity PDF falls only as L^(beta + 2) below l:
+    the integral reaches hundreds of e-folds below the datum."""
+    th = [-1.95, math.log(0.01), 0.0]
+    got = bb1.marginal_terms(th)
+    for i in (0, 11):
+        fhat, k = float(bb1.wl.data[0][i]), float(bb1.wl.data[1][i])
+        peak = math.log(fhat) + k
+        shift = sum(bb1.log_terms(i, [peak], th))
+        g = lambda x: math.exp(sum(bb1.log_terms(i, [x], th)) - shift)
+        pts = [peak - 60, peak - 10, peak - 1, peak, peak + 1, peak + 15]
+        v = integrate.quad(g, -np.inf, pts[0], limit=400, epsabs=0, epsrel=1e-12)[0]
+        v += sum(integrate.quad(g, a, b, limit=400, epsabs=0, epsrel=1e-13)[0] for a, b in zip(pts, pts[1:]))
+        assert abs(got[i] - (shift + math.log(v))) < 1e-9, i

@@ -229,6 +229,19 @@ def pin_marginal_bb1(path, rr):
     return abs(o.marginal_terms(th)[i] - ref) < 1e-10
 
 
+def pin_marginal_bb1_slow_tail(path, rr):
+    o = _bb1_oracle(path)
+    th = [-1.95, math.log(0.01), 0.0]
+    fhat, k = float(o.wl.data[0][0]), float(o.wl.data[1][0])
+    peak = math.log(fhat) + k
+    shift = sum(o.log_terms(0, [peak], th))
+    g = lambda x: math.exp(sum(o.log_terms(0, [x], th)) - shift)
+    pts = [peak - 60, peak - 10, peak - 1, peak, peak + 1, peak + 15]
+    v = integrate.quad(g, -np.inf, pts[0], limit=400, epsabs=0, epsrel=1e-12)[0]
+    v += sum(integrate.quad(g, a, b, limit=400, epsabs=0, epsrel=1e-13)[0] for a, b in zip(pts, pts[1:]))
+    return abs(o.marginal_terms(th)[0] - (shift + math.log(v))) < 1e-9
+
+
 MUTATIONS = [
     ("philox multiplier", "0xD2511F53u", "0xD2511F57u", pin_philox),
     ("philox key bump", "k1 += weyl1;", "k1 += weyl0;", pin_philox),
@@ -268,6 +281,8 @@ MUTATIONS = [
      "centre = y;", pin_marginal_nn1d),
     ("marginal tail panel dropped", "double total = gl_composite(c, i, theta, shift, centre - 200.0, lo, 0.25, t20, w20)",
      "double total = 0.0 * gl_composite(c, i, theta, shift, centre - 200.0, lo, 0.25, t20, w20)", pin_marginal_bb1),
+    ("marginal power tail cut at 200 e-folds", "if (top < feature - 40.0 && !(add > 1e-17 * total))",
+     "if (1)", pin_marginal_bb1_slow_tail),
 ]
 
 
