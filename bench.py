@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="gamma_lf_1d",
                     choices=["gamma_lf_1d", "gamma_lf_color_3d", "normal_normal_1d", "normal_normal_3d",
-                             "bb1_lf", "gamma_lf_batch256", "serving"])
+                             "bb1_lf", "gamma_lf_batch256", "serving", "marginal_gamma_lf_1d", "marginal_bb1_lf",
+                             "marginal_normal_normal_1d"])
     ap.add_argument("--horizon", type=float, default=60.0, help="serving: seconds of Poisson arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--sat-jobs", type=int, default=200, help="serving: jobs in the saturation run")
@@ -58,6 +59,8 @@ def parse():
                     help="tiles per sweep workgroup; auto runs the autotuner during burn-in")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 20 times (calibration run for HBM counters)")
+    ap.add_argument("--thetas", type=int, default=64,
+                    help="marginal workloads: theta rows evaluated per call (one step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -300,6 +303,101 @@ def bench_serving(args, torch, synth, hbm):
     print(json.dumps(out), flush=True)
 
 
+# FP64 operations per node evaluation of the marginal kernel (an FMA counts
+# two), from the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters of the
+# marginal bench command divided by the node evaluations it made.
+FLOPS_PER_NODE = {"marginal_gamma_lf_1d": None, "marginal_bb1_lf": None, "marginal_normal_normal_1d": None}
+FP64_PEAK_TFLOPS = 78.6
+NODES_PER_OBJECT = {"marginal_gamma_lf_1d": 216, "marginal_bb1_lf": 216, "marginal_normal_normal_1d": 48}
+
+
+def cpu_baseline_marginal(wl, theta, seconds: float):
+    """The oracle's marginal terms, timed on a bounded prefix of the catalog."""
+    import copy
+
+    import oracle
+
+    oracle.build(force=False)
+    m = min(wl.n, 2000)
+    sub = copy.copy(wl)
+    sub.data = np.ascontiguousarray(wl.data[:, :m])
+    sub.chi0 = np.ascontiguousarray(wl.chi0[:, :m])
+    sub.n = m
+    o = oracle.Oracle(sub)
+    o.marginal_terms(theta)
+    done, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        o.marginal_terms(theta)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": m * done / dt, "unit": "object integrals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} evaluations of the first {m} objects' marginal terms at one theta ({dt:.1f} s, FP64, "
+                      "one thread)"}
+
+
+def bench_marginal(args, torch, synth, hbm):
+    """Latent-free log-likelihood of theta, each object's latent integrated out
+    by per-object quadrature (Sec. 6).  A step is one call evaluating
+    --thetas theta rows over the whole catalog."""
+    make = {"marginal_gamma_lf_1d": (synth.gamma_lf_1d, 300_000), "marginal_bb1_lf": (synth.bb1_lf, 100_000),
+            "marginal_normal_normal_1d": (synth.normal_normal_1d, 300_000)}
+    gen, n_default = make[args.workload]
+    wl = gen(n=args.n or n_default)
+    s = hbm.Sampler(wl, device="cuda:0", max_cycles=8)
+    rng = np.random.default_rng(0)
+    th0 = np.array(wl.theta_true, dtype=np.float64)
+    ths = th0 + 0.01 * rng.standard_normal((args.thetas, wl.p))
+    for _ in range(max(1, args.warmup // 20)):
+        s.marginal_loglik(ths)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = s.marginal_loglik(ths)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert np.all(np.isfinite(out)), "non-finite marginal log-likelihood"
+    # kernel durations from HIP events on the sampler's stream
+    n_ev = min(args.steps, 200)
+    hbm.kernel_timing(s.ctx, True)
+    for _ in range(n_ev):
+        s.marginal_loglik(ths)
+    n_launch, kern_ms = hbm.read_kernel_timing(s.ctx)
+    hbm.kernel_timing(s.ctx, False)
+    # one theta per call: the rate a Metropolis chain on theta would step at
+    n_one = 1000
+    t1 = time.perf_counter()
+    for j in range(n_one):
+        s.marginal_loglik(ths[j % args.thetas])
+    one_wall = time.perf_counter() - t1
+    hbm.kernel_timing(s.ctx, True)
+    for j in range(200):
+        s.marginal_loglik(ths[j % args.thetas])
+    _, kern_one_ms = hbm.read_kernel_timing(s.ctx)
+    hbm.kernel_timing(s.ctx, False)
+    nodes = NODES_PER_OBJECT[args.workload] * wl.n * args.thetas
+    fpn = FLOPS_PER_NODE[args.workload]
+    achieved = fpn * nodes / (kern_ms * 1e-3) / 1e12 if (fpn and kern_ms > 0) else None
+    out = {
+        "metric": METRIC, "value": wl.n * args.thetas * args.steps / wall, "unit": "object integrals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": f"synthetic (seeded {wl.name} catalog; theta rows near the truth)",
+        "config": {"workload": args.workload, "n_objects": wl.n, "thetas_per_step": args.thetas,
+                   "nodes_per_object": NODES_PER_OBJECT[args.workload]},
+        "theta_evaluations_per_s": args.thetas * args.steps / wall,
+        "single_theta": {"calls_per_s": n_one / one_wall, "ms_per_call": 1e3 * one_wall / n_one,
+                         "kernel_ms": kern_one_ms},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": None,
+                     "kernel": f"marginal_kernel<{wl.name}>", "flops_per_node": fpn, "node_evaluations": nodes,
+                     "kernel_ms": kern_ms, "launches_timed": n_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_marginal(wl, th0, args.cpu_seconds)
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -327,6 +425,9 @@ def main():
         return
     if args.workload == "serving":
         bench_serving(args, torch, synth, hbm)
+        return
+    if args.workload.startswith("marginal_"):
+        bench_marginal(args, torch, synth, hbm)
         return
     make = {"gamma_lf_1d": (synth.gamma_lf_1d, 300_000), "gamma_lf_color_3d": (synth.gamma_lf_3d, 1_000_000),
             "normal_normal_1d": (synth.normal_normal_1d, 300_000), "normal_normal_3d": (synth.normal_normal_3d, 300_000),
