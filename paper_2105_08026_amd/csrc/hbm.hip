@@ -94,7 +94,7 @@ struct CtxImpl {
     int64_t graph_len = 0;
     // marginal likelihood: node tables (datum rule, then product rule) and a
     // scratch area grown on demand for theta, results and partial sums
-    double2 *marg_rule = nullptr;
+    MargNode *marg_rule = nullptr;
     double *marg_buf = nullptr;
     size_t marg_bytes = 0;
     // per-launch timing of the sweep and marginal kernels
@@ -838,11 +838,11 @@ void host_gauss_legendre(int n, double *t, double *w)
 hbm_status ensure_marg_rule(CtxImpl *c)
 {
     if (c->marg_rule) return HBM_OK;
-    std::vector<double2> r(kMargShapeNodes + kMargProductNodes);
+    std::vector<MargNode> r(kMargShapeNodes + kMargProductNodes);
     double t[64], w[64];
     using S = MargRuleShape;
     host_gauss_legendre(S::kCore, t, w);
-    for (int q = 0; q < 2 * S::kCore; ++q) r[q] = double2{t[q % S::kCore], w[q % S::kCore]};
+    for (int q = 0; q < 2 * S::kCore; ++q) r[q] = MargNode{t[q % S::kCore], w[q % S::kCore], 0.0, 0.0};
     // graded panels from the top: 4 of width 0.25, 8 of 0.5, 8 of 1
     constexpr int kPerPanel = 8;
     host_gauss_legendre(kPerPanel, t, w);
@@ -850,20 +850,23 @@ hbm_status ensure_marg_rule(CtxImpl *c)
     int q = 2 * S::kCore;
     for (int panel = 0; panel < S::kGraded / kPerPanel; ++panel) {
         const double width = panel < 4 ? 0.25 : panel < 12 ? 0.5 : 1.0;
-        for (int j = 0; j < kPerPanel; ++j)
-            r[q++] = double2{top + 0.5 * width * (1.0 - t[j]), 0.5 * width * w[j]};
+        for (int j = 0; j < kPerPanel; ++j) {
+            const double depth = top + 0.5 * width * (1.0 - t[j]);
+            r[q++] = MargNode{depth, 0.5 * width * w[j], std::exp(-depth), 0.0};
+        }
         top += width;
     }
     if (std::fabs(top - S::kDepth) > 1e-12) return fail(c, HBM_EINVAL, "marginal rule: graded panels miss the depth");
     host_gauss_legendre(S::kTail, t, w);
-    for (int j = 0; j < S::kTail; ++j) r[q++] = double2{std::log(0.5 * (1.0 + t[j])), 0.5 * w[j]};
+    for (int j = 0; j < S::kTail; ++j) r[q++] = MargNode{std::log(0.5 * (1.0 + t[j])), 0.5 * w[j], 0.0, 0.0};
     host_gauss_legendre(MargRuleProduct::kCore, t, w);
     for (int j = 0; j < kMargProductNodes; ++j)
-        r[q++] = double2{t[j % MargRuleProduct::kCore], w[j % MargRuleProduct::kCore]};
+        r[q++] = MargNode{t[j % MargRuleProduct::kCore], w[j % MargRuleProduct::kCore], 0.0, 0.0};
     void *p = nullptr;
-    if (hipMalloc(&p, sizeof(double2) * r.size()) != hipSuccess) return fail(c, HBM_ENOMEM, "hipMalloc: marginal rule");
-    c->marg_rule = static_cast<double2 *>(p);
-    HIPCHK(c, hipMemcpyAsync(c->marg_rule, r.data(), sizeof(double2) * r.size(), hipMemcpyHostToDevice, c->stream));
+    if (hipMalloc(&p, sizeof(MargNode) * r.size()) != hipSuccess)
+        return fail(c, HBM_ENOMEM, "hipMalloc: marginal rule");
+    c->marg_rule = static_cast<MargNode *>(p);
+    HIPCHK(c, hipMemcpyAsync(c->marg_rule, r.data(), sizeof(MargNode) * r.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HBM_OK;
 }

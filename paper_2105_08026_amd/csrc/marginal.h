@@ -48,12 +48,16 @@ struct MargGeo {
     double c0, h0, c1, h1;
     double k;
     double xa, xt;
+    double fa, ft;     // flux at chi_A and at chi_T
 };
 
 // Rules, laid out per node q (the host fills the tables):
-//   core nodes    (t, w) of Gauss-Legendre on [-1, 1];
-//   graded nodes  (depth below chi_A, weight);
-//   tail nodes    (ln v, weight) on v in (0, 1].
+//   core nodes    a = t, w of Gauss-Legendre on [-1, 1];
+//   graded nodes  a = depth below chi_A, w = weight, e = e^-depth;
+//   tail nodes    a = ln v, w = weight, on v in (0, 1].
+struct MargNode {
+    double a, w, e, pad;
+};
 struct MargRuleShape {
     static constexpr int kCore = 20, kGraded = 160, kTail = 16;
     static constexpr double kSigmas = 9.0, kClip = 0.25, kDepth = 13.0;
@@ -65,6 +69,9 @@ struct MargRuleProduct {
 
 template <class M>
 struct Marg;
+
+// Value of lane `lane` in every lane (lane is wave-uniform).
+__device__ __forceinline__ double bcast(double v, int lane) { return lane_f64(v, lane); }
 
 template <class M>
 struct HasMarg {
@@ -103,20 +110,29 @@ struct Marg<NN1D> {
         const double prec = o.is2 + t.itau2;
         const double m = (o.y * o.is2 + t.mu * t.itau2) / prec;
         const double half = 0.5 * R::kSigmas / sqrt(prec);
-        return MargGeo{m - half, half, m + half, half, 0.0, 0.0, 0.0};
+        return MargGeo{m - half, half, m + half, half, 0.0, 0.0, 0.0, 0.0, 0.0};
     }
-    __device__ static double logh(const Obj &o, double x, const Th &t, const Statics &)
+    struct Pre {};
+    __device__ static Pre pre(const Obj &, const Th &, const Statics &) { return Pre{}; }
+    __device__ static double logh(const Obj &o, const Pre &, double, double x, const Th &t)
     {
         const double r = o.y - x, v = x - t.mu;
         return -0.5 * (r * r) * o.is2 - 0.5 * (v * v) * t.itau2 - t.lnorm;
     }
-    __device__ static double log_tail(const Obj &, double, const Th &, const Statics &) { return 0.0; }
+    __device__ static double log_tail(const Obj &, const Pre &, double, double, const Th &) { return 0.0; }
+    __device__ static double log_l_below(const Obj &, double, const Statics &) { return 0.0; }
+    __device__ static void bcast(const Obj &o, const Pre &, Obj &oj, Pre &, int src)
+    {
+        oj = Obj{hbm::bcast(o.y, src), hbm::bcast(o.is2, src)};
+    }
 };
 
 // ---------------------------------------------------------------------------
 // Gamma luminosity function, constant flux error (Sec. 4-5):
-// log l = -((Fhat - e^(x - k)) / sigma_F)^2 / 2,
+// log l = -((Fhat - F) / sigma_F)^2 / 2, F = e^(x - k),
 // log f = (beta + 1)(x - ln L*) - e^(x - ln L*) - lnGamma(beta + 1).
+// The nodes know the flux F (in the core it is the variable itself), so
+// e^(x - ln L*) = F e^(k - ln L*) with one exponential per object.
 // ---------------------------------------------------------------------------
 template <>
 struct Marg<LF1D> {
@@ -128,6 +144,10 @@ struct Marg<LF1D> {
     struct Obj {
         double fh, k;
     };
+    struct Pre {
+        double ekl;      // e^(k - ln L*)
+        double isig;
+    };
     __device__ static Th prep(const double *th)
     {
         const double a = th[0] + 1.0;
@@ -138,22 +158,32 @@ struct Marg<LF1D> {
         const float *d = static_cast<const float *>(data);
         return Obj{static_cast<double>(d[i]), static_cast<double>(d[cap + i])};
     }
+    __device__ static Pre pre(const Obj &o, const Th &t, const Statics &s)
+    {
+        return Pre{exp(o.k - t.lnls), 1.0 / s.mc[1]};
+    }
     __device__ static double sigma(const Obj &, const Statics &s) { return s.mc[1]; }
     __device__ static double alpha(const Statics &) { return 0.0; }
-    __device__ static double log_meas(const Obj &o, double x, const Statics &s)
+    // ln of sup l over F <= fa (l rises with F below the datum)
+    __device__ static double log_l_below(const Obj &o, double fa, const Statics &s)
     {
-        const double z = (o.fh - exp(x - o.k)) / s.mc[1];
+        const double z = (o.fh - fa) / s.mc[1];
         return -0.5 * z * z;
     }
-    __device__ static double logh(const Obj &o, double x, const Th &t, const Statics &s)
+    // log l + log f - g x at flux F and x = ln F + k
+    __device__ static double log_tail(const Obj &o, const Pre &p, double flux, double, const Th &t)
     {
-        const double q = x - t.lnls;
-        return log_meas(o, x, s) + t.a * q - exp(q) - t.lga;
+        const double z = (o.fh - flux) * p.isig;
+        return -0.5 * z * z - t.a * t.lnls - flux * p.ekl - t.lga;
     }
-    // log l + log f - g x
-    __device__ static double log_tail(const Obj &o, double x, const Th &t, const Statics &s)
+    __device__ static double logh(const Obj &o, const Pre &p, double flux, double x, const Th &t)
     {
-        return log_meas(o, x, s) - t.a * t.lnls - exp(x - t.lnls) - t.lga;
+        return t.a * x + log_tail(o, p, flux, x, t);
+    }
+    __device__ static void bcast(const Obj &o, const Pre &p, Obj &oj, Pre &pj, int src)
+    {
+        oj = Obj{hbm::bcast(o.fh, src), hbm::bcast(o.k, src)};
+        pj = Pre{hbm::bcast(p.ekl, src), p.isig};
     }
 };
 
@@ -162,7 +192,8 @@ struct Marg<LF1D> {
 // log l = -(Fhat - F)^2 / (2 sigma(F)^2) - ln sigma(F), F = e^(x - k),
 // log f = ln C + (beta + 1)(x - ln u) + ln(1 - e^(-L/l)) - L/u.
 // The break factor is written as ln(L/l) + ln phi(L/l), phi(y) = (1 - e^-y)/y,
-// which stays finite however far below l the node lies.
+// which stays finite however far below l the node lies; L/l and L/u are the
+// flux times per-object factors.
 // ---------------------------------------------------------------------------
 template <>
 struct Marg<BB1> {
@@ -174,6 +205,11 @@ struct Marg<BB1> {
     struct Obj {
         double fh, k;
     };
+    struct Pre {
+        double ekl, eku;     // e^(k - ln l), e^(k - ln u)
+        double c0;           // ln C - (beta + 1) ln u - ln l
+        double s2, a2;       // sigma0^2, alpha^2
+    };
     __device__ static Th prep(const double *th)
     {
         const double g = th[0] + 2.0;
@@ -184,34 +220,41 @@ struct Marg<BB1> {
         const float *d = static_cast<const float *>(data);
         return Obj{static_cast<double>(d[i]), static_cast<double>(d[cap + i])};
     }
+    __device__ static Pre pre(const Obj &o, const Th &t, const Statics &s)
+    {
+        return Pre{exp(o.k - t.lnl), exp(o.k - t.lnu), t.lnc - t.b1 * t.lnu - t.lnl, s.mc[1] * s.mc[1],
+                   s.mc[2] * s.mc[2]};
+    }
     __device__ static double sigma(const Obj &o, const Statics &s)
     {
         return sqrt(s.mc[1] * s.mc[1] + s.mc[2] * s.mc[2] * o.fh * o.fh);
     }
     __device__ static double alpha(const Statics &s) { return s.mc[2]; }
-    __device__ static double log_meas(const Obj &o, double x, const Statics &s)
+    // sup of l over F <= fa: the normal factor rises with F below the datum
+    // and 1 / sigma(F) is at most 1 / sigma0
+    __device__ static double log_l_below(const Obj &o, double fa, const Statics &s)
     {
-        const double flux = exp(x - o.k);
-        const double var = s.mc[1] * s.mc[1] + s.mc[2] * s.mc[2] * flux * flux;
+        const double r = o.fh - fa;
+        return -0.5 * (r * r) / (s.mc[1] * s.mc[1] + s.mc[2] * s.mc[2] * fa * fa) - log(s.mc[1]);
+    }
+    // log l + log f - (beta + 2) x; -ln sigma(F) and ln phi share one log
+    // (phi lies in [e^-y, 1], far from the ends of the double range here)
+    __device__ static double log_tail(const Obj &o, const Pre &p, double flux, double, const Th &)
+    {
+        const double var = p.s2 + p.a2 * flux * flux;
         const double r = o.fh - flux;
-        return -0.5 * (r * r) / var - 0.5 * log(var);
+        const double y = flux * p.ekl;
+        const double phi = y > 1e-300 ? -expm1(-y) / y : 1.0;
+        return -0.5 * (r * r) / var + 0.5 * log(phi * phi / var) + p.c0 - flux * p.eku;
     }
-    __device__ static double log_phi(double y)
+    __device__ static double logh(const Obj &o, const Pre &p, double flux, double x, const Th &t)
     {
-        return y > 1e-300 ? log(-expm1(-y) / y) : 0.0;
+        return t.g * x + log_tail(o, p, flux, x, t);
     }
-    // log f - (beta + 2) x
-    __device__ static double log_psi(double x, const Th &t)
+    __device__ static void bcast(const Obj &o, const Pre &p, Obj &oj, Pre &pj, int src)
     {
-        return t.lnc - t.b1 * t.lnu - t.lnl + log_phi(exp(x - t.lnl)) - exp(x - t.lnu);
-    }
-    __device__ static double logh(const Obj &o, double x, const Th &t, const Statics &s)
-    {
-        return log_meas(o, x, s) + t.g * x + log_psi(x, t);
-    }
-    __device__ static double log_tail(const Obj &o, double x, const Th &t, const Statics &s)
-    {
-        return log_meas(o, x, s) + log_psi(x, t);
+        oj = Obj{hbm::bcast(o.fh, src), hbm::bcast(o.k, src)};
+        pj = Pre{hbm::bcast(p.ekl, src), hbm::bcast(p.eku, src), p.c0, p.s2, p.a2};
     }
 };
 
@@ -225,7 +268,7 @@ __device__ __forceinline__ MargGeo datum_geo(const typename G::Obj &o, const Sta
     const double fb = o.fh + R::kSigmas * sig / (1.0 - R::kSigmas * G::alpha(s));
     const double xa = o.k + log(fa);
     return MargGeo{0.5 * (fa + o.fh), 0.5 * (o.fh - fa), 0.5 * (o.fh + fb), 0.5 * (fb - o.fh), o.k, xa,
-                   xa - R::kDepth};
+                   xa - R::kDepth, fa, fa * exp(-R::kDepth)};
 }
 
 template <class G>
@@ -237,7 +280,7 @@ __device__ __forceinline__ MargGeo marg_geo(const typename G::Obj &o, const type
 
 struct MargArgs {
     const void *data;          // the context's packed data [components][cap]
-    const double2 *rule;       // per node q: see MargRuleShape / MargRuleProduct
+    const MargNode *rule;      // per node q: see MargRuleShape / MargRuleProduct
     const double *theta;       // [n_theta][p]
     double *partials;          // [n_theta][n_blocks]
     double *terms;             // [n_theta][n] or nullptr
@@ -246,75 +289,164 @@ struct MargArgs {
     int32_t n_blocks;
 };
 
-// Node value: log of (integrand x Jacobian) at node q, and its weight.
+// Core node: log of (integrand x Jacobian) at node q of the object's core
+// and its weight; the core variable is the flux for datum-centred models.
 template <class G, int kRow>
-__device__ __forceinline__ double marg_node(const typename G::Obj &o, const typename G::Th &t, const Statics &s,
-                                            const MargGeo &g, double2 rq, int q, double &w)
+__device__ __forceinline__ double core_node(const typename G::Obj &o, const typename G::Pre &p,
+                                            const typename G::Th &t, const MargGeo &g, const MargNode &rq, int q,
+                                            double &w)
 {
     using R = typename G::R;
-    constexpr int q0 = kRow * kMargLanes;
-    if constexpr (q0 < 2 * R::kCore) {
-        const bool up = q >= R::kCore;
-        const double c = up ? g.c1 : g.c0, h = up ? g.h1 : g.h0;
-        w = h * rq.y;
-        const double u = c + h * rq.x;
-        if constexpr (G::kFlux) {
-            const double lu = log(u);
-            return G::logh(o, g.k + lu, t, s) - lu;      // dchi = dF / F
-        } else {
-            return G::logh(o, u, t, s);
-        }
-    } else if constexpr (q0 < 2 * R::kCore + R::kGraded) {
-        w = rq.y;
-        return G::logh(o, g.xa - rq.x, t, s);
+    const bool up = q >= R::kCore;
+    const double c = up ? g.c1 : g.c0, h = up ? g.h1 : g.h0;
+    w = h * rq.w;
+    const double u = c + h * rq.a;
+    if constexpr (G::kFlux) {
+        const double lu = log(u);
+        return G::logh(o, p, u, g.k + lu, t) - lu;      // dchi = dF / F
     } else {
-        w = rq.y;
-        return G::log_tail(o, g.xt + rq.x / t.g, t, s) + t.g * g.xt - t.lng;
+        return G::logh(o, p, 0.0, u, t);
     }
 }
 
 template <class G, int... r>
-__device__ __forceinline__ void marg_rows(const typename G::Obj &o, const typename G::Th &t, const Statics &s,
-                                          const MargGeo &g, const double2 *rule, int sub, double *hv, double *wv,
+__device__ __forceinline__ void core_rows(const typename G::Obj &o, const typename G::Pre &p, const typename G::Th &t,
+                                          const MargGeo &g, const MargNode *rule, int sub, double *hv, double *wv,
                                           std::integer_sequence<int, r...>)
 {
-    ((hv[r] = marg_node<G, r>(o, t, s, g, rule[r * kMargLanes + sub], r * kMargLanes + sub, wv[r])), ...);
+    ((hv[r] = core_node<G, r>(o, p, t, g, rule[r * kMargLanes + sub], r * kMargLanes + sub, wv[r])), ...);
 }
+
+// Node q (0-based) of the region below chi_A: graded panels, then the tail.
+// On the graded panels F = F_A e^-(depth), the factor held by the table.
+template <class G>
+__device__ __forceinline__ double below_node(const typename G::Obj &o, const typename G::Pre &p,
+                                             const typename G::Th &t, const MargGeo &g, const MargNode &rq, int q,
+                                             double &w)
+{
+    using R = typename G::R;
+    if (q < R::kGraded) {
+        w = rq.w;
+        return G::logh(o, p, g.fa * rq.e, g.xa - rq.a, t);
+    }
+    if (q < R::kGraded + R::kTail) {
+        w = rq.w;
+        const double d = rq.a / t.g;                    // chi - chi_T
+        return G::log_tail(o, p, g.ft * exp(d), g.xt + d, t) + t.g * g.xt - t.lng;
+    }
+    w = 0.0;
+    return -HUGE_VAL;
+}
+
+// max and sum over the kMargLanes lanes of one object (every lane gets the
+// same bits: each butterfly step combines the same two values in either order)
+__device__ __forceinline__ double group_max(double v)
+{
+#pragma unroll
+    for (int d = 1; d < kMargLanes; d <<= 1) v = fmax(v, __shfl_xor(v, d, kMargLanes));
+    return v;
+}
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int d = 1; d < kMargLanes; d <<= 1) v += __shfl_xor(v, d, kMargLanes);
+    return v;
+}
+
+// Wavefront max with the fixed DPP pattern of wave_sum; uniform result.
+__device__ __forceinline__ double wave_max(double v)
+{
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x124>(v));
+    v = fmax(v, dpp_f64<0x128>(v));
+    return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
+}
+
+// Below chi_A the member likelihood is at most its value at F_A (times
+// sigma(F_A) / sigma0 for BB1) and the population density integrates to at
+// most 1 there, so that region adds at most e^(log_l_below) to the
+// integral.  An object skips it when this bound is below e^-30 of its core
+// integral: the log integral then changes by less than 1e-13.
+constexpr double kSkipBelow = -30.0;
 
 // grid (n_blocks, n_theta); each workgroup covers kBlock / kMargLanes objects
 // of the slot for one theta and writes one FP64 partial sum of their terms.
+// Core: eight lanes per object.  Region below chi_A: the objects of a
+// wavefront that need it are taken one at a time by all 64 lanes, so a
+// wavefront pays for the objects that need it, not for its slowest group.
 template <class M>
 __global__ __launch_bounds__(kBlock) void marginal_kernel(MargArgs a)
 {
     using G = Marg<M>;
     using R = typename G::R;
-    constexpr int kNodes = 2 * R::kCore + R::kGraded + R::kTail;
-    static_assert(kNodes % kMargLanes == 0 && (2 * R::kCore) % kMargLanes == 0 && R::kGraded % kMargLanes == 0,
-                  "every row of nodes must lie in one region");
-    constexpr int kRows = kNodes / kMargLanes;
+    static_assert((2 * R::kCore) % kMargLanes == 0, "core rows must be whole");
+    constexpr int kCoreRows = 2 * R::kCore / kMargLanes;
+    constexpr int kBelow = R::kGraded + R::kTail, kBelowRows = (kBelow + kWave - 1) / kWave;
     __shared__ double red[1][kWavesPerBlock];
     const Statics &s = *a.st;
     const int it = blockIdx.y;
     const typename G::Th t = G::prep(a.theta + static_cast<int64_t>(it) * M::P);
     const int64_t il = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kMargLanes;
-    const int sub = threadIdx.x % kMargLanes;
+    const int sub = threadIdx.x % kMargLanes, lane = threadIdx.x % kWave;
     const bool valid = il < s.n;
     const typename G::Obj o = G::load(a.data, s.obj_start + (valid ? il : s.n - 1), a.cap);
     const MargGeo g = marg_geo<G>(o, t, s);
-    double hv[kRows], wv[kRows];
-    marg_rows<G>(o, t, s, g, a.rule, sub, hv, wv, std::make_integer_sequence<int, kRows>{});
-    double m = hv[0];
+    const typename G::Pre p = G::pre(o, t, s);
+    double m, sum;
+    {
+        double hv[kCoreRows], wv[kCoreRows];
+        core_rows<G>(o, p, t, g, a.rule, sub, hv, wv, std::make_integer_sequence<int, kCoreRows>{});
+        m = hv[0];
 #pragma unroll
-    for (int r = 1; r < kRows; ++r) m = fmax(m, hv[r]);
+        for (int r = 1; r < kCoreRows; ++r) m = fmax(m, hv[r]);
+        m = group_max(m);
+        sum = 0.0;
+        if (m > -HUGE_VAL) {
 #pragma unroll
-    for (int d = 1; d < kMargLanes; d <<= 1) m = fmax(m, __shfl_xor(m, d, kMargLanes));
-    double sum = 0.0;
-    if (m > -HUGE_VAL) {
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) sum += wv[r] * exp(hv[r] - m);
+            for (int r = 0; r < kCoreRows; ++r) sum += wv[r] * exp(hv[r] - m);
+        }
+        sum = group_sum(sum);
     }
+    if constexpr (kBelow > 0) {
+        const bool need = valid && sub == 0 && !(G::log_l_below(o, g.fa, s) < m + log(sum) + kSkipBelow);
+        uint64_t todo = __ballot(need);
+        const MargNode *rule = a.rule + 2 * R::kCore;
+        while (todo) {
+            const int src = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+            todo &= todo - 1;
+            typename G::Obj oj;
+            typename G::Pre pj;
+            MargGeo gj;
+            G::bcast(o, p, oj, pj, src);
+            gj.k = bcast(g.k, src);
+            gj.xa = bcast(g.xa, src);
+            gj.xt = bcast(g.xt, src);
+            gj.fa = bcast(g.fa, src);
+            gj.ft = bcast(g.ft, src);
+            double hb[kBelowRows], wb[kBelowRows];
 #pragma unroll
-    for (int d = 1; d < kMargLanes; d <<= 1) sum += __shfl_xor(sum, d, kMargLanes);
+            for (int r = 0; r < kBelowRows; ++r) {
+                const int q = r * kWave + lane;
+                hb[r] = below_node<G>(oj, pj, t, gj, rule[q < kBelow ? q : 0], q, wb[r]);
+            }
+            double mb = hb[0];
+#pragma unroll
+            for (int r = 1; r < kBelowRows; ++r) mb = fmax(mb, hb[r]);
+            mb = wave_max(mb);
+            double sb = 0.0;
+            if (mb > -HUGE_VAL) {
+#pragma unroll
+                for (int r = 0; r < kBelowRows; ++r) sb += wb[r] * exp(hb[r] - mb);
+            }
+            sb = wave_sum(sb);
+            if (lane / kMargLanes == src / kMargLanes && mb > -HUGE_VAL) {
+                const double mm = fmax(m, mb);
+                sum = (m > -HUGE_VAL ? sum * exp(m - mm) : 0.0) + sb * exp(mb - mm);
+                m = mm;
+            }
+        }
+    }
     const double term = (m > -HUGE_VAL) ? m + log(sum) : -HUGE_VAL;
     const bool writer = valid && sub == 0;
     if (writer && a.terms) a.terms[static_cast<int64_t>(it) * s.n + il] = term;
