@@ -303,10 +303,12 @@ def bench_serving(args, torch, synth, hbm):
     print(json.dumps(out), flush=True)
 
 
-# FP64 operations per node evaluation of the marginal kernel (an FMA counts
-# two), from the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters of the
-# marginal bench command divided by the node evaluations it made.
-FLOPS_PER_NODE = {"marginal_gamma_lf_1d": None, "marginal_bb1_lf": None, "marginal_normal_normal_1d": None}
+# FP64 operations per object integral of the marginal kernel (an FMA counts
+# two): 64 x (ADD + MUL + 2 FMA + TRANS) from the SQ_INSTS_VALU_*_F64
+# counters of the marginal bench command, per launch, divided by N x theta
+# rows (theta near the truth; the count depends on how many objects need the
+# region below the datum).
+FLOPS_PER_INTEGRAL = {"marginal_gamma_lf_1d": 9461, "marginal_bb1_lf": 59434, "marginal_normal_normal_1d": None}
 FP64_PEAK_TFLOPS = 78.6
 NODES_PER_OBJECT = {"marginal_gamma_lf_1d": 216, "marginal_bb1_lf": 216, "marginal_normal_normal_1d": 48}
 
@@ -375,8 +377,8 @@ def bench_marginal(args, torch, synth, hbm):
     _, kern_one_ms = hbm.read_kernel_timing(s.ctx)
     hbm.kernel_timing(s.ctx, False)
     nodes = NODES_PER_OBJECT[args.workload] * wl.n * args.thetas
-    fpn = FLOPS_PER_NODE[args.workload]
-    achieved = fpn * nodes / (kern_ms * 1e-3) / 1e12 if (fpn and kern_ms > 0) else None
+    fpi = FLOPS_PER_INTEGRAL[args.workload]
+    achieved = fpi * wl.n * args.thetas / (kern_ms * 1e-3) / 1e12 if (fpi and kern_ms > 0) else None
     out = {
         "metric": METRIC, "value": wl.n * args.thetas * args.steps / wall, "unit": "object integrals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
@@ -389,7 +391,8 @@ def bench_marginal(args, torch, synth, hbm):
                          "kernel_ms": kern_one_ms},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": None,
-                     "kernel": f"marginal_kernel<{wl.name}>", "flops_per_node": fpn, "node_evaluations": nodes,
+                     "kernel": f"marginal_kernel<{wl.name}>", "flops_per_object_integral": fpi,
+                     "nominal_node_evaluations": nodes,
                      "kernel_ms": kern_ms, "launches_timed": n_launch},
     }
     if not args.no_cpu_baseline:
