@@ -48,6 +48,8 @@ def lib(path: str = None):
         L.orc_gauss_legendre.argtypes = [i32, d, d, P, P]
         L.orc_new.argtypes = [i32, i64, P, P, u64, d, d, d, i32, i32]
         L.orc_new.restype = P
+        L.orc_set_theta_substeps.argtypes = [P, i32]
+        L.orc_set_theta_substeps.restype = None
         L.orc_free.argtypes = [P]
         L.orc_log_terms.argtypes = [P, i64, P, P, P, P]
         L.orc_log_prior.argtypes = [P, P]
@@ -151,7 +153,8 @@ class Oracle:
     """FP64 reference sampler for one dataset (a :class:`synth.workloads.Workload`)."""
 
     def __init__(self, wl, nq: int = 512, gamma: float = 2.0 / 3.0, alpha_star=None,
-                 alpha_star_theta: float = 0.4, adapt_theta: bool = True, seed=None, lib_path: str = None):
+                 alpha_star_theta: float = 0.4, adapt_theta: bool = True, seed=None, lib_path: str = None,
+                 theta_substeps: int = 1):
         self._L = lib(lib_path)
         self.wl = wl
         self.n, self.d, self.p = wl.n, wl.d, wl.p
@@ -163,6 +166,8 @@ class Oracle:
                                 self.alpha_star, gamma, alpha_star_theta, int(adapt_theta), nq)
         if not self._h:
             raise ValueError("oracle: unknown model")
+        self.theta_substeps = max(1, int(theta_substeps))
+        self._L.orc_set_theta_substeps(self._h, self.theta_substeps)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -261,7 +266,7 @@ class Oracle:
         info = np.zeros(6)
         self._L.orc_theta_step(self._h, kk, _ptr(st.theta), _ptr(st.chol_theta), _ptr(st.chi), _ptr(info))
         return {"delta": info[0], "ln_u": info[1], "accepted": bool(info[2]), "alpha": info[3],
-                "sum_prop": info[4], "sum_cur": info[5]}
+                "sum_prop": info[4], "sum_cur": info[5], "n_accepted": int(info[2])}
 
     def run(self, st: State, n_cycles: int, thin: int = 0, fix_theta: bool = False,
             fix_chi: bool = False, chi_trace: bool = False):

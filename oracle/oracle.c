@@ -28,6 +28,7 @@ struct orc_ctx {
     uint64_t seed;
     double alpha_star, gamma, alpha_star_theta;
     int adapt_theta;
+    int theta_substeps;      /* Metropolis steps on theta per cycle (>= 1) */
     /* selection normaliser: nodes in x = ln L, weights, efficiency per node */
     int nq;
     double *qx, *qw, *qeps;
@@ -448,6 +449,7 @@ orc_ctx *orc_new(int model, int64_t n, const double *data, const double *consts,
     c->gamma = gamma;
     c->alpha_star_theta = alpha_star_theta;
     c->adapt_theta = adapt_theta;
+    c->theta_substeps = 1;
     c->nq = (model == ORC_LF1D || model == ORC_LF3D || model == ORC_BB1) ? nq : 0;
     if (c->nq > 0) {
         c->qx = malloc(sizeof(double) * c->nq);
@@ -648,21 +650,21 @@ void orc_sweep(const orc_ctx *c, int64_t k, const double *theta,
 /* Theta step: Gaussian random walk with a RAM-adapted factor, accepted   */
 /* on  log pi(theta) + sum_i log f(chi_i; theta) - N log Z(theta).        */
 /* ===================================================================== */
-static void theta_normals(const orc_ctx *c, int64_t k, double *zv)
+/* Sub-step j (0-based) of cycle k draws its proposal normals from blocks
+ * (j, k, 1, b) and its accept uniform from block (j, k, 2, 0). */
+static void theta_normals(const orc_ctx *c, int64_t k, int j, double *zv)
 {
-    for (int j = 0; j < c->p; j++) {
+    for (int r = 0; r < c->p; r++) {
         double u[5], z[4];
-        uint32_t ctr[4] = {0u, (uint32_t)k, 1u, (uint32_t)(j / 4)};
+        uint32_t ctr[4] = {(uint32_t)j, (uint32_t)k, 1u, (uint32_t)(r / 4)};
         orc_variates(c->seed, ctr, u, z);
-        zv[j] = z[j % 4];
+        zv[r] = z[r % 4];
     }
 }
 
-void orc_theta_proposal(const orc_ctx *c, int64_t k, const double *theta,
-                        const double *chol_theta, double *theta_prop)
+static void proposal_from(const orc_ctx *c, const double *zv, const double *theta, const double *chol_theta,
+                          double *theta_prop)
 {
-    double zv[8];
-    theta_normals(c, k, zv);
     for (int r = 0; r < c->p; r++) {
         theta_prop[r] = theta[r];
         for (int s = 0; s <= r; s++)
@@ -670,13 +672,29 @@ void orc_theta_proposal(const orc_ctx *c, int64_t k, const double *theta,
     }
 }
 
-int orc_theta_step(const orc_ctx *c, int64_t k, double *theta, double *chol_theta,
-                   const double *chi, double *info)
+void orc_theta_proposal(const orc_ctx *c, int64_t k, const double *theta,
+                        const double *chol_theta, double *theta_prop)
+{
+    double zv[8];
+    theta_normals(c, k, 0, zv);
+    proposal_from(c, zv, theta, chol_theta, theta_prop);
+}
+
+void orc_set_theta_substeps(orc_ctx *c, int substeps)
+{
+    c->theta_substeps = substeps > 1 ? substeps : 1;
+}
+
+/* One Metropolis step on theta given chi: sub-step j of cycle k.  The RAM
+ * factor adapts with eta_n, n counting theta steps: n = (k - 1) K + j + 1
+ * for K steps per cycle (n = k when K = 1, the latent sweeps' count). */
+static int theta_substep(const orc_ctx *c, int64_t k, int j, double *theta, double *chol_theta,
+                         const double *chi, double *info)
 {
     const int p = c->p;
     double zv[8], prop[8];
-    theta_normals(c, k, zv);
-    orc_theta_proposal(c, k, theta, chol_theta, prop);
+    theta_normals(c, k, j, zv);
+    proposal_from(c, zv, theta, chol_theta, prop);
     double lprior_prop = orc_log_prior(c, prop);
     double sum_prop = NAN, sum_cur = NAN, delta = -INFINITY;
     if (isfinite(lprior_prop)) {
@@ -690,14 +708,16 @@ int orc_theta_step(const orc_ctx *c, int64_t k, double *theta, double *chol_thet
     }
     double alpha = delta >= 0.0 ? 1.0 : exp(delta);
     double u[5], z[4];
-    uint32_t ctr[4] = {0u, (uint32_t)k, 2u, 0u};
+    uint32_t ctr[4] = {(uint32_t)j, (uint32_t)k, 2u, 0u};
     orc_variates(c->seed, ctr, u, z);
     double ln_u = log(u[4]);
     int accepted = ln_u < delta;
     if (accepted)
         memcpy(theta, prop, sizeof(double) * p);
-    if (c->adapt_theta)
-        ram_adapt(p, chol_theta, zv, eta_of(c, k) * (alpha - c->alpha_star_theta));
+    if (c->adapt_theta) {
+        int64_t n = (k - 1) * (int64_t)c->theta_substeps + j + 1;
+        ram_adapt(p, chol_theta, zv, pow((double)(n + 1), -c->gamma) * (alpha - c->alpha_star_theta));
+    }
     if (info) {
         info[0] = delta;
         info[1] = ln_u;
@@ -707,6 +727,17 @@ int orc_theta_step(const orc_ctx *c, int64_t k, double *theta, double *chol_thet
         info[5] = sum_cur;
     }
     return accepted;
+}
+
+int orc_theta_step(const orc_ctx *c, int64_t k, double *theta, double *chol_theta,
+                   const double *chi, double *info)
+{
+    int n_acc = 0;
+    for (int j = 0; j < c->theta_substeps; j++)
+        n_acc += theta_substep(c, k, j, theta, chol_theta, chi, info);
+    if (info)
+        info[2] = n_acc;
+    return n_acc;
 }
 
 void orc_run(const orc_ctx *c, int64_t k0, int64_t n_cycles, double *theta, double *chol_theta,

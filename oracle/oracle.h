@@ -88,11 +88,16 @@ void orc_sweep(const orc_ctx *c, int64_t k, const double *theta,
 /* Proposal of the theta step of cycle k: theta' = theta + S_theta z. */
 void orc_theta_proposal(const orc_ctx *c, int64_t k, const double *theta,
                         const double *chol_theta, double *theta_prop);
-/* Theta step of cycle k at latent state chi.  Updates theta and chol_theta
- * (p x p lower, row-major).  info (nullable) [6]: delta, ln_u, accepted,
- * alpha, sum lf(theta'), sum lf(theta).  Returns accepted. */
+/* Theta step of cycle k at latent state chi: K Metropolis steps on theta
+ * given chi (K = 1 unless set below), each from the full N-term sums.
+ * Updates theta and chol_theta (p x p lower, row-major).  info (nullable)
+ * [6]: delta, ln_u, accepted, alpha, sum lf(theta'), sum lf(theta) of the
+ * last step, with info[2] the number of steps accepted.  Returns that number. */
 int orc_theta_step(const orc_ctx *c, int64_t k, double *theta, double *chol_theta,
                    const double *chi, double *info);
+
+/* Metropolis steps on theta per cycle (values below 1 mean 1). */
+void orc_set_theta_substeps(orc_ctx *c, int substeps);
 
 /* n_cycles MWG cycles starting after sweep k0.
  * theta_trace [n_cycles][p] (nullable); chi_trace [n_cycles/thin][d][n]

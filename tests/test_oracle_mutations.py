@@ -242,6 +242,32 @@ def pin_marginal_bb1_slow_tail(path, rr):
     return abs(o.marginal_terms(th)[0] - (shift + math.log(v))) < 1e-9
 
 
+def pin_theta_substeps(path, rr):
+    wl = synth.gamma_lf_1d(n=60, seed=31, fth=389.75)
+    K, gamma = 2, 2.0 / 3.0
+    o = oracle.Oracle(wl, lib_path=path, theta_substeps=K)
+    st = o.initial_state()
+    o.run(st, 4)
+    k = st.k + 1
+    theta, low = st.theta.copy(), st.chol_theta.copy()
+    st.k = k
+    for j in range(K):
+        z = np.array([oracle.variates(o.seed, [j, k, 1, r // 4], lib_path=path)[1][r % 4] for r in range(o.p)])
+        prop = theta + low @ z
+        delta = -math.inf
+        if np.isfinite(o.log_prior(prop)):
+            delta = (o.log_prior(prop) + o.pop_sum(prop, st.chi) - o.n * o.log_Z(prop)) - \
+                    (o.log_prior(theta) + o.pop_sum(theta, st.chi) - o.n * o.log_Z(theta))
+        ln_u = math.log(oracle.variates(o.seed, [j, k, 2, 0], lib_path=path)[0][4])
+        alpha = 1.0 if delta >= 0 else math.exp(delta)
+        if ln_u < delta:
+            theta = prop
+        c = ((k - 1) * K + j + 2) ** -gamma * (alpha - 0.4)
+        low = np.linalg.cholesky(low @ (np.eye(o.p) + c * np.outer(z, z) / (z @ z)) @ low.T)
+    o.theta_step(st)
+    return np.allclose(st.theta, theta, rtol=0, atol=1e-12) and np.allclose(st.chol_theta, low, rtol=1e-10, atol=1e-13)
+
+
 MUTATIONS = [
     ("philox multiplier", "0xD2511F53u", "0xD2511F57u", pin_philox),
     ("philox key bump", "k1 += weyl1;", "k1 += weyl0;", pin_philox),
@@ -281,6 +307,10 @@ MUTATIONS = [
      "centre = y;", pin_marginal_nn1d),
     ("marginal tail panel dropped", "double total = gl_composite(c, i, theta, shift, centre - 200.0, lo, 0.25, t20, w20)",
      "double total = 0.0 * gl_composite(c, i, theta, shift, centre - 200.0, lo, 0.25, t20, w20)", pin_marginal_bb1),
+    ("theta sub-step normals reuse the first block", "uint32_t ctr[4] = {(uint32_t)j, (uint32_t)k, 1u, (uint32_t)(r / 4)};",
+     "uint32_t ctr[4] = {0u, (uint32_t)k, 1u, (uint32_t)(r / 4)};", pin_theta_substeps),
+    ("theta sub-step adaptation counts cycles", "int64_t n = (k - 1) * (int64_t)c->theta_substeps + j + 1;",
+     "int64_t n = k;", pin_theta_substeps),
     ("marginal power tail cut at 200 e-folds", "if (top < feature - 40.0 && !(add > 1e-17 * total))",
      "if (1)", pin_marginal_bb1_slow_tail),
 ]

@@ -162,3 +162,63 @@ def test_theta_factor_determinant_identity(oracle_lib):
         z = np.array([oracle_lib.variates(wl.seed, [0, st.k, 1, j // 4])[1][j % 4] for j in range(2)])
         tgt = before @ (np.eye(2) + c * np.outer(z, z) / z.dot(z)) @ before.T
         np.testing.assert_allclose(st.chol_theta, np.linalg.cholesky(tgt), rtol=1e-12, atol=1e-15)
+
+
+def test_theta_substeps_sample_theta_given_chi(oracle_lib):
+    """Several Metropolis steps on theta per cycle (each from the full N-term
+    sums) still sample theta | chi: the normal-normal closed form."""
+    wl = synth.normal_normal_1d(n=200, seed=0)
+    o = oracle_lib.Oracle(wl, theta_substeps=3)
+    st = o.initial_state()
+    chi = wl.truth["chi"]
+    st.chi[0] = chi
+    tt, _ = o.run(st, 25000, fix_chi=True)
+    keep = tt[2500:]
+    n, xbar, ss = chi.size, chi.mean(), np.sum((chi - chi.mean()) ** 2)
+    lt = np.linspace(-2.0, 2.0, 400001)
+    logp = -(n - 2) * lt - ss / (2 * np.exp(2 * lt))
+    p = np.exp(logp - logp.max())
+    p /= np.trapezoid(p, lt)
+    e_lt = np.trapezoid(lt * p, lt)
+    v_lt = np.trapezoid((lt - e_lt) ** 2 * p, lt)
+    e_tau2 = np.trapezoid(np.exp(2 * lt) * p, lt)
+    _check(keep[:, 0], xbar, e_tau2 / n, "mu")
+    _check(keep[:, 1], e_lt, v_lt, "ln tau")
+
+
+def _ram_factor(low, z, c):
+    # lower factor of S (I + c z z^T / |z|^2) S^T
+    m = low @ (np.eye(len(z)) + c * np.outer(z, z) / (z @ z)) @ low.T
+    return np.linalg.cholesky(m)
+
+
+def test_theta_substep_draws_and_adaptation(oracle_lib):
+    """Sub-step j of cycle k draws from Philox blocks (j, k, 1, b) and
+    (j, k, 2, 0) and adapts with eta_n, n = (k - 1) K + j + 1."""
+    wl = synth.gamma_lf_1d(n=60, seed=31, fth=389.75)
+    K, gamma = 2, 2.0 / 3.0
+    o = oracle_lib.Oracle(wl, theta_substeps=K)
+    st = o.initial_state()
+    o.run(st, 4)
+    k = st.k + 1
+    theta, low = st.theta.copy(), st.chol_theta.copy()
+    st.k = k
+    n_acc = 0
+    for j in range(K):
+        z = np.array([oracle_lib.variates(o.seed, [j, k, 1, r // 4])[1][r % 4] for r in range(o.p)])
+        prop = theta + low @ z
+        lp = o.log_prior(prop)
+        delta = -math.inf
+        if np.isfinite(lp):
+            delta = (lp + o.pop_sum(prop, st.chi) - o.n * o.log_Z(prop)) - \
+                    (o.log_prior(theta) + o.pop_sum(theta, st.chi) - o.n * o.log_Z(theta))
+        ln_u = math.log(oracle_lib.variates(o.seed, [j, k, 2, 0])[0][4])
+        alpha = 1.0 if delta >= 0 else math.exp(delta)
+        if ln_u < delta:
+            theta, n_acc = prop, n_acc + 1
+        eta = ((k - 1) * K + j + 2) ** -gamma
+        low = _ram_factor(low, z, eta * (alpha - 0.4))
+    info = o.theta_step(st)
+    assert info["n_accepted"] == n_acc
+    assert np.allclose(st.theta, theta, rtol=0, atol=1e-12)
+    assert np.allclose(st.chol_theta, low, rtol=1e-10, atol=1e-13)
