@@ -128,6 +128,14 @@ typedef struct hbm_config {
     int32_t thin_chi;            /* latent snapshot after every sweep k with k % thin_chi == 0; 0: none */
     int32_t tiles_per_group;     /* launch shape: 256-object tiles per sweep workgroup, 1, 2 or 4 (0 = 1);
                                     init_chains / init_batch take it from (the first) config */
+    int32_t theta_substeps;      /* 0: one theta step per cycle from the N-term sums of the proposal
+                                    (any model); K in 1..64: K Metropolis steps on theta per cycle
+                                    from the sweep's sufficient statistics (exponential-family
+                                    populations: both normal-normal and both gamma-LF models), sub-step
+                                    j of cycle k drawing Philox blocks (j, k, 1, b) and (j, k, 2, 0);
+                                    K = 1 makes the same chain as 0 up to rounding of the log ratio.
+                                    Every dataset of a context uses 0, or every one K >= 1. */
+    int32_t reserved;            /* must be 0 */
     int64_t max_cycles;          /* capacity of the theta trace (and bound on snapshots) */
     double theta_chol0[25];      /* initial theta proposal factor, p x p lower, row-major */
     double model_consts[16];
@@ -150,7 +158,8 @@ typedef struct hbm_pool_config {
     int64_t max_cycles;          /* theta trace rows per slot */
     int64_t snap_rows;           /* rows of chi_samples (0 when NULL) */
     int32_t tiles_per_group;     /* launch shape: tiles per sweep workgroup, 1, 2 or 4 (0 = 1) */
-    int32_t reserved;            /* must be 0 */
+    int32_t stats_theta;         /* 1: every dataset takes its theta steps from sufficient statistics
+                                    (its theta_substeps >= 1); 0: from the N-term sums (theta_substeps 0) */
 } hbm_pool_config;
 
 /* Create a sampler (Sec. 2.2: "X_1 with pi(X_1) > 0, S_1 = I").

@@ -263,10 +263,11 @@ class Oracle:
     def theta_step(self, st: State, k=None):
         """Theta step of cycle k (default: the sweep just done).  Returns info dict."""
         kk = st.k if k is None else k
-        info = np.zeros(6)
+        info = np.zeros(6 + 2 * self.p)
         self._L.orc_theta_step(self._h, kk, _ptr(st.theta), _ptr(st.chol_theta), _ptr(st.chi), _ptr(info))
         return {"delta": info[0], "ln_u": info[1], "accepted": bool(info[2]), "alpha": info[3],
-                "sum_prop": info[4], "sum_cur": info[5], "n_accepted": int(info[2])}
+                "sum_prop": info[4], "sum_cur": info[5], "n_accepted": int(info[2]),
+                "prop_last": info[6:6 + self.p].copy(), "theta_before_last": info[6 + self.p:6 + 2 * self.p].copy()}
 
     def run(self, st: State, n_cycles: int, thin: int = 0, fix_theta: bool = False,
             fix_chi: bool = False, chi_trace: bool = False):

@@ -725,6 +725,7 @@ static int theta_substep(const orc_ctx *c, int64_t k, int j, double *theta, doub
         info[3] = alpha;
         info[4] = sum_prop;
         info[5] = sum_cur;
+        memcpy(info + 6, prop, sizeof(double) * p);
     }
     return accepted;
 }
@@ -733,8 +734,11 @@ int orc_theta_step(const orc_ctx *c, int64_t k, double *theta, double *chol_thet
                    const double *chi, double *info)
 {
     int n_acc = 0;
-    for (int j = 0; j < c->theta_substeps; j++)
+    for (int j = 0; j < c->theta_substeps; j++) {
+        if (info)
+            memcpy(info + 6 + c->p, theta, sizeof(double) * c->p);
         n_acc += theta_substep(c, k, j, theta, chol_theta, chi, info);
+    }
     if (info)
         info[2] = n_acc;
     return n_acc;

@@ -91,8 +91,9 @@ void orc_theta_proposal(const orc_ctx *c, int64_t k, const double *theta,
 /* Theta step of cycle k at latent state chi: K Metropolis steps on theta
  * given chi (K = 1 unless set below), each from the full N-term sums.
  * Updates theta and chol_theta (p x p lower, row-major).  info (nullable)
- * [6]: delta, ln_u, accepted, alpha, sum lf(theta'), sum lf(theta) of the
- * last step, with info[2] the number of steps accepted.  Returns that number. */
+ * [6 + 2p]: delta, ln_u, accepted, alpha, sum lf(theta'), sum lf(theta) of
+ * the last step, with info[2] the number of steps accepted, then that
+ * step's proposal and the theta it started from.  Returns the number. */
 int orc_theta_step(const orc_ctx *c, int64_t k, double *theta, double *chol_theta,
                    const double *chi, double *info);
 

@@ -53,7 +53,7 @@ class Config(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("target_accept", ctypes.c_double), ("eta_exponent", ctypes.c_double),
         ("s0", ctypes.c_double), ("theta_target_accept", ctypes.c_double), ("adapt_theta", ctypes.c_int32),
         ("n_quad", ctypes.c_int32), ("thin_chi", ctypes.c_int32), ("tiles_per_group", ctypes.c_int32),
-        ("max_cycles", ctypes.c_int64), ("theta_chol0", ctypes.c_double * 25), ("model_consts", ctypes.c_double * 16),
+        ("theta_substeps", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_cycles", ctypes.c_int64), ("theta_chol0", ctypes.c_double * 25), ("model_consts", ctypes.c_double * 16),
     ]
 
 
@@ -65,7 +65,7 @@ class Buffers(ctypes.Structure):
 class PoolConfig(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_slots", ctypes.c_int32),
                 ("n_quad", ctypes.c_int32), ("capacity", ctypes.c_int64), ("max_cycles", ctypes.c_int64),
-                ("snap_rows", ctypes.c_int64), ("tiles_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("snap_rows", ctypes.c_int64), ("tiles_per_group", ctypes.c_int32), ("stats_theta", ctypes.c_int32)]
 
 
 _lib = None
@@ -302,8 +302,11 @@ def destroy_chains(ctx):
 # -- convenience wrappers ------------------------------------------------------
 
 def make_config(wl, max_cycles: int = 10000, thin: int = 0, s0: float = 1.0, adapt_theta: bool = True,
-                n_quad: int = 512, gamma: float = 2.0 / 3.0, alpha_star_theta: float = 0.4, seed=None) -> Config:
-    """The hbm_config of a :mod:`synth` workload."""
+                n_quad: int = 512, gamma: float = 2.0 / 3.0, alpha_star_theta: float = 0.4, seed=None,
+                theta_substeps: int = 0) -> Config:
+    """The hbm_config of a :mod:`synth` workload.  theta_substeps: 0 for one
+    theta step per cycle from the N-term sums, K >= 1 for K steps per cycle
+    from sufficient statistics."""
     d, p, m, prec = _MODEL_DIMS[wl.model]
     cfg = Config()
     cfg.model, cfg.precision, cfg.n_objects = wl.model, prec, wl.n
@@ -311,6 +314,7 @@ def make_config(wl, max_cycles: int = 10000, thin: int = 0, s0: float = 1.0, ada
     cfg.target_accept, cfg.eta_exponent, cfg.s0 = wl.alpha_star, gamma, s0
     cfg.theta_target_accept, cfg.adapt_theta = alpha_star_theta, int(adapt_theta)
     cfg.n_quad, cfg.thin_chi, cfg.max_cycles = n_quad, thin, max_cycles
+    cfg.theta_substeps = int(theta_substeps)
     ch0 = np.asarray(wl.theta_chol0, dtype=np.float64)
     for r in range(p):
         for q in range(p):
@@ -380,12 +384,14 @@ class Sampler(_Chains):
 
     def __init__(self, wl, device: str = "cuda:0", max_cycles: int = 10000, thin: int = 0, s0: float = 1.0,
                  adapt_theta: bool = True, n_quad: int = 512, gamma: float = 2.0 / 3.0,
-                 alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None, seed=None):
+                 alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None, seed=None,
+                 theta_substeps: int = 0):
         self.wl, self.n = wl, wl.n
         self._alloc(wl.model, wl.n, max_cycles // thin if thin > 0 else 0, device, stream)
         with torch.no_grad():
             self.data.copy_(torch.as_tensor(np.ascontiguousarray(wl.data), dtype=self.dtype))
-        self.config = make_config(wl, max_cycles, thin, s0, adapt_theta, n_quad, gamma, alpha_star_theta, seed)
+        self.config = make_config(wl, max_cycles, thin, s0, adapt_theta, n_quad, gamma, alpha_star_theta, seed,
+                                  theta_substeps)
         torch.cuda.synchronize(self.device)
         with torch.cuda.device(self.device):
             self.ctx = init_chains(self.config, self.buffers, wl.chi0, wl.theta0, self.stream.cuda_stream)
@@ -395,8 +401,9 @@ class Sampler(_Chains):
         r = ram_sweep(self.ctx, n, rate)
         return float(r[0]) if rate else None
 
-    def theta_step(self) -> bool:
-        return bool(theta_step(self.ctx)[0] == 1)
+    def theta_step(self) -> int:
+        """Steps accepted (0 or 1; up to K with K theta sub-steps)."""
+        return int(theta_step(self.ctx)[0])
 
     def pop_loglik(self, theta) -> float:
         return float(pop_loglik(self.ctx, np.asarray(theta, dtype=np.float64).reshape(1, -1))[0])
@@ -461,7 +468,7 @@ class Batch(_Chains):
 
     def __init__(self, wls, device: str = "cuda:0", max_cycles: int = 10000, s0: float = 1.0,
                  adapt_theta: bool = True, n_quad: int = 512, gamma: float = 2.0 / 3.0,
-                 alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None):
+                 alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None, theta_substeps: int = 0):
         self.wls = list(wls)
         ns = [w.n for w in self.wls]
         self.offsets, cap = packed_offsets(ns)
@@ -475,8 +482,8 @@ class Batch(_Chains):
         with torch.no_grad():
             self.data.copy_(torch.as_tensor(data))
             self.chi.copy_(torch.as_tensor(chi))
-        self.configs = [make_config(w, max_cycles, 0, s0, adapt_theta, n_quad, gamma, alpha_star_theta)
-                        for w in self.wls]
+        self.configs = [make_config(w, max_cycles, 0, s0, adapt_theta, n_quad, gamma, alpha_star_theta,
+                                    theta_substeps=theta_substeps) for w in self.wls]
         theta0 = np.array([w.theta0 for w in self.wls], dtype=np.float64)
         torch.cuda.synchronize(self.device)
         with torch.cuda.device(self.device):
@@ -525,12 +532,13 @@ class Pool(_Chains):
     """
 
     def __init__(self, model: int, capacity: int, n_slots: int, max_cycles: int, device: str = "cuda:0",
-                 n_quad: int = 512, stream: Optional[torch.cuda.Stream] = None):
+                 n_quad: int = 512, stream: Optional[torch.cuda.Stream] = None, stats_theta: bool = False):
         cap = -(-int(capacity) // TILE) * TILE
         self._alloc(model, cap, 0, device, stream)
         pc = PoolConfig()
         pc.model, pc.precision, pc.n_slots = model, _MODEL_DIMS[model][3], n_slots
         pc.n_quad, pc.capacity, pc.max_cycles, pc.snap_rows = n_quad, cap, max_cycles, 0
+        pc.stats_theta = int(stats_theta)
         self.pool_config, self.n_slots, self.max_cycles = pc, n_slots, max_cycles
         self.free_slots = list(range(n_slots - 1, -1, -1))
         self.alloc = TileAllocator(cap // TILE)                     # slot owning each tile

@@ -13,6 +13,7 @@ constexpr int kBlock = 256;                 // objects per workgroup = one reduc
 constexpr int kWave = 64;                   // CDNA wavefront width
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxP = 8;                    // largest theta dimension supported
+constexpr int kMaxStats = 6;                // most sufficient statistics of a model
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each round multiplies
@@ -267,6 +268,7 @@ struct CycleState {
     double poplik_logz;
     double zc_prop[4];             // FP64 constants of the pending proposal for the quadrature
     double sum_dlf_raw;            // per-object part of sum_dlf as reduced from the tiles
+    double stats[kMaxStats];       // sufficient statistics of the last sweep, at the theta it ran with
     int64_t k;                     // sweeps done
     int64_t n_theta;               // theta steps done (= trace rows written)
     int64_t budget;                // theta steps after which the dataset stops (0: no limit)
@@ -296,6 +298,8 @@ struct Statics {
     int32_t nq;
     int32_t adapt_theta;
     int32_t p;
+    int32_t substeps;              // theta steps per cycle from sufficient statistics (0: generic sums)
+    int32_t pad_;
     uint32_t key0, key1;
     double gamma;                  // eta exponent
     double alpha_star, alpha_star_theta;

@@ -68,10 +68,11 @@ struct CtxImpl {
     int32_t n_slots = 0;
     int32_t nq = 1;
     int32_t tpw = 1;                // tiles per sweep workgroup (1, 2 or 4)
+    bool stats_mode = false;        // theta steps from sufficient statistics
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
     void *dd = nullptr;             // [md][cap] derived per-object data
-    double *partials = nullptr;     // [3][n_tiles]
+    double *partials = nullptr;     // [2 + kMaxStats][n_tiles]: tile sums, then accepted counts
     double *pout = nullptr;         // [n_slots][2] results of pop_loglik
     double *theta_in = nullptr;     // [n_slots][p] arguments of pop_loglik
     Precomp *side = nullptr;        // [n_slots] values the side workgroups leave for the epilogue
@@ -205,36 +206,48 @@ struct Ops {
             c->ev_pending.push_back(e0);
             c->ev_pending.push_back(e1);
         }
+        if constexpr (M::NS > 0) {
+            if (c->stats_mode) return sweep_as<true>(c, full, trace, grid, tpw, a, e0, e1);
+        }
+        return sweep_as<false>(c, full, trace, grid, tpw, a, e0, e1);
+    }
+
+    template <bool kStats>
+    static hbm_status sweep_as(CtxImpl *c, bool full, void *trace, dim3 grid, int tpw, const SweepArgs<T> &a,
+                               hipEvent_t e0, hipEvent_t e1)
+    {
         const bool one = single(c);
-        if (trace) launch_sweep<true, 1, false>(c, grid, a, e0, e1);
-        else if (one && tpw == 4) launch_sweep<false, 4, true>(c, grid, a, e0, e1);
-        else if (one && tpw == 2) launch_sweep<false, 2, true>(c, grid, a, e0, e1);
-        else if (one) launch_sweep<false, 1, true>(c, grid, a, e0, e1);
-        else if (tpw == 4) launch_sweep<false, 4, false>(c, grid, a, e0, e1);
-        else if (tpw == 2) launch_sweep<false, 2, false>(c, grid, a, e0, e1);
-        else launch_sweep<false, 1, false>(c, grid, a, e0, e1);
+        if (trace) launch_sweep<true, 1, false, kStats>(c, grid, a, e0, e1);
+        else if (one && tpw == 4) launch_sweep<false, 4, true, kStats>(c, grid, a, e0, e1);
+        else if (one && tpw == 2) launch_sweep<false, 2, true, kStats>(c, grid, a, e0, e1);
+        else if (one) launch_sweep<false, 1, true, kStats>(c, grid, a, e0, e1);
+        else if (tpw == 4) launch_sweep<false, 4, false, kStats>(c, grid, a, e0, e1);
+        else if (tpw == 2) launch_sweep<false, 2, false, kStats>(c, grid, a, e0, e1);
+        else launch_sweep<false, 1, false, kStats>(c, grid, a, e0, e1);
         LAUNCHCHK(c, "sweep_kernel");
         const EpiArgs e = epi_args(c);
         if (full && one)
-            hipLaunchKernelGGL((epilogue_kernel<M, true, true>), dim3(1), dim3(kBlock), 0, c->stream, e);
+            hipLaunchKernelGGL((epilogue_kernel<M, true, true, kStats>), dim3(1), dim3(kBlock), 0, c->stream, e);
         else if (full)
-            hipLaunchKernelGGL((epilogue_kernel<M, true, false>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, e);
+            hipLaunchKernelGGL((epilogue_kernel<M, true, false, kStats>), dim3(c->n_slots), dim3(kBlock), 0,
+                               c->stream, e);
         else if (one)
-            hipLaunchKernelGGL((epilogue_kernel<M, false, true>), dim3(1), dim3(kBlock), 0, c->stream, e);
+            hipLaunchKernelGGL((epilogue_kernel<M, false, true, kStats>), dim3(1), dim3(kBlock), 0, c->stream, e);
         else
-            hipLaunchKernelGGL((epilogue_kernel<M, false, false>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, e);
+            hipLaunchKernelGGL((epilogue_kernel<M, false, false, kStats>), dim3(c->n_slots), dim3(kBlock), 0,
+                               c->stream, e);
         LAUNCHCHK(c, "epilogue_kernel");
         return HBM_OK;
     }
 
-    template <bool kTrace, int TPW, bool kSingle>
+    template <bool kTrace, int TPW, bool kSingle, bool kStats>
     static void launch_sweep(CtxImpl *c, dim3 grid, const SweepArgs<T> &a, hipEvent_t e0, hipEvent_t e1)
     {
         if (e0)
-            hipExtLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle>), grid, dim3(kBlock), 0, c->stream, e0, e1,
-                                  0, a);
+            hipExtLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle, kStats>), grid, dim3(kBlock), 0, c->stream,
+                                  e0, e1, 0, a);
         else
-            hipLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle>), grid, dim3(kBlock), 0, c->stream, a);
+            hipLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle, kStats>), grid, dim3(kBlock), 0, c->stream, a);
     }
 
     static EpiArgs epi_args(CtxImpl *c)
@@ -245,14 +258,25 @@ struct Ops {
         e.partials = c->partials;
         e.side = c->side;
         e.theta_trace = c->theta_trace;
+        e.qx = c->qx;
+        e.qw = c->qw;
+        e.qeps = c->qeps;
         e.trace_stride = c->pool.max_cycles;
         e.n_tiles_total = c->n_tiles;
+        e.nq = c->nq;
         return e;
     }
 
     static hbm_status theta(CtxImpl *c)
     {
-        hipLaunchKernelGGL((theta_kernel<M>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, epi_args(c));
+        bool launched = false;
+        if constexpr (M::NS > 0) {
+            if (c->stats_mode) {
+                hipLaunchKernelGGL((theta_kernel<M, true>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, epi_args(c));
+                launched = true;
+            }
+        }
+        if (!launched) hipLaunchKernelGGL((theta_kernel<M>), dim3(c->n_slots), dim3(kBlock), 0, c->stream, epi_args(c));
         LAUNCHCHK(c, "theta_kernel");
         return HBM_OK;
     }
@@ -374,16 +398,17 @@ struct Ops {
 struct ModelInfo {
     int d, p, m, md, precision;
     const Launch *ops;
+    int ns;                    // sufficient statistics (0: none)
 };
 
 bool model_info(int model, ModelInfo *mi)
 {
     switch (model) {
-    case HBM_NORMAL_NORMAL_1D: *mi = {NN1D::D, NN1D::P, NN1D::M, NN1D::MD, HBM_FP64, Ops<NN1D>::table()}; return true;
-    case HBM_GAMMA_LF_1D: *mi = {LF1D::D, LF1D::P, LF1D::M, LF1D::MD, HBM_FP32, Ops<LF1D>::table()}; return true;
-    case HBM_GAMMA_LF_COLOR_3D: *mi = {LF3D::D, LF3D::P, LF3D::M, LF3D::MD, HBM_FP32, Ops<LF3D>::table()}; return true;
-    case HBM_NORMAL_NORMAL_3D: *mi = {NN3D::D, NN3D::P, NN3D::M, NN3D::MD, HBM_FP64, Ops<NN3D>::table()}; return true;
-    case HBM_BB1_LF: *mi = {BB1::D, BB1::P, BB1::M, BB1::MD, HBM_FP32, Ops<BB1>::table()}; return true;
+    case HBM_NORMAL_NORMAL_1D: *mi = {NN1D::D, NN1D::P, NN1D::M, NN1D::MD, HBM_FP64, Ops<NN1D>::table(), NN1D::NS}; return true;
+    case HBM_GAMMA_LF_1D: *mi = {LF1D::D, LF1D::P, LF1D::M, LF1D::MD, HBM_FP32, Ops<LF1D>::table(), LF1D::NS}; return true;
+    case HBM_GAMMA_LF_COLOR_3D: *mi = {LF3D::D, LF3D::P, LF3D::M, LF3D::MD, HBM_FP32, Ops<LF3D>::table(), LF3D::NS}; return true;
+    case HBM_NORMAL_NORMAL_3D: *mi = {NN3D::D, NN3D::P, NN3D::M, NN3D::MD, HBM_FP64, Ops<NN3D>::table(), NN3D::NS}; return true;
+    case HBM_BB1_LF: *mi = {BB1::D, BB1::P, BB1::M, BB1::MD, HBM_FP32, Ops<BB1>::table(), BB1::NS}; return true;
     default: return false;
     }
 }
@@ -473,7 +498,10 @@ void release(CtxImpl *c)
 }
 
 // Checks one dataset's configuration (everything but its placement).
-hbm_status validate_dataset(CtxImpl *c, const hbm_config *cfg, const double *theta0, const ModelInfo &mi)
+// stats_mode: whether the context takes its theta steps from sufficient
+// statistics (c may be null: the check then runs before the context exists).
+hbm_status validate_dataset(CtxImpl *c, const hbm_config *cfg, const double *theta0, const ModelInfo &mi,
+                            bool stats_mode)
 {
     if (!cfg || !theta0) return fail(c, HBM_EINVAL, "config and theta0 must be non-NULL");
     if (cfg->precision != mi.precision)
@@ -487,6 +515,14 @@ hbm_status validate_dataset(CtxImpl *c, const hbm_config *cfg, const double *the
         return fail(c, HBM_EINVAL, "eta_exponent must lie in (1/2, 1]");
     if (!(cfg->s0 > 0.0) || !std::isfinite(cfg->s0)) return fail(c, HBM_EINVAL, "s0 must be positive");
     if (cfg->thin_chi < 0 || cfg->max_cycles < 0) return fail(c, HBM_EINVAL, "thin_chi and max_cycles must be >= 0");
+    if (cfg->reserved != 0) return fail(c, HBM_EINVAL, "reserved must be 0");
+    if (stats_mode ? (cfg->theta_substeps < 1 || cfg->theta_substeps > 64) : cfg->theta_substeps != 0)
+        return fail(c, HBM_EINVAL,
+                    stats_mode ? "theta_substeps must be in [1, 64] in a context whose theta steps use sufficient "
+                                 "statistics"
+                               : "theta_substeps must be 0 in a context whose theta steps use the N-term sums");
+    if (stats_mode && mi.ns == 0)
+        return fail(c, HBM_EINVAL, "this model has no sufficient statistics (theta steps need the N-term sums)");
     if (cfg->model == HBM_BB1_LF) {
         const double *mc = cfg->model_consts;
         if (!(mc[0] > 0.0) || !(mc[1] > 0.0) || !(mc[2] >= 0.0) || !std::isfinite(mc[3]) || !std::isfinite(mc[4]) ||
@@ -535,6 +571,9 @@ hbm_status validate_pool(const hbm_pool_config *pool, const hbm_buffers *b, Mode
         return fail(nullptr, HBM_EINVAL, "tiles_per_group must be 0 (default), 1, 2 or 4");
     if (pool->snap_rows > 0 && !b->chi_samples)
         return fail(nullptr, HBM_EINVAL, "snap_rows > 0 needs a chi_samples buffer");
+    if (pool->stats_theta != 0 && pool->stats_theta != 1) return fail(nullptr, HBM_EINVAL, "stats_theta must be 0 or 1");
+    if (pool->stats_theta && mi->ns == 0)
+        return fail(nullptr, HBM_EINVAL, "this model has no sufficient statistics (theta steps need the N-term sums)");
     return HBM_OK;
 }
 
@@ -600,6 +639,7 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
     c->n_slots = pool->n_slots;
     c->nq = has_selection(pool->model) ? pool->n_quad : 1;
     c->tpw = pool->tiles_per_group > 0 ? pool->tiles_per_group : 1;
+    c->stats_mode = pool->stats_theta != 0;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->ops = mi.ops;
     c->slots.assign(c->n_slots, Slot{});
@@ -622,7 +662,8 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
     };
     const size_t ns = static_cast<size_t>(c->n_slots), nq = static_cast<size_t>(c->nq);
     if ((s = alloc(&c->dd, c->esize * c->md * c->cap)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->partials), sizeof(double) * 3 * c->n_tiles)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->partials), sizeof(double) * (2 + kMaxStats) * c->n_tiles)) !=
+            HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->pout), sizeof(double) * 2 * ns)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->theta_in), sizeof(double) * c->p * ns)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->side), sizeof(Precomp) * ns)) != HBM_OK ||
@@ -674,7 +715,7 @@ hbm_status load(CtxImpl *c, int32_t count, const int32_t *slots, const int64_t *
         if (s != HBM_OK) return s;
         if (c->slots[j].loaded) return fail(c, HBM_EINVAL, who + "slot already holds a dataset");
         if (cfg->model != c->pool.model) return fail(c, HBM_EINVAL, who + "model differs from the pool's");
-        if ((s = validate_dataset(c, cfg, theta0 + static_cast<size_t>(q) * c->p, mi)) != HBM_OK) {
+        if ((s = validate_dataset(c, cfg, theta0 + static_cast<size_t>(q) * c->p, mi, c->stats_mode)) != HBM_OK) {
             c->err = who + c->err;
             return s;
         }
@@ -719,6 +760,7 @@ hbm_status load(CtxImpl *c, int32_t count, const int32_t *slots, const int64_t *
         s.nq = c->nq;
         s.adapt_theta = cfg->adapt_theta;
         s.p = c->p;
+        s.substeps = cfg->theta_substeps;
         s.key0 = static_cast<uint32_t>(cfg->seed & 0xffffffffu);
         s.key1 = static_cast<uint32_t>(cfg->seed >> 32);
         s.gamma = cfg->eta_exponent;
@@ -954,10 +996,11 @@ hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, con
     pool.max_cycles = config->max_cycles;
     pool.snap_rows = (config->thin_chi > 0 && buffers->chi_samples) ? config->max_cycles / config->thin_chi : 0;
     pool.tiles_per_group = config->tiles_per_group;
+    pool.stats_theta = config->theta_substeps > 0 ? 1 : 0;
     // dataset checks first, so a bad dataset reports its own reason
     ModelInfo mi;
     if (!model_info(config->model, &mi)) return fail(nullptr, HBM_EINVAL, "unknown model id");
-    hbm_status s = validate_dataset(nullptr, config, theta0, mi);
+    hbm_status s = validate_dataset(nullptr, config, theta0, mi, config->theta_substeps > 0);
     if (s != HBM_OK) return s;
     if (has_selection(config->model) && (config->n_quad < 16 || config->n_quad > 4096))
         return fail(nullptr, HBM_EINVAL, "n_quad must be in [16, 4096]");
@@ -1005,6 +1048,7 @@ hbm_status init_batch(int32_t n_datasets, const hbm_config *configs, const hbm_b
     pool.n_slots = n_datasets;
     pool.n_quad = configs[0].n_quad;
     pool.tiles_per_group = configs[0].tiles_per_group;
+    pool.stats_theta = configs[0].theta_substeps > 0 ? 1 : 0;
     int64_t o = 0;
     for (int32_t q = 0; q < n_datasets; ++q) {
         const hbm_config &cf = configs[q];

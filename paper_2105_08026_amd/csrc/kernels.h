@@ -133,13 +133,19 @@ __device__ void prepare_next(CycleState &c, const Statics &s, const Precomp &pc)
 // Turns the reduced sums of sweep c.k + 1 into the quantities its theta step
 // judges (lane 0): the proposal the sweep used, its ln Z, log prior and
 // aux scalars, and sum_i [log f(chi_i; theta') - log f(chi_i; theta)].
-template <class M>
+template <class M, bool kStats = false>
 __device__ void finish_sweep(CycleState &c, const Statics &s, const double *v, double zraw, const Precomp &pc)
 {
     c.k += 1;
     c.sum_lf = v[0];
-    c.sum_dlf_raw = v[1];
-    c.n_acc_last = v[2];
+    if constexpr (kStats) {
+        for (int j = 0; j < M::NS; ++j) c.stats[j] = v[1 + j];
+        c.sum_dlf_raw = 0.0;
+        c.n_acc_last = v[1 + M::NS];
+    } else {
+        c.sum_dlf_raw = v[1];
+        c.n_acc_last = v[2];
+    }
     for (int r = 0; r < M::P; ++r) {
         c.used_prop[r] = c.prop[r];
         c.used_z[r] = c.zprop[r];
@@ -155,8 +161,10 @@ __device__ void finish_sweep(CycleState &c, const Statics &s, const double *v, d
             c.logZ_used = zraw - M::logz_shift(c.aux_used);
             if (!(c.logZ_used > -HUGE_VAL && c.logZ_used < HUGE_VAL)) c.flags |= kFlagBadZ;
         }
-        c.sum_dlf = v[1] - static_cast<double>(s.n) * M::dlf_const(c.theta, c.used_prop, c.aux_cur, c.aux_used);
+        if constexpr (!kStats)
+            c.sum_dlf = v[1] - static_cast<double>(s.n) * M::dlf_const(c.theta, c.used_prop, c.aux_cur, c.aux_used);
     }
+    if constexpr (kStats) c.sum_dlf = 0.0;
     c.eta_used = c.eta_next;
     c.sums_ready = 1;
 }
@@ -202,6 +210,134 @@ __device__ void theta_mh(CycleState &c, const Statics &s, double *theta_trace, d
     if (c.budget > 0 && c.n_theta >= c.budget) c.active = 0;
 }
 
+template <class M>
+__device__ __forceinline__ double block_log_z(const double *zc, const double *qx, const double *qw,
+                                              const double *qeps, int nq, double (*red)[kWavesPerBlock]);
+
+// The theta step from the sweep's sufficient statistics: K = s.substeps
+// Metropolis steps on theta given chi, K >= 1, every thread of the
+// workgroup taking part (the selection normaliser of each later proposal is
+// a workgroup sum); lane 0 holds the chain.  Sub-step j of cycle k draws
+// its proposal normals from Philox blocks (j, k, 1, b) and its uniform from
+// (j, k, 2, 0); sub-step 0 judges the proposal the sweep was prepared with
+// (its ln Z comes from the sweep's side workgroup).  The change of
+// sum_i log f between any two theta follows from the statistics in O(1);
+// the theta RAM adapts with eta_n, n = (k - 1) K + j + 1.
+template <class M>
+__device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_trace, const Precomp &pc,
+                               const double *qx, const double *qw, const double *qeps, int nq,
+                               double (*red)[kWavesPerBlock])
+{
+    constexpr int P = M::P, NB = (P + 3) / 4;
+    __shared__ double sh_prop[kMaxP], sh_z[kMaxP];
+    __shared__ int32_t sh_valid;
+    double t0[kMaxP], a0[2];
+    for (int r = 0; r < P; ++r) t0[r] = c.theta[r];
+    a0[0] = c.aux_cur[0];
+    a0[1] = c.aux_cur[1];
+    const int K = s.substeps;
+    const double n = static_cast<double>(s.n);
+    double d_cur = 0.0;                 // sum log f(theta_j) - sum log f(theta_0)
+    int n_acc = 0;
+    double delta = -HUGE_VAL, alpha = 0.0;
+    for (int j = 0; j < K; ++j) {
+        if (threadIdx.x == 0) {
+            if (j == 0) {
+                for (int r = 0; r < P; ++r) {
+                    sh_prop[r] = c.used_prop[r];
+                    sh_z[r] = c.used_z[r];
+                }
+                sh_valid = c.used_valid;
+            } else {
+                for (int b = 0; b < NB; ++b) {
+                    const Block4 blk = philox(static_cast<uint32_t>(j), static_cast<uint32_t>(c.k), 1u,
+                                              static_cast<uint32_t>(b), s.key0, s.key1);
+                    double z4[4];
+                    normals<double, 4>(blk, z4);
+                    for (int q = 0; q < 4; ++q)
+                        if (4 * b + q < P) sh_z[4 * b + q] = z4[q];
+                }
+                for (int r = 0; r < P; ++r) {
+                    double v = c.theta[r];
+                    for (int q = 0; q <= r; ++q) v += c.chol_theta[r * P + q] * sh_z[q];
+                    sh_prop[r] = v;
+                }
+                sh_valid = M::in_support(sh_prop);
+            }
+        }
+        __syncthreads();
+        double zraw = 0.0;
+        if constexpr (M::kSelection) {
+            if (j > 0 && sh_valid) {
+                double zc[4];
+                M::z_consts(sh_prop, zc);
+                zraw = block_log_z<M>(zc, qx, qw, qeps, nq, red);
+            }
+        }
+        if (threadIdx.x == 0) {
+            double ap[2] = {0.0, 0.0}, lp = -HUGE_VAL, lz = 0.0, d_prop = 0.0;
+            delta = -HUGE_VAL;
+            if (sh_valid) {
+                if (j == 0) {
+                    ap[0] = c.aux_used[0];
+                    ap[1] = c.aux_used[1];
+                    lp = c.lprior_used;
+                    lz = c.logZ_used;
+                } else {
+                    M::aux(sh_prop, ap);
+                    lp = M::log_prior(sh_prop);
+                    if (M::kSelection) {
+                        lz = zraw - M::logz_shift(ap);
+                        if (!(lz > -HUGE_VAL && lz < HUGE_VAL)) c.flags |= kFlagBadZ;
+                    }
+                }
+                d_prop = M::stats_dlf(t0, sh_prop, a0, ap, c.stats, n, s);
+                delta = (d_prop - d_cur) - n * (lz - c.logZ_cur) + (lp - c.lprior_cur);
+                if (delta != delta) delta = -HUGE_VAL;
+            }
+            alpha = delta >= 0.0 ? 1.0 : exp(delta);
+            double ln_u = pc.ln_u;
+            if (j > 0) {
+                const Block4 ub = philox(static_cast<uint32_t>(j), static_cast<uint32_t>(c.k), 2u, 0u, s.key0, s.key1);
+                ln_u = log(uniform24<double>(ub, 4));
+            }
+            if (ln_u < delta) {
+                for (int r = 0; r < P; ++r) c.theta[r] = sh_prop[r];
+                c.logZ_cur = lz;
+                c.lprior_cur = lp;
+                c.aux_cur[0] = ap[0];
+                c.aux_cur[1] = ap[1];
+                d_cur = d_prop;
+                n_acc += 1;
+            }
+            if (s.adapt_theta) {
+                const double eta = pow(static_cast<double>((c.k - 1) * K + j + 2), -s.gamma);
+                double L[P * (P + 1) / 2], zz[P];
+                for (int r = 0, e = 0; r < P; ++r)
+                    for (int q = 0; q <= r; ++q, ++e) L[e] = c.chol_theta[r * P + q];
+                for (int r = 0; r < P; ++r) zz[r] = sh_z[r];
+                ram_adapt<double, P>(L, zz, eta * (alpha - s.alpha_star_theta));
+                for (int r = 0, e = 0; r < P; ++r)
+                    for (int q = 0; q <= r; ++q, ++e) c.chol_theta[r * P + q] = L[e];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c.n_theta < s.trace_cap) {
+            for (int r = 0; r < P; ++r) theta_trace[c.n_theta * P + r] = c.theta[r];
+            c.n_theta += 1;
+        } else {
+            c.flags |= kFlagTraceFull;
+        }
+        c.sums_ready = 0;
+        c.delta_last = delta;
+        c.alpha_last = alpha;
+        c.accepted_last = n_acc;
+        if (c.budget > 0 && c.n_theta >= c.budget) c.active = 0;
+    }
+}
+
 // ln of the selection quadrature sum_j w_j g(x_j; theta) eps_j over the fixed
 // ln L rule, where g is the luminosity PDF in x = ln L without its
 // normaliser (the model's zlog; the normaliser is applied by the caller
@@ -244,7 +380,7 @@ __device__ __forceinline__ TileView<typename M::T> tile_view(const SweepArgs<typ
 // object's state already loaded into registers; returns whether the move
 // was accepted.  i: position in the packed arrays; il: index within its
 // dataset (the random-number counter).
-template <class M, bool kTrace>
+template <class M, bool kTrace, bool kStats = false>
 __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, int ds, const TileView<typename M::T> &tv,
                                             int64_t il, int64_t i, typename M::T *x, typename M::T *S, uint32_t nacc,
                                             const typename M::Obj &o, double *v, bool valid = true)
@@ -282,7 +418,14 @@ __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, i
     const Eval<T> en = accept ? ey : ex;
     ram_adapt<T, D>(S, U, eta * (alpha - astar));
     v[0] = valid ? static_cast<double>(en.lf) : 0.0;
-    v[1] = valid ? static_cast<double>(M::dlf(o, x, en, kc, st)) : 0.0;
+    if constexpr (kStats) {
+        T sv[M::NS > 0 ? M::NS : 1];
+        M::stats(o, x, en, kc, st, sv);
+#pragma unroll
+        for (int j = 0; j < M::NS; ++j) v[1 + j] = valid ? static_cast<double>(sv[j]) : 0.0;
+    } else {
+        v[1] = valid ? static_cast<double>(M::dlf(o, x, en, kc, st)) : 0.0;
+    }
     if (!valid) return false;
 #pragma unroll
     for (int j = 0; j < D; ++j) a.chi[j * n + i] = x[j];
@@ -320,10 +463,13 @@ __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, i
 // kSingle: the context holds one dataset covering every position (object i
 // of the dataset at position i), so tiles need no table and no per-dataset
 // placement.
-template <class M, bool kTrace, int TPW, bool kSingle>
+// kStats: the tiles reduce the model's sufficient statistics at the new
+// state instead of the change of log f for the pending proposal.
+template <class M, bool kTrace, int TPW, bool kSingle, bool kStats = false>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> a)
 {
-    __shared__ double red[2 * TPW][kWavesPerBlock];
+    constexpr int kCols = kStats ? 1 + M::NS : 2;     // FP64 sums per tile besides the accepted count
+    __shared__ double red[kCols * TPW][kWavesPerBlock];
     __shared__ uint32_t nacc_w[TPW][kWavesPerBlock];
 
     const int n_side = kSingle ? 1 : a.n_ds;
@@ -408,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         dss[u] = ds;
         any = any || ds >= 0;
     }
-    double v[2 * TPW];
+    double v[kCols * TPW];
     bool accepted[TPW];
     if constexpr (kSingle) {
         // no exit between the loads and the arithmetic (the compiler would
@@ -417,21 +563,23 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
 #pragma unroll
         for (int u = 0; u < TPW; ++u) {
             const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
-            accepted[u] = step_object<M, kTrace>(a, 0, tv[u], i, i, xs[u], Ss[u], na[u], os[u], v + 2 * u,
-                                                 dss[u] >= 0 && i < a.n_total);
+            accepted[u] = step_object<M, kTrace, kStats>(a, 0, tv[u], i, i, xs[u], Ss[u], na[u], os[u],
+                                                         v + kCols * u, dss[u] >= 0 && i < a.n_total);
         }
     } else {
         if (!any) return;
 #pragma unroll
         for (int u = 0; u < TPW; ++u) {
-            v[2 * u] = v[2 * u + 1] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kCols; ++q) v[kCols * u + q] = 0.0;
             accepted[u] = false;
             const int ds = dss[u];
             if (ds < 0) continue;
             const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
             const int64_t il = i - tv[u].obj_start;
             if (il >= 0 && il < tv[u].n)
-                accepted[u] = step_object<M, kTrace>(a, ds, tv[u], il, i, xs[u], Ss[u], na[u], os[u], v + 2 * u);
+                accepted[u] = step_object<M, kTrace, kStats>(a, ds, tv[u], il, i, xs[u], Ss[u], na[u], os[u],
+                                                             v + kCols * u);
         }
     }
     if (!any) return;           // (kSingle) the dataset is off: nothing to publish
@@ -441,15 +589,15 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         const uint32_t nw = static_cast<uint32_t>(__popcll(__ballot(accepted[u])));
         if ((threadIdx.x & (kWave - 1)) == 0) nacc_w[u][threadIdx.x / kWave] = nw;
     }
-    block_sum<2 * TPW>(v, red);
+    block_sum<kCols * TPW>(v, red);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int u = 0; u < TPW; ++u) {
             if (dss[u] < 0) continue;
             const int g = g0 + u;
-            a.partials[g] = v[2 * u];
-            a.partials[a.n_tiles_total + g] = v[2 * u + 1];
-            a.partials[2 * a.n_tiles_total + g] =
+#pragma unroll
+            for (int q = 0; q < kCols; ++q) a.partials[q * a.n_tiles_total + g] = v[kCols * u + q];
+            a.partials[kCols * a.n_tiles_total + g] =
                 static_cast<double>((nacc_w[u][0] + nacc_w[u][1]) + (nacc_w[u][2] + nacc_w[u][3]));
         }
     }
@@ -461,19 +609,23 @@ struct EpiArgs {
     const double *partials;
     const Precomp *side;
     double *theta_trace;       // [n_ds][trace_stride][p]
+    const double *qx, *qw, *qeps;   // [n_ds][nq] selection tables (theta sub-steps)
     int64_t trace_stride;
     int32_t n_tiles_total;
+    int32_t nq;
 };
 
 // Epilogue of a sweep, one workgroup per dataset: fixed-order reduction of
 // the dataset's tile partials, bookkeeping, then (kFull) the theta step,
 // then the proposal for the next sweep.
-template <class M, bool kFull, bool kSingle>
+template <class M, bool kFull, bool kSingle, bool kStats = false>
 __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
 {
+    constexpr int NCOL = (kStats ? 1 + M::NS : 2) + 1;     // tile sums, then the accepted count
+    constexpr int G = NCOL > 3 ? 4 : 8;                     // tiles whose loads are issued together
     __shared__ CycleState c;
     __shared__ Precomp pc;
-    __shared__ double red[3][kWavesPerBlock];
+    __shared__ double red[NCOL][kWavesPerBlock];
     const int ds = kSingle ? 0 : static_cast<int>(blockIdx.x);
     const Statics &st = a.st[ds];
     const int32_t ntt = a.n_tiles_total;
@@ -483,23 +635,23 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
     // tile partials of this dataset, structure of arrays [3][n_tiles_total]:
     // lane t adds tiles t, t + 256, t + 512, ... in that order; the loads of
     // up to 8 such tiles are issued together before any is added
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int base = 0; base < nt; base += 8 * kBlock) {
-        double q[3][8];
+    double v[NCOL];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+    for (int col = 0; col < NCOL; ++col) v[col] = 0.0;
+    for (int base = 0; base < nt; base += G * kBlock) {
+        double q[NCOL][G];
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
             const int t = base + m * kBlock + threadIdx.x;
             const bool in = t < nt;
-            q[0][m] = in ? a.partials[t0 + t] : 0.0;
-            q[1][m] = in ? a.partials[ntt + t0 + t] : 0.0;
-            q[2][m] = in ? a.partials[2 * ntt + t0 + t] : 0.0;
+#pragma unroll
+            for (int col = 0; col < NCOL; ++col) q[col][m] = in ? a.partials[col * ntt + t0 + t] : 0.0;
         }
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < G; ++m) {
             if (base + m * kBlock + static_cast<int>(threadIdx.x) < nt) {
-                v[0] += q[0][m];
-                v[1] += q[1][m];
-                v[2] += q[2][m];
+#pragma unroll
+                for (int col = 0; col < NCOL; ++col) v[col] += q[col][m];
             }
         }
     }
@@ -510,8 +662,17 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
     }
     stage_in(c, a.cs + ds);              // its barrier also publishes pc
     if (!c.active) return;               // uniform: read from LDS after the barrier
-    block_sum<3>(v, red);
-    if (threadIdx.x == 0) {
+    block_sum<NCOL>(v, red);
+    if constexpr (kStats) {
+        if (threadIdx.x == 0) finish_sweep<M, true>(c, st, v, pc.zraw, pc);
+        if constexpr (kFull) {
+            __syncthreads();
+            const int64_t qo = static_cast<int64_t>(ds) * a.nq;
+            theta_substeps<M>(c, st, a.theta_trace + ds * a.trace_stride * M::P, pc, a.qx + qo, a.qw + qo,
+                              a.qeps + qo, a.nq, red);
+        }
+        if (threadIdx.x == 0) prepare_next<M>(c, st, pc);
+    } else if (threadIdx.x == 0) {
         finish_sweep<M>(c, st, v, pc.zraw, pc);
         if (kFull) theta_mh<M>(c, st, a.theta_trace + ds * a.trace_stride * M::P, pc.ln_u);
         prepare_next<M>(c, st, pc);
@@ -520,11 +681,12 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
 }
 
 // Theta step on its own, after a ram_sweep (plain cycle), one workgroup per dataset.
-template <class M>
+template <class M, bool kStats = false>
 __global__ __launch_bounds__(kBlock) void theta_kernel(EpiArgs a)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
+    __shared__ double red[1][kWavesPerBlock];
     const int ds = blockIdx.x;
     if (!a.cs[ds].active) return;
     {
@@ -533,8 +695,18 @@ __global__ __launch_bounds__(kBlock) void theta_kernel(EpiArgs a)
         for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
     }
     stage_in(c, a.cs + ds);
-    const bool ready = c.sums_ready != 0;
-    if (threadIdx.x == 0) {
+    const bool ready = c.sums_ready != 0;       // uniform: read from LDS after the barrier
+    if constexpr (kStats) {
+        if (ready) {
+            const int64_t qo = static_cast<int64_t>(ds) * a.nq;
+            theta_substeps<M>(c, a.st[ds], a.theta_trace + ds * a.trace_stride * M::P, pc, a.qx + qo, a.qw + qo,
+                              a.qeps + qo, a.nq, red);
+        }
+        if (threadIdx.x == 0) {
+            if (ready) prepare_next<M>(c, a.st[ds], pc);
+            else c.flags |= kFlagNoSums;
+        }
+    } else if (threadIdx.x == 0) {
         if (ready) {
             theta_mh<M>(c, a.st[ds], a.theta_trace + ds * a.trace_stride * M::P, pc.ln_u);
             prepare_next<M>(c, a.st[ds], pc);
@@ -542,6 +714,7 @@ __global__ __launch_bounds__(kBlock) void theta_kernel(EpiArgs a)
             c.flags |= kFlagNoSums;
         }
     }
+    (void)red;
     stage_out(a.cs + ds, c);
 }
 

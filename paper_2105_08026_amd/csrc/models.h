@@ -32,6 +32,10 @@
 //                       units, and the detection efficiency of a flux
 //   eval, dlf           per-object log densities and the per-object part of
 //                       the log f change, in the per-object precision
+//   NS, stats, stats_dlf (exponential-family models) NS per-object
+//                       sufficient statistics at the current theta theta0,
+//                       and sum_i log f(chi_i; tp) - sum_i log f(chi_i; theta0)
+//                       from their FP64 sums (NS = 0: no such statistics)
 #pragma once
 
 #include "device.h"
@@ -108,6 +112,21 @@ struct NN1D {
     {
         const T dv = (x[0] - kc[3]) * kc[4];
         return (-0.5 * dv * dv - kc[5]) - e.lf;
+    }
+    // d = chi - mu0: sum d, sum d^2; sum (chi - mu)^2 = S2 + 2 (mu0 - mu) S1 + N (mu0 - mu)^2
+    static constexpr int NS = 2;
+    __device__ static void stats(const Obj &, const T *x, const Eval<T> &, const T *kc, const Statics &, T *out)
+    {
+        const T d = x[0] - kc[0];
+        out[0] = d;
+        out[1] = d * d;
+    }
+    __device__ static double stats_dlf(const double *t0, const double *tp, const double *, const double *,
+                                       const double *sv, double n, const Statics &)
+    {
+        const double dm = t0[0] - tp[0];
+        const double ssp = sv[1] + 2.0 * dm * sv[0] + n * dm * dm;
+        return -0.5 * ssp * exp(-2.0 * tp[1]) + 0.5 * sv[1] * exp(-2.0 * t0[1]) - n * (tp[1] - t0[1]);
     }
 };
 
@@ -189,6 +208,23 @@ struct NN3D {
     {
         return (-0.5 * quad(s, x[0] - kc[3], x[1] - kc[4], x[2] - kc[5]) - s.md[6]) - e.lf;
     }
+    // d = chi - mu0 (3 sums); with delta = mu0 - mu the change of sum log f is
+    // -delta^T C^-1 sum d - N delta^T C^-1 delta / 2
+    static constexpr int NS = 3;
+    __device__ static void stats(const Obj &, const T *x, const Eval<T> &, const T *kc, const Statics &, T *out)
+    {
+        for (int j = 0; j < 3; ++j) out[j] = x[j] - kc[j];
+    }
+    __device__ static double stats_dlf(const double *t0, const double *tp, const double *, const double *,
+                                       const double *sv, double n, const Statics &s)
+    {
+        const double d0 = t0[0] - tp[0], d1 = t0[1] - tp[1], d2 = t0[2] - tp[2];
+        const double *w = s.md;
+        const double g0 = w[0] * d0 + w[1] * d1 + w[3] * d2;      // C^-1 delta
+        const double g1 = w[1] * d0 + w[2] * d1 + w[4] * d2;
+        const double g2 = w[3] * d0 + w[4] * d1 + w[5] * d2;
+        return -(g0 * sv[0] + g1 * sv[1] + g2 * sv[2]) - 0.5 * n * (g0 * d0 + g1 * d1 + g2 * d2);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -220,6 +256,17 @@ __device__ __forceinline__ double gamma_dconst(const double *th, const double *t
 }
 
 __device__ __forceinline__ bool lf_beta_ok(double beta) { return beta > -1.0 && beta < 0.0; }
+
+// Change of sum_i log f of the gamma law from theta0 to tp, from the sums
+// Sq = sum (chi - ln L*0) and Se = sum e^(chi - ln L*0) (lnGamma in a0, ap):
+// (beta' - beta0) Sq + (beta' + 1) N (ln L*0 - ln L*') - expm1(ln L*0 - ln L*') Se
+// - N (lnGamma(beta' + 1) - lnGamma(beta0 + 1)).
+__device__ __forceinline__ double gamma_stats_dlf(const double *t0, const double *tp, const double *a0,
+                                                  const double *ap, double sq, double se, double n)
+{
+    const double dl = t0[1] - tp[1];
+    return (tp[0] - t0[0]) * sq + (tp[0] + 1.0) * n * dl - expm1(dl) * se - n * (ap[0] - a0[0]);
+}
 
 // ===========================================================================
 // Gamma luminosity function, flux-limited, known distances; chi = ln L.
@@ -303,6 +350,18 @@ struct LF1D {
     __device__ static T dlf(const Obj &, const T *, const Eval<T> &e, const T *kc, const Statics &)
     {
         return kc[4] * e.q - e.eq * kc[5];
+    }
+    // q = chi - ln L*0 and e^q, as the density evaluation has them
+    static constexpr int NS = 2;
+    __device__ static void stats(const Obj &, const T *, const Eval<T> &e, const T *, const Statics &, T *out)
+    {
+        out[0] = e.q;
+        out[1] = e.eq;
+    }
+    __device__ static double stats_dlf(const double *t0, const double *tp, const double *a0, const double *ap,
+                                       const double *sv, double n, const Statics &)
+    {
+        return gamma_stats_dlf(t0, tp, a0, ap, sv[0], sv[1], n);
     }
 };
 
@@ -411,6 +470,30 @@ struct LF3D {
         const float dg = kc[4] * e.q - e.eq * kc[5];
         const float du = e.res * kc[13] - (kc[11] + kc[12] * x[0]) * kc[14];
         return dg - 0.5f * du * (2.0f * e.u + du);
+    }
+    // gamma part: q = chi_1 - ln L*0, e^q; colour part: r = c - a0 - b0 chi_1,
+    // r^2, r q, q^2.  With A = (a0 - a') + (b0 - b') ln L*0, B = b0 - b':
+    // sum (c - a' - b' chi_1)^2 = Sr2 + 2A Sr + 2B Srq + N A^2 + 2AB Sq + B^2 Sq2.
+    // a0 and b0 are the single-precision values the sweep formed r with
+    // (their rounding would otherwise enter N times).
+    static constexpr int NS = 6;
+    __device__ static void stats(const Obj &, const T *, const Eval<T> &e, const T *, const Statics &, T *out)
+    {
+        out[0] = e.q;
+        out[1] = e.eq;
+        out[2] = e.res;
+        out[3] = e.res * e.res;
+        out[4] = e.res * e.q;
+        out[5] = e.q * e.q;
+    }
+    __device__ static double stats_dlf(const double *t0, const double *tp, const double *a0, const double *ap,
+                                       const double *sv, double n, const Statics &)
+    {
+        const double af = static_cast<float>(t0[2]), bf = static_cast<float>(t0[3]);
+        const double A = (af - tp[2]) + (bf - tp[3]) * t0[1], B = bf - tp[3];
+        const double ssp = sv[3] + 2.0 * A * sv[2] + 2.0 * B * sv[4] + n * A * A + 2.0 * A * B * sv[0] + B * B * sv[5];
+        const double dcol = -0.5 * ssp / (tp[4] * tp[4]) + 0.5 * sv[3] / (t0[4] * t0[4]) - n * (ap[1] - a0[1]);
+        return gamma_stats_dlf(t0, tp, a0, ap, sv[0], sv[1], n) + dcol;
     }
 };
 
@@ -549,6 +632,14 @@ struct BB1 {
         const float num = (dx > -60.0f) ? expf(-x) * -expm1f(-dx) : expf(-x) - expf(-(x + dx));
         const float brk = (den > 0.0f) ? log1pf(num / den) : log1pf(kc[7]);
         return kc[8] * e.q - e.eq * kc[6] + brk;
+    }
+    // the break factor ties l to every object: no finite sufficient statistics
+    static constexpr int NS = 0;
+    __device__ static void stats(const Obj &, const T *, const Eval<T> &, const T *, const Statics &, T *) {}
+    __device__ static double stats_dlf(const double *, const double *, const double *, const double *, const double *,
+                                       double, const Statics &)
+    {
+        return 0.0;
     }
 };
 

@@ -129,6 +129,36 @@ def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
     stats = sampler.stats()
     theta1, cth1, _ = sampler.theta()
     d_g, d_o = stats["delta"], info["delta"]
+    n_sub = getattr(orc, "theta_substeps", 1)
+    if n_sub > 1:
+        # K steps on theta: the same number accepted, the same theta, the
+        # last step's log ratio within the tolerance (a near-tie inside the
+        # K steps would show as a different count)
+        has_sel = orc.wl.model in (2, 3, 5)
+        pl, tb = info["prop_last"], info["theta_before_last"]
+        scale, mag = 0.0, 0.0
+        if np.isfinite(orc.log_prior(pl)):
+            lp_p, lp_c = orc.pop_terms(pl, chi1), orc.pop_terms(tb, chi1)
+            scale = float(np.sum(np.abs(lp_p - lp_c)))
+            mag = float(np.sum(np.abs(lp_p)) + np.sum(np.abs(lp_c)))
+        # the statistics give Delta as a difference of N-term sums: in FP64 it
+        # carries rounding of the order of an ulp of the terms' magnitudes, not
+        # of their differences (in FP32 the per-object rounding dominates)
+        theta_tol = tol["theta_rel"] * max(1.0, scale) + (1e-12 * sampler.n if has_sel else 0.0) + \
+            (1e-14 * mag if prec == "f64" else 0.0)
+        assert int(acc_th_g) == info["n_accepted"], ("theta steps accepted", int(acc_th_g), info["n_accepted"])
+        if np.isfinite(d_o):
+            assert abs(d_g - d_o) <= theta_tol, ("theta delta", d_g, d_o, theta_tol)
+        # later proposals start from a factor adapted on alpha = min(1, e^Delta):
+        # each step moves the factor by at most |d Delta| relative, and a
+        # proposal by that times the step S z (a few diagonal scales)
+        dd = abs(d_g - d_o) if np.isfinite(d_o) else 0.0
+        rt = 1e-8 + 10.0 * n_sub * dd
+        scale_th = float(np.abs(np.diag(st.chol_theta)).max())
+        np.testing.assert_allclose(theta1, st.theta, rtol=rt, atol=rt * scale_th)
+        np.testing.assert_allclose(cth1, st.chol_theta, rtol=rt, atol=rt * scale_th)
+        return StepReport(sampler.n, float(rel_x.max()), float(rel_y.max()), near, len(mism), chi_err, chol_rel,
+                          d_g, d_o, theta_tol, False)
     # FP64 selection normalisers of the two sides agree to ~1e-13 relative
     has_sel = orc.wl.model in (2, 3, 5)
     theta_tol = tol["theta_rel"] * max(1.0, scale) + (1e-12 * sampler.n if has_sel else 0.0)

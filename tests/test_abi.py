@@ -68,3 +68,34 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(hbm, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         hbm.lib()
+
+
+def _reject(hbm, cfg, theta0):
+    L = ctypes.CDLL(hbm.LIB_PATH)
+    L.init_chains.argtypes = [ctypes.c_void_p] * 6
+    L.init_chains.restype = ctypes.c_int32
+    L.last_error.argtypes = [ctypes.c_void_p]
+    L.last_error.restype = ctypes.c_char_p
+    bufs = hbm.Buffers(8, 8, 8, 8, None)          # never dereferenced: the config fails first
+    out = ctypes.c_void_p()
+    th = (ctypes.c_double * len(theta0))(*theta0)
+    st = L.init_chains(ctypes.byref(cfg), ctypes.byref(bufs), None, th, None, ctypes.byref(out))
+    return st, L.last_error(None).decode(), out.value
+
+
+def test_init_chains_rejects_bad_theta_modes_before_touching_the_device():
+    """Dataset checks run before a context exists; they must not need one."""
+    import paper_2105_08026_amd as hbm
+    import synth
+    if not os.path.exists(hbm.LIB_PATH):
+        pytest.skip("library not built")
+    lf = synth.gamma_lf_1d(n=300, seed=3, fth=389.75)
+    st, msg, out = _reject(hbm, hbm.make_config(lf, max_cycles=10, theta_substeps=65), lf.theta0)
+    assert st == hbm.HBM_EINVAL and "theta_substeps" in msg and not out
+    cfg = hbm.make_config(lf, max_cycles=10, theta_substeps=2)
+    cfg.reserved = 1
+    st, msg, out = _reject(hbm, cfg, lf.theta0)
+    assert st == hbm.HBM_EINVAL and "reserved" in msg and not out
+    bb = synth.bb1_lf(n=50, seed=2, chunk=100_000)
+    st, msg, out = _reject(hbm, hbm.make_config(bb, max_cycles=10, theta_substeps=2), bb.theta0)
+    assert st == hbm.HBM_EINVAL and "sufficient statistics" in msg and not out
