@@ -59,6 +59,9 @@ def parse():
                     help="tiles per sweep workgroup; auto runs the autotuner during burn-in")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 20 times (calibration run for HBM counters)")
+    ap.add_argument("--theta-substeps", type=int, default=0,
+                    help="single-catalog workloads: 0 for one theta step per cycle from the N-term sums, K >= 1 "
+                         "for K steps per cycle from sufficient statistics")
     ap.add_argument("--thetas", type=int, default=64,
                     help="marginal workloads: theta rows evaluated per call (one step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -439,7 +442,7 @@ def main():
     wl = gen(n=args.n or n_default)
     trial = 64
     total = 3 * (32 + trial) + args.warmup + 2 * args.steps
-    s = hbm.Sampler(wl, device="cuda:0", max_cycles=total)
+    s = hbm.Sampler(wl, device="cuda:0", max_cycles=total, theta_substeps=args.theta_substeps)
     use_graph = not args.no_graph
 
     # burn-in: the launch-shape autotuner's cycles (or a fixed shape), then plain warm-up cycles
@@ -473,6 +476,15 @@ def main():
     th = s.theta_trace()
     assert np.all(np.isfinite(th)), "non-finite theta"
     stats = s.stats()
+    # effective samples of theta per second over the graph-timed cycles
+    # (variance over the squared batch-means standard error)
+    tw = th[len(th) - 2 * args.steps:len(th) - args.steps]
+    ess = []
+    for j in range(wl.p):
+        b = max(2, int(np.sqrt(len(tw))))
+        xb = tw[: b * (len(tw) // b), j].reshape(b, -1).mean(axis=1)
+        se2 = xb.var(ddof=1) / b
+        ess.append(float(tw[:, j].var() / se2) if se2 > 0 else None)
 
     updates = wl.n * args.steps / wall
     bpu = BYTES_PER_UPDATE[wl.name]
@@ -493,7 +505,9 @@ def main():
         "data": f"synthetic (seeded {wl.name} catalog)",
         "config": {"workload": wl.name, "n_objects": wl.n, "latent_dim": wl.d, "theta_dim": wl.p,
                    "selection_quadrature_nodes": 512 if wl.model in (2, 3, 5) else 0, "graph": use_graph,
-                   "sweeps_per_step": 1, "tiles_per_workgroup": pick},
+                   "sweeps_per_step": 1, "tiles_per_workgroup": pick,
+                   "theta_substeps": args.theta_substeps},
+        "theta_ess_per_s": [e / wall if e else None for e in ess],
         "autotune_us_per_cycle": {"1": tuned[0], "2": tuned[1], "4": tuned[2]},
         "gibbs_sweeps_per_s": args.steps / wall,
         "breakdown_ms": {"step": 1e3 * wall / args.steps, "sweep_kernel": kern_ms,

@@ -216,50 +216,77 @@ __device__ __forceinline__ double block_log_z(const double *zc, const double *qx
 
 // The theta step from the sweep's sufficient statistics: K = s.substeps
 // Metropolis steps on theta given chi, K >= 1, every thread of the
-// workgroup taking part (the selection normaliser of each later proposal is
-// a workgroup sum); lane 0 holds the chain.  Sub-step j of cycle k draws
-// its proposal normals from Philox blocks (j, k, 1, b) and its uniform from
-// (j, k, 2, 0); sub-step 0 judges the proposal the sweep was prepared with
-// (its ln Z comes from the sweep's side workgroup).  The change of
+// workgroup taking part.  Sub-step j of cycle k draws its proposal normals
+// from Philox blocks (j, k, 1, b) and its uniform from (j, k, 2, 0);
+// sub-step 0 judges the proposal the sweep was prepared with (its ln Z and
+// per-theta scalars come from the sweep's side workgroup).  The change of
 // sum_i log f between any two theta follows from the statistics in O(1);
 // the theta RAM adapts with eta_n, n = (k - 1) K + j + 1.
+//
+// Only the chain itself is sequential.  The draws, the step sizes eta and
+// (per step) the proposal's ln Z, lnGamma-type scalars and log prior do not
+// depend on the accept decisions that precede them in the same way: the
+// draws and eta for all K steps come first, one lane each; then each step's
+// proposal is formed by lane 0, and while the workgroup sums its selection
+// normaliser, lane 64 evaluates its per-theta scalars.
+constexpr int kMaxSubsteps = 64;
+
+// The per-theta scalars of a model (lnGamma ...) called out of line: inlined
+// into the sub-step loop they would spill the workgroup's registers.
+template <class M>
+__device__ __attribute__((noinline)) void aux_out_of_line(const double *th, double *a)
+{
+    M::aux(th, a);
+}
+
 template <class M>
 __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_trace, const Precomp &pc,
                                const double *qx, const double *qw, const double *qeps, int nq,
                                double (*red)[kWavesPerBlock])
 {
     constexpr int P = M::P, NB = (P + 3) / 4;
-    __shared__ double sh_prop[kMaxP], sh_z[kMaxP];
+    constexpr int kAuxLane = kWave;               // first lane of the second wavefront
+    __shared__ double sh_z[kMaxSubsteps][kMaxP];
+    __shared__ double sh_lnu[kMaxSubsteps], sh_eta[kMaxSubsteps];
+    __shared__ double sh_prop[kMaxP], sh_ap[2], sh_lp;
     __shared__ int32_t sh_valid;
+    const int K = s.substeps;
+    for (int j = threadIdx.x; j < K; j += kBlock) {
+        if (j == 0) {
+            for (int r = 0; r < P; ++r) sh_z[0][r] = c.used_z[r];
+            sh_lnu[0] = pc.ln_u;
+        } else {
+            for (int b = 0; b < NB; ++b) {
+                const Block4 blk = philox(static_cast<uint32_t>(j), static_cast<uint32_t>(c.k), 1u,
+                                          static_cast<uint32_t>(b), s.key0, s.key1);
+                double z4[4];
+                normals<double, 4>(blk, z4);
+                for (int q = 0; q < 4; ++q)
+                    if (4 * b + q < P) sh_z[j][4 * b + q] = z4[q];
+            }
+            const Block4 ub = philox(static_cast<uint32_t>(j), static_cast<uint32_t>(c.k), 2u, 0u, s.key0, s.key1);
+            sh_lnu[j] = log(uniform24<double>(ub, 4));
+        }
+        sh_eta[j] = pow(static_cast<double>((c.k - 1) * K + j + 2), -s.gamma);
+    }
     double t0[kMaxP], a0[2];
     for (int r = 0; r < P; ++r) t0[r] = c.theta[r];
     a0[0] = c.aux_cur[0];
     a0[1] = c.aux_cur[1];
-    const int K = s.substeps;
     const double n = static_cast<double>(s.n);
     double d_cur = 0.0;                 // sum log f(theta_j) - sum log f(theta_0)
     int n_acc = 0;
     double delta = -HUGE_VAL, alpha = 0.0;
+    __syncthreads();
     for (int j = 0; j < K; ++j) {
         if (threadIdx.x == 0) {
             if (j == 0) {
-                for (int r = 0; r < P; ++r) {
-                    sh_prop[r] = c.used_prop[r];
-                    sh_z[r] = c.used_z[r];
-                }
+                for (int r = 0; r < P; ++r) sh_prop[r] = c.used_prop[r];
                 sh_valid = c.used_valid;
             } else {
-                for (int b = 0; b < NB; ++b) {
-                    const Block4 blk = philox(static_cast<uint32_t>(j), static_cast<uint32_t>(c.k), 1u,
-                                              static_cast<uint32_t>(b), s.key0, s.key1);
-                    double z4[4];
-                    normals<double, 4>(blk, z4);
-                    for (int q = 0; q < 4; ++q)
-                        if (4 * b + q < P) sh_z[4 * b + q] = z4[q];
-                }
                 for (int r = 0; r < P; ++r) {
                     double v = c.theta[r];
-                    for (int q = 0; q <= r; ++q) v += c.chol_theta[r * P + q] * sh_z[q];
+                    for (int q = 0; q <= r; ++q) v += c.chol_theta[r * P + q] * sh_z[j][q];
                     sh_prop[r] = v;
                 }
                 sh_valid = M::in_support(sh_prop);
@@ -267,12 +294,20 @@ __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_tr
         }
         __syncthreads();
         double zraw = 0.0;
-        if constexpr (M::kSelection) {
-            if (j > 0 && sh_valid) {
+        if (j > 0 && sh_valid) {
+            if (threadIdx.x == kAuxLane) {
+                double ap[2];
+                aux_out_of_line<M>(sh_prop, ap);
+                sh_ap[0] = ap[0];
+                sh_ap[1] = ap[1];
+                sh_lp = M::log_prior(sh_prop);
+            }
+            if constexpr (M::kSelection) {
                 double zc[4];
                 M::z_consts(sh_prop, zc);
                 zraw = block_log_z<M>(zc, qx, qw, qeps, nq, red);
             }
+            __syncthreads();
         }
         if (threadIdx.x == 0) {
             double ap[2] = {0.0, 0.0}, lp = -HUGE_VAL, lz = 0.0, d_prop = 0.0;
@@ -284,8 +319,9 @@ __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_tr
                     lp = c.lprior_used;
                     lz = c.logZ_used;
                 } else {
-                    M::aux(sh_prop, ap);
-                    lp = M::log_prior(sh_prop);
+                    ap[0] = sh_ap[0];
+                    ap[1] = sh_ap[1];
+                    lp = sh_lp;
                     if (M::kSelection) {
                         lz = zraw - M::logz_shift(ap);
                         if (!(lz > -HUGE_VAL && lz < HUGE_VAL)) c.flags |= kFlagBadZ;
@@ -296,12 +332,7 @@ __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_tr
                 if (delta != delta) delta = -HUGE_VAL;
             }
             alpha = delta >= 0.0 ? 1.0 : exp(delta);
-            double ln_u = pc.ln_u;
-            if (j > 0) {
-                const Block4 ub = philox(static_cast<uint32_t>(j), static_cast<uint32_t>(c.k), 2u, 0u, s.key0, s.key1);
-                ln_u = log(uniform24<double>(ub, 4));
-            }
-            if (ln_u < delta) {
+            if (sh_lnu[j] < delta) {
                 for (int r = 0; r < P; ++r) c.theta[r] = sh_prop[r];
                 c.logZ_cur = lz;
                 c.lprior_cur = lp;
@@ -311,12 +342,11 @@ __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_tr
                 n_acc += 1;
             }
             if (s.adapt_theta) {
-                const double eta = pow(static_cast<double>((c.k - 1) * K + j + 2), -s.gamma);
                 double L[P * (P + 1) / 2], zz[P];
                 for (int r = 0, e = 0; r < P; ++r)
                     for (int q = 0; q <= r; ++q, ++e) L[e] = c.chol_theta[r * P + q];
-                for (int r = 0; r < P; ++r) zz[r] = sh_z[r];
-                ram_adapt<double, P>(L, zz, eta * (alpha - s.alpha_star_theta));
+                for (int r = 0; r < P; ++r) zz[r] = sh_z[j][r];
+                ram_adapt<double, P>(L, zz, sh_eta[j] * (alpha - s.alpha_star_theta));
                 for (int r = 0, e = 0; r < P; ++r)
                     for (int q = 0; q <= r; ++q, ++e) c.chol_theta[r * P + q] = L[e];
             }
