@@ -135,7 +135,9 @@ typedef struct hbm_config {
                                     j of cycle k drawing Philox blocks (j, k, 1, b) and (j, k, 2, 0);
                                     K = 1 makes the same chain as 0 up to rounding of the log ratio.
                                     Every dataset of a context uses 0, or every one K >= 1. */
-    int32_t reserved;            /* must be 0 */
+    int32_t snap_rows;           /* init_chains / init_batch: rows of chi_samples for this dataset
+                                    (0: max_cycles / thin_chi, every snapshot of the run; fewer rows
+                                    make a ring for run_cycles_streamed) */
     int64_t max_cycles;          /* capacity of the theta trace (and bound on snapshots) */
     double theta_chol0[25];      /* initial theta proposal factor, p x p lower, row-major */
     double model_consts[16];
@@ -270,6 +272,32 @@ HBM_API hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted);
  * Results are identical to alternating ram_sweep(1) and theta_step.
  * Asynchronous. */
 HBM_API hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph);
+
+/* Receives streamed latent snapshots of one slot: its snapshots number
+ * first .. first + count - 1 (snapshot r is the state after sweep
+ * (r + 1) * thin_chi), as count x d x N values of the context's precision
+ * (FP32 or FP64), row-major, in host memory valid only during the call.
+ * Return 0 to go on; any other value stops the run after the chunk in
+ * flight (run_cycles_streamed then returns HBM_ESTATE). */
+typedef int32_t (*hbm_snapshot_sink)(void *user, int32_t slot, int64_t first, int64_t count, const void *rows);
+
+/* run_cycles with every latent snapshot streamed to the host as it is taken
+ * (the paper's compact-memory sampler, Appendix A, keeps samples off the
+ * device the same way): chi_samples serves each slot as a ring of its
+ * snap_cap rows, so a run of any length needs only
+ * 2 * ceil(chunk_cycles / thin_chi) rows of device memory per slot instead
+ * of max_cycles / thin_chi.  Cycles go in chunks of chunk_cycles (graph
+ * replays, as run_cycles with use_graph); the copy of chunk c's rows into
+ * pinned host memory runs on a second stream while chunk c + 1 computes, and
+ * sink is called with chunk c's rows, on the calling thread, while chunk
+ * c + 1 computes.  Chunk c + 2 waits (on the device) for chunk c's copy
+ * before it overwrites those rows.  Slots with thin_chi = 0 stream nothing.
+ * Same chain, bit for bit, as run_cycles.  HBM_EINVAL when a streaming
+ * slot's ring is smaller than 2 * ceil(chunk_cycles / thin_chi) rows or
+ * sink is NULL.  Allocates its pinned staging (2 chunks of rows) on each
+ * call.  Synchronous: returns after the last rows were delivered. */
+HBM_API hbm_status run_cycles_streamed(hbm_ctx *ctx, int64_t n_cycles, int32_t chunk_cycles, hbm_snapshot_sink sink,
+                                       void *user);
 
 /* Copy a slot's recorded samples to host.  theta_out: [count][p] rows
  * first..first+count-1 of its theta trace (or NULL).  chi_out: [count][d][N]

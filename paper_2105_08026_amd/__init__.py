@@ -26,7 +26,8 @@ HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_
 HBM_FP64, HBM_FP32 = 1, 2
 
 EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
-            "ram_sweep", "pop_loglik", "marginal_loglik", "theta_step", "run_cycles", "get_samples", "get_theta", "set_theta",
+            "ram_sweep", "pop_loglik", "marginal_loglik", "theta_step", "run_cycles", "run_cycles_streamed",
+            "get_samples", "get_theta", "set_theta",
             "ram_sweep_trace", "get_state", "set_state", "get_stats", "set_launch", "autotune", "kernel_timing",
             "read_kernel_timing", "last_error", "destroy_chains")
 
@@ -53,7 +54,7 @@ class Config(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("target_accept", ctypes.c_double), ("eta_exponent", ctypes.c_double),
         ("s0", ctypes.c_double), ("theta_target_accept", ctypes.c_double), ("adapt_theta", ctypes.c_int32),
         ("n_quad", ctypes.c_int32), ("thin_chi", ctypes.c_int32), ("tiles_per_group", ctypes.c_int32),
-        ("theta_substeps", ctypes.c_int32), ("reserved", ctypes.c_int32), ("max_cycles", ctypes.c_int64), ("theta_chol0", ctypes.c_double * 25), ("model_consts", ctypes.c_double * 16),
+        ("theta_substeps", ctypes.c_int32), ("snap_rows", ctypes.c_int32), ("max_cycles", ctypes.c_int64), ("theta_chol0", ctypes.c_double * 25), ("model_consts", ctypes.c_double * 16),
     ]
 
 
@@ -91,6 +92,7 @@ def lib():
             "marginal_loglik": [P, i32, i32, P, P, P],
             "theta_step": [P, P],
             "run_cycles": [P, i64, i32],
+            "run_cycles_streamed": [P, i64, i32, SNAPSHOT_SINK, P],
             "get_samples": [P, i32, i64, i64, P, P, P],
             "get_theta": [P, i32, P, P, P],
             "set_theta": [P, i32, P, P, i64],
@@ -216,6 +218,26 @@ def run_cycles(ctx, n_cycles: int, use_graph: bool = True):
     _check(lib().run_cycles(ctx, n_cycles, int(use_graph)), ctx)
 
 
+# int32 sink(void *user, int32 slot, int64 first, int64 count, const void *rows)
+SNAPSHOT_SINK = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_void_p)
+
+
+def run_cycles_streamed(ctx, n_cycles: int, chunk_cycles: int, on_rows, row_shape, dtype):
+    """Runs n_cycles cycles streaming every latent snapshot: on_rows(slot, first,
+    rows) receives each slot's new snapshots as a [count][d][N] array it owns
+    (row_shape(slot) gives (d, N)); returning True stops the run."""
+    itemsize = np.dtype(dtype).itemsize
+
+    def _sink(_user, slot, first, count, ptr):
+        d, n = row_shape(slot)
+        buf = (ctypes.c_char * (count * d * n * itemsize)).from_address(ptr)
+        rows = np.frombuffer(buf, dtype=dtype).reshape(count, d, n).copy()
+        return 1 if on_rows(slot, first, rows) else 0
+    cb = SNAPSHOT_SINK(_sink)
+    _check(lib().run_cycles_streamed(ctx, n_cycles, chunk_cycles, cb, None), ctx)
+
+
 def get_samples(ctx, slot: int, first: int, count: int, p: int, chi_shape=None, chi_dtype=None):
     """Returns (theta rows [count][p], latent snapshots [count][d][N] or None)."""
     th = np.zeros((count, p))
@@ -303,7 +325,7 @@ def destroy_chains(ctx):
 
 def make_config(wl, max_cycles: int = 10000, thin: int = 0, s0: float = 1.0, adapt_theta: bool = True,
                 n_quad: int = 512, gamma: float = 2.0 / 3.0, alpha_star_theta: float = 0.4, seed=None,
-                theta_substeps: int = 0) -> Config:
+                theta_substeps: int = 0, snap_rows: int = 0) -> Config:
     """The hbm_config of a :mod:`synth` workload.  theta_substeps: 0 for one
     theta step per cycle from the N-term sums, K >= 1 for K steps per cycle
     from sufficient statistics."""
@@ -315,6 +337,7 @@ def make_config(wl, max_cycles: int = 10000, thin: int = 0, s0: float = 1.0, ada
     cfg.theta_target_accept, cfg.adapt_theta = alpha_star_theta, int(adapt_theta)
     cfg.n_quad, cfg.thin_chi, cfg.max_cycles = n_quad, thin, max_cycles
     cfg.theta_substeps = int(theta_substeps)
+    cfg.snap_rows = int(snap_rows)
     ch0 = np.asarray(wl.theta_chol0, dtype=np.float64)
     for r in range(p):
         for q in range(p):
@@ -385,13 +408,14 @@ class Sampler(_Chains):
     def __init__(self, wl, device: str = "cuda:0", max_cycles: int = 10000, thin: int = 0, s0: float = 1.0,
                  adapt_theta: bool = True, n_quad: int = 512, gamma: float = 2.0 / 3.0,
                  alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None, seed=None,
-                 theta_substeps: int = 0):
+                 theta_substeps: int = 0, snap_rows: int = 0):
         self.wl, self.n = wl, wl.n
-        self._alloc(wl.model, wl.n, max_cycles // thin if thin > 0 else 0, device, stream)
+        rows = (snap_rows if snap_rows > 0 else max_cycles // thin) if thin > 0 else 0
+        self._alloc(wl.model, wl.n, rows, device, stream)
         with torch.no_grad():
             self.data.copy_(torch.as_tensor(np.ascontiguousarray(wl.data), dtype=self.dtype))
         self.config = make_config(wl, max_cycles, thin, s0, adapt_theta, n_quad, gamma, alpha_star_theta, seed,
-                                  theta_substeps)
+                                  theta_substeps, snap_rows)
         torch.cuda.synchronize(self.device)
         with torch.cuda.device(self.device):
             self.ctx = init_chains(self.config, self.buffers, wl.chi0, wl.theta0, self.stream.cuda_stream)
@@ -427,6 +451,18 @@ class Sampler(_Chains):
 
     def chi_snapshots(self, first: int, count: int) -> np.ndarray:
         return get_samples(self.ctx, 0, first, count, self.p, (self.d, self.n), self.npdtype)[1]
+
+    def run_streamed(self, n: int, chunk: int, on_rows=None):
+        """n cycles with every latent snapshot streamed to the host through a
+        ring of snap_rows device rows; on_rows(first, rows) receives each
+        chunk's snapshots (default: collect them and return [count][d][N])."""
+        got = []
+        cb = (lambda slot, first, rows: on_rows(first, rows)) if on_rows else \
+            (lambda slot, first, rows: got.append((first, rows)) and False)
+        run_cycles_streamed(self.ctx, n, chunk, cb, lambda slot: (self.d, self.n), self.npdtype)
+        if on_rows is None:
+            return np.concatenate([r for _, r in got]) if got else np.zeros((0, self.d, self.n), self.npdtype)
+        return None
 
     def trace_sweep(self) -> np.ndarray:
         """One sweep returning per-object (log pi(X), log pi(Y), accepted, Y[0..d-1]) as float64 [3 + d][N]."""
@@ -532,12 +568,13 @@ class Pool(_Chains):
     """
 
     def __init__(self, model: int, capacity: int, n_slots: int, max_cycles: int, device: str = "cuda:0",
-                 n_quad: int = 512, stream: Optional[torch.cuda.Stream] = None, stats_theta: bool = False):
+                 n_quad: int = 512, stream: Optional[torch.cuda.Stream] = None, stats_theta: bool = False,
+                 snap_rows: int = 0):
         cap = -(-int(capacity) // TILE) * TILE
-        self._alloc(model, cap, 0, device, stream)
+        self._alloc(model, cap, snap_rows, device, stream)
         pc = PoolConfig()
         pc.model, pc.precision, pc.n_slots = model, _MODEL_DIMS[model][3], n_slots
-        pc.n_quad, pc.capacity, pc.max_cycles, pc.snap_rows = n_quad, cap, max_cycles, 0
+        pc.n_quad, pc.capacity, pc.max_cycles, pc.snap_rows = n_quad, cap, max_cycles, snap_rows
         pc.stats_theta = int(stats_theta)
         self.pool_config, self.n_slots, self.max_cycles = pc, n_slots, max_cycles
         self.free_slots = list(range(n_slots - 1, -1, -1))
@@ -598,6 +635,14 @@ class Pool(_Chains):
 
     def run_cycles(self, n: int, use_graph: bool = True):
         run_cycles(self.ctx, n, use_graph)
+        for s in self.left:
+            self.left[s] -= n
+
+    def run_streamed(self, n: int, chunk: int, on_rows):
+        """n cycles streaming every resident job's latent snapshots:
+        on_rows(slot, first, rows [count][d][N_slot])."""
+        run_cycles_streamed(self.ctx, n, chunk, on_rows, lambda slot: (self.d, self.resident[slot][1]),
+                            self.npdtype)
         for s in self.left:
             self.left[s] -= n
 

@@ -299,7 +299,7 @@ struct Statics {
     int32_t adapt_theta;
     int32_t p;
     int32_t substeps;              // theta steps per cycle from sufficient statistics (0: generic sums)
-    int32_t pad_;
+    int32_t snap_ring;             // 1 while a streamed run uses the snapshot rows as a ring
     uint32_t key0, key1;
     double gamma;                  // eta exponent
     double alpha_star, alpha_star_theta;

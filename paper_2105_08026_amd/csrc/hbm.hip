@@ -18,7 +18,9 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -93,6 +95,9 @@ struct CtxImpl {
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t graph_len = 0;
+    // streamed runs: the copy stream and its events
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t swept[2] = {nullptr, nullptr}, copied[2] = {nullptr, nullptr};
     // marginal likelihood: node tables (datum rule, then product rule) and a
     // scratch area grown on demand for theta, results and partial sums
     MargNode *marg_rule = nullptr;
@@ -488,6 +493,12 @@ void release(CtxImpl *c)
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->copy_stream) {
+        (void)hipStreamSynchronize(c->copy_stream);
+        (void)hipStreamDestroy(c->copy_stream);
+    }
+    for (hipEvent_t e : {c->swept[0], c->swept[1], c->copied[0], c->copied[1]})
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
     void *ptrs[] = {c->dd, c->partials, c->pout, c->theta_in, c->side, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
@@ -515,7 +526,7 @@ hbm_status validate_dataset(CtxImpl *c, const hbm_config *cfg, const double *the
         return fail(c, HBM_EINVAL, "eta_exponent must lie in (1/2, 1]");
     if (!(cfg->s0 > 0.0) || !std::isfinite(cfg->s0)) return fail(c, HBM_EINVAL, "s0 must be positive");
     if (cfg->thin_chi < 0 || cfg->max_cycles < 0) return fail(c, HBM_EINVAL, "thin_chi and max_cycles must be >= 0");
-    if (cfg->reserved != 0) return fail(c, HBM_EINVAL, "reserved must be 0");
+    if (cfg->snap_rows < 0) return fail(c, HBM_EINVAL, "snap_rows must be >= 0");
     if (stats_mode ? (cfg->theta_substeps < 1 || cfg->theta_substeps > 64) : cfg->theta_substeps != 0)
         return fail(c, HBM_EINVAL,
                     stats_mode ? "theta_substeps must be in [1, 64] in a context whose theta steps use sufficient "
@@ -754,7 +765,9 @@ hbm_status load(CtxImpl *c, int32_t count, const int32_t *slots, const int64_t *
         s.snap_cap = 0;
         if (cfg->thin_chi > 0 && c->buf.chi_samples) {
             const int64_t want = cfg->max_cycles / cfg->thin_chi;
-            s.snap_cap = want < c->pool.snap_rows ? want : c->pool.snap_rows;
+            const int64_t rows = (cfg->snap_rows > 0 && cfg->snap_rows < c->pool.snap_rows) ? cfg->snap_rows
+                                                                                            : c->pool.snap_rows;
+            s.snap_cap = want < rows ? want : rows;
         }
         s.thin = cfg->thin_chi;
         s.nq = c->nq;
@@ -924,6 +937,155 @@ bool marg_density_ok(int model, const double *th)
     }
 }
 
+// Checks that n_cycles full cycles can run now.
+hbm_status check_cycles(CtxImpl *c, int64_t n_cycles)
+{
+    if (n_cycles < 0) return fail(c, HBM_EINVAL, "n_cycles must be >= 0");
+    for (const Slot &sl : c->slots) {
+        if (!sl.active) continue;
+        if (sl.sums_ready) return fail(c, HBM_ESTATE, "a ram_sweep is waiting for its theta_step");
+        if (sl.n_theta + cycles_taken(sl, n_cycles) > sl.trace_cap)
+            return fail(c, HBM_ENOSPACE, "theta trace would overflow (max_cycles)");
+    }
+    return HBM_OK;
+}
+
+// Issues n full cycles on the context's stream: replays of a captured graph
+// of 32 cycles, then single cycles for the rest.  Host mirrors unchanged.
+hbm_status issue_cycles(CtxImpl *c, int64_t n_cycles, bool use_graph)
+{
+    int64_t left = n_cycles;
+    if (use_graph && !c->timing && n_cycles > 0) {
+        const int64_t glen = 32;
+        if (!c->graph_exec) {
+            if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+            hipStream_t saved = c->stream;
+            c->stream = c->capture_stream;
+            HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+            hbm_status st = HBM_OK;
+            for (int64_t j = 0; j < glen && st == HBM_OK; ++j) st = c->ops->sweep(c, true, nullptr);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+            c->stream = saved;
+            if (st != HBM_OK) return st;
+            if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+            c->graph = g;
+            HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+            c->graph_len = glen;
+        }
+        while (left >= c->graph_len) {
+            HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+            left -= c->graph_len;
+        }
+    }
+    for (int64_t j = 0; j < left; ++j) {
+        hbm_status st = c->ops->sweep(c, true, nullptr);
+        if (st != HBM_OK) return st;
+    }
+    return HBM_OK;
+}
+
+// Sets every streaming slot's ring flag in its device statics.
+hbm_status set_snap_ring(CtxImpl *c, int32_t on)
+{
+    for (int32_t j = 0; j < c->n_slots; ++j) {
+        const Slot &sl = c->slots[j];
+        if (!sl.loaded || sl.thin <= 0) continue;
+        HIPCHK(c, hipMemcpyAsync(reinterpret_cast<char *>(c->st + j) + offsetof(Statics, snap_ring), &on,
+                                 sizeof(on), hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HBM_OK;
+}
+
+// Rows of one slot copied in one chunk: snapshots [first, first + count).
+struct ChunkPiece {
+    int32_t slot;
+    int64_t first, count;
+    size_t offset;             // into the chunk's staging
+};
+
+// The body of run_cycles_streamed (arguments checked).
+hbm_status stream_cycles(CtxImpl *c, int64_t n_cycles, int32_t chunk_cycles, size_t chunk_bytes,
+                         hbm_snapshot_sink sink, void *user)
+{
+    if (!c->copy_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+        if (!c->swept[b]) HIPCHK(c, hipEventCreateWithFlags(&c->swept[b], hipEventDisableTiming));
+        if (!c->copied[b]) HIPCHK(c, hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming));
+    }
+    void *staging[2] = {nullptr, nullptr};
+    for (int b = 0; b < 2; ++b)
+        if (chunk_bytes > 0 && hipHostMalloc(&staging[b], chunk_bytes, hipHostMallocDefault) != hipSuccess) {
+            if (staging[0]) (void)hipHostFree(staging[0]);
+            return fail(c, HBM_ENOMEM, "hipHostMalloc: snapshot staging");
+        }
+    std::vector<ChunkPiece> pieces[2];
+    hbm_status st = set_snap_ring(c, 1);
+    bool stop = false;
+    const int64_t n_chunks = (n_cycles + chunk_cycles - 1) / chunk_cycles;
+    // hands chunk q's rows to the sink once its copy has landed
+    auto deliver = [&](int64_t q) -> hbm_status {
+        const int b = static_cast<int>(q & 1);
+        HIPCHK(c, hipEventSynchronize(c->copied[b]));
+        for (const ChunkPiece &pc : pieces[b])
+            if (!stop && sink(user, pc.slot, pc.first, pc.count, static_cast<char *>(staging[b]) + pc.offset) != 0)
+                stop = true;
+        pieces[b].clear();
+        return HBM_OK;
+    };
+    for (int64_t q = 0; q < n_chunks && st == HBM_OK && !stop; ++q) {
+        const int b = static_cast<int>(q & 1);
+        const int64_t len = std::min<int64_t>(chunk_cycles, n_cycles - q * chunk_cycles);
+        // the rows chunk q - 2 left in the ring must be copied before this chunk overwrites them
+        if (q >= 2) HIPCHK(c, hipStreamWaitEvent(c->stream, c->copied[b], 0));
+        std::vector<int64_t> k0(c->n_slots);
+        for (int32_t j = 0; j < c->n_slots; ++j) k0[j] = c->slots[j].k;
+        if ((st = issue_cycles(c, len, true)) != HBM_OK) break;
+        for (Slot &sl : c->slots) after_theta_steps(sl, cycles_taken(sl, len));
+        HIPCHK(c, hipEventRecord(c->swept[b], c->stream));
+        if (q >= 1 && (st = deliver(q - 1)) != HBM_OK) break;
+        // this chunk's snapshots, slot by slot, into staging[b]
+        HIPCHK(c, hipStreamWaitEvent(c->copy_stream, c->swept[b], 0));
+        size_t off = 0;
+        for (int32_t j = 0; j < c->n_slots; ++j) {
+            const Slot &sl = c->slots[j];
+            if (!sl.loaded || sl.thin <= 0) continue;
+            const int64_t first = k0[j] / sl.thin, end = sl.k / sl.thin;
+            if (end <= first) continue;
+            const size_t row_bytes = static_cast<size_t>(c->d) * sl.n * c->esize;
+            pieces[b].push_back(ChunkPiece{j, first, end - first, off});
+            for (int64_t r = first; r < end;) {
+                // a run of consecutive ring rows: one strided copy of its d x N blocks
+                const int64_t ring = r % sl.snap_cap;
+                const int64_t run = std::min<int64_t>(end - r, sl.snap_cap - ring);
+                const char *src = static_cast<const char *>(c->buf.chi_samples) +
+                                  (static_cast<size_t>(ring) * c->d * c->cap + sl.obj_start) * c->esize;
+                HIPCHK(c, hipMemcpy2DAsync(static_cast<char *>(staging[b]) + off, sl.n * c->esize, src,
+                                           c->cap * c->esize, sl.n * c->esize, run * c->d, hipMemcpyDeviceToHost,
+                                           c->copy_stream));
+                off += static_cast<size_t>(run) * row_bytes;
+                r += run;
+            }
+        }
+        HIPCHK(c, hipEventRecord(c->copied[b], c->copy_stream));
+        if (q == n_chunks - 1 || stop) st = deliver(q);
+    }
+    hbm_status st2 = HBM_OK;
+    {
+        hipError_t e1 = hipStreamSynchronize(c->copy_stream), e2 = hipStreamSynchronize(c->stream);
+        if (e1 != hipSuccess) st2 = hip_fail(c, e1, "copy stream");
+        else if (e2 != hipSuccess) st2 = hip_fail(c, e2, "stream");
+    }
+    if (st2 == HBM_OK && (st2 = set_snap_ring(c, 0)) != HBM_OK) {}
+    for (void *p : staging)
+        if (p) (void)hipHostFree(p);
+    if (st != HBM_OK) return st;
+    if (st2 != HBM_OK) return st2;
+    if (stop) return fail(c, HBM_ESTATE, "the snapshot sink stopped the run");
+    return HBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -994,7 +1156,9 @@ hbm_status init_chains(const hbm_config *config, const hbm_buffers *buffers, con
     pool.n_quad = config->n_quad;
     pool.capacity = config->n_objects;
     pool.max_cycles = config->max_cycles;
-    pool.snap_rows = (config->thin_chi > 0 && buffers->chi_samples) ? config->max_cycles / config->thin_chi : 0;
+    pool.snap_rows = (config->thin_chi > 0 && buffers->chi_samples)
+                         ? (config->snap_rows > 0 ? config->snap_rows : config->max_cycles / config->thin_chi)
+                         : 0;
     pool.tiles_per_group = config->tiles_per_group;
     pool.stats_theta = config->theta_substeps > 0 ? 1 : 0;
     // dataset checks first, so a bad dataset reports its own reason
@@ -1059,8 +1223,8 @@ hbm_status init_batch(int32_t n_datasets, const hbm_config *configs, const hbm_b
         pool.capacity = o + cf.n_objects;
         o += static_cast<int64_t>(tiles_for(cf.n_objects)) * kBlock;
         if (cf.max_cycles > pool.max_cycles) pool.max_cycles = cf.max_cycles;
-        if (cf.thin_chi > 0 && buffers->chi_samples && cf.max_cycles / cf.thin_chi > pool.snap_rows)
-            pool.snap_rows = cf.max_cycles / cf.thin_chi;
+        const int64_t rows = cf.snap_rows > 0 ? cf.snap_rows : (cf.thin_chi > 0 ? cf.max_cycles / cf.thin_chi : 0);
+        if (cf.thin_chi > 0 && buffers->chi_samples && rows > pool.snap_rows) pool.snap_rows = rows;
     }
     CtxImpl *c = nullptr;
     hbm_status s = create_ctx(&pool, buffers, hip_stream, &c);
@@ -1189,44 +1353,32 @@ hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted)
 hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
-        if (n_cycles < 0) return fail(c, HBM_EINVAL, "n_cycles must be >= 0");
-        for (const Slot &sl : c->slots) {
-            if (!sl.active) continue;
-            if (sl.sums_ready) return fail(c, HBM_ESTATE, "a ram_sweep is waiting for its theta_step");
-            if (sl.n_theta + cycles_taken(sl, n_cycles) > sl.trace_cap)
-                return fail(c, HBM_ENOSPACE, "theta trace would overflow (max_cycles)");
-        }
-        int64_t left = n_cycles;
-        if (use_graph && !c->timing && n_cycles > 0) {
-            const int64_t glen = 32;
-            if (!c->graph_exec) {
-                if (!c->capture_stream)
-                    HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
-                hipStream_t saved = c->stream;
-                c->stream = c->capture_stream;
-                HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-                hbm_status st = HBM_OK;
-                for (int64_t j = 0; j < glen && st == HBM_OK; ++j) st = c->ops->sweep(c, true, nullptr);
-                hipGraph_t g = nullptr;
-                hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
-                c->stream = saved;
-                if (st != HBM_OK) return st;
-                if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-                c->graph = g;
-                HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
-                c->graph_len = glen;
-            }
-            while (left >= c->graph_len) {
-                HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
-                left -= c->graph_len;
-            }
-        }
-        for (int64_t j = 0; j < left; ++j) {
-            hbm_status st = c->ops->sweep(c, true, nullptr);
-            if (st != HBM_OK) return st;
-        }
+        hbm_status st = check_cycles(c, n_cycles);
+        if (st != HBM_OK) return st;
+        if ((st = issue_cycles(c, n_cycles, use_graph != 0)) != HBM_OK) return st;
         for (Slot &sl : c->slots) after_theta_steps(sl, cycles_taken(sl, n_cycles));
         return HBM_OK;
+    });
+}
+
+hbm_status run_cycles_streamed(hbm_ctx *ctx, int64_t n_cycles, int32_t chunk_cycles, hbm_snapshot_sink sink,
+                               void *user)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        hbm_status st = check_cycles(c, n_cycles);
+        if (st != HBM_OK) return st;
+        if (!sink) return fail(c, HBM_EINVAL, "sink must be non-NULL");
+        if (chunk_cycles < 1) return fail(c, HBM_EINVAL, "chunk_cycles must be >= 1");
+        // every streaming slot needs two chunks of ring rows
+        size_t chunk_bytes = 0;
+        for (const Slot &sl : c->slots) {
+            if (!sl.active || sl.thin <= 0) continue;
+            const int64_t per_chunk = (chunk_cycles + sl.thin - 1) / sl.thin;
+            if (sl.snap_cap < 2 * per_chunk)
+                return fail(c, HBM_EINVAL, "a streaming slot needs snap_rows >= 2 * ceil(chunk_cycles / thin_chi)");
+            chunk_bytes += static_cast<size_t>(per_chunk) * c->d * sl.n * c->esize;
+        }
+        return stream_cycles(c, n_cycles, chunk_cycles, chunk_bytes, sink, user);
     });
 }
 

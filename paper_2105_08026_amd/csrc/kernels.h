@@ -393,6 +393,7 @@ struct TileView {
     uint32_t key0, key1;
     int32_t thin;
     int32_t active;
+    int32_t snap_ring;         // snapshots wrap around the snap_cap rows (streamed runs)
     T eta, astar;
 };
 
@@ -402,7 +403,7 @@ __device__ __forceinline__ TileView<typename M::T> tile_view(const SweepArgs<typ
     using T = typename M::T;
     const CycleState &c = a.cs[ds];
     const Statics &s = a.st[ds];
-    return TileView<T>{c.k + 1, s.obj_start, s.n, s.snap_cap, s.key0, s.key1, s.thin, c.active,
+    return TileView<T>{c.k + 1, s.obj_start, s.n, s.snap_cap, s.key0, s.key1, s.thin, c.active, s.snap_ring,
                        static_cast<T>(c.eta_next), static_cast<T>(s.alpha_star)};
 }
 
@@ -471,7 +472,8 @@ __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, i
         for (int j = 0; j < D; ++j) a.trace[(3 + j) * n + i] = y[j];
     }
     if (a.snaps != nullptr && tv.thin > 0 && k % tv.thin == 0) {
-        const int64_t snap = k / tv.thin - 1;
+        int64_t snap = k / tv.thin - 1;
+        if (tv.snap_ring && tv.snap_cap > 0) snap %= tv.snap_cap;
         if (snap < tv.snap_cap) {
 #pragma unroll
             for (int j = 0; j < D; ++j) a.snaps[(snap * D + j) * n + i] = x[j];

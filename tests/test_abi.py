@@ -93,9 +93,9 @@ def test_init_chains_rejects_bad_theta_modes_before_touching_the_device():
     st, msg, out = _reject(hbm, hbm.make_config(lf, max_cycles=10, theta_substeps=65), lf.theta0)
     assert st == hbm.HBM_EINVAL and "theta_substeps" in msg and not out
     cfg = hbm.make_config(lf, max_cycles=10, theta_substeps=2)
-    cfg.reserved = 1
+    cfg.snap_rows = -1
     st, msg, out = _reject(hbm, cfg, lf.theta0)
-    assert st == hbm.HBM_EINVAL and "reserved" in msg and not out
+    assert st == hbm.HBM_EINVAL and "snap_rows" in msg and not out
     bb = synth.bb1_lf(n=50, seed=2, chunk=100_000)
     st, msg, out = _reject(hbm, hbm.make_config(bb, max_cycles=10, theta_substeps=2), bb.theta0)
     assert st == hbm.HBM_EINVAL and "sufficient statistics" in msg and not out
