@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--workload", default="gamma_lf_1d",
                     choices=["gamma_lf_1d", "gamma_lf_color_3d", "normal_normal_1d", "normal_normal_3d",
                              "bb1_lf", "gamma_lf_batch256", "serving", "marginal_gamma_lf_1d", "marginal_bb1_lf",
-                             "marginal_normal_normal_1d"])
+                             "marginal_normal_normal_1d", "streaming_gamma_lf_1d"])
     ap.add_argument("--horizon", type=float, default=60.0, help="serving: seconds of Poisson arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--sat-jobs", type=int, default=200, help="serving: jobs in the saturation run")
@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--theta-substeps", type=int, default=0,
                     help="single-catalog workloads: 0 for one theta step per cycle from the N-term sums, K >= 1 "
                          "for K steps per cycle from sufficient statistics")
+    ap.add_argument("--thin", type=int, default=10, help="streaming: a latent snapshot every THIN sweeps")
+    ap.add_argument("--chunk", type=int, default=320, help="streaming: cycles per streamed chunk")
     ap.add_argument("--thetas", type=int, default=64,
                     help="marginal workloads: theta rows evaluated per call (one step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -404,6 +406,75 @@ def bench_marginal(args, torch, synth, hbm):
     print(json.dumps(out), flush=True)
 
 
+def bench_streaming(args, torch, synth, hbm):
+    """Latent snapshots every --thin sweeps of the 300,000-object gamma-LF
+    catalog, streamed to the host through a ring of 2 ceil(chunk / thin)
+    device rows, against the same cycles with no snapshots and with every
+    snapshot kept in a full device buffer."""
+    import os
+    import tempfile
+
+    wl = synth.gamma_lf_1d(n=args.n or 300_000)
+    steps, thin, chunk = args.steps, args.thin, args.chunk
+    ring = 2 * (-(-chunk // thin))
+    row_bytes = wl.n * 4
+
+    def timed(s, run):
+        s.run_cycles(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    total = args.warmup + steps
+    plain = hbm.Sampler(wl, device="cuda:0", max_cycles=total)
+    plain.set_launch(1)
+    t_plain = timed(plain, lambda: plain.run_cycles(steps))
+    plain.close()
+    full = hbm.Sampler(wl, device="cuda:0", max_cycles=total, thin=thin)
+    full.set_launch(1)
+    t_full = timed(full, lambda: full.run_cycles(steps))
+    full_rows = full.snaps.shape[0]
+    full.close()
+    del full
+    torch.cuda.empty_cache()
+    got = {"rows": 0}
+
+    def count(first, rows):
+        got["rows"] += rows.shape[0]
+        return False
+    st = hbm.Sampler(wl, device="cuda:0", max_cycles=total, thin=thin, snap_rows=ring)
+    st.set_launch(1)
+    t_stream = timed(st, lambda: st.run_streamed(steps, chunk, count, copy=False))
+    st.close()
+    fs = hbm.Sampler(wl, device="cuda:0", max_cycles=total, thin=thin, snap_rows=ring)
+    fs.set_launch(1)
+    fd, path = tempfile.mkstemp(dir=os.environ.get("TMPDIR", "/tmp"), suffix=".f32")
+    os.close(fd)
+    try:
+        t_file = timed(fs, lambda: fs.run_to_file(steps, chunk, path))
+        file_bytes = os.path.getsize(path)
+    finally:
+        os.unlink(path)
+    fs.close()
+    rows_streamed = (args.warmup + steps) // thin - args.warmup // thin
+    out = {
+        "metric": METRIC, "value": wl.n * steps / t_stream, "unit": "updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_stream / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded gamma_lf_1d catalog)",
+        "config": {"workload": "streaming_gamma_lf_1d", "n_objects": wl.n, "thin": thin, "chunk_cycles": chunk,
+                   "ring_rows": ring},
+        "us_per_cycle": {"no_snapshots": 1e6 * t_plain / steps, "full_device_buffer": 1e6 * t_full / steps,
+                         "streamed_to_host": 1e6 * t_stream / steps, "streamed_to_file": 1e6 * t_file / steps},
+        "snapshot_device_bytes": {"full_device_buffer": full_rows * row_bytes, "streamed_ring": ring * row_bytes},
+        "rows_delivered": got["rows"], "rows_expected": rows_streamed, "file_bytes": file_bytes,
+        "d2h_GBps_streamed": rows_streamed * row_bytes / t_stream / 1e9,
+        "d2h_GBps_to_file": rows_streamed * row_bytes / t_file / 1e9,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -434,6 +505,9 @@ def main():
         return
     if args.workload.startswith("marginal_"):
         bench_marginal(args, torch, synth, hbm)
+        return
+    if args.workload == "streaming_gamma_lf_1d":
+        bench_streaming(args, torch, synth, hbm)
         return
     make = {"gamma_lf_1d": (synth.gamma_lf_1d, 300_000), "gamma_lf_color_3d": (synth.gamma_lf_3d, 1_000_000),
             "normal_normal_1d": (synth.normal_normal_1d, 300_000), "normal_normal_3d": (synth.normal_normal_3d, 300_000),

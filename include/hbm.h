@@ -276,10 +276,16 @@ HBM_API hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph)
 /* Receives streamed latent snapshots of one slot: its snapshots number
  * first .. first + count - 1 (snapshot r is the state after sweep
  * (r + 1) * thin_chi), as count x d x N values of the context's precision
- * (FP32 or FP64), row-major, in host memory valid only during the call.
- * Return 0 to go on; any other value stops the run after the chunk in
- * flight (run_cycles_streamed then returns HBM_ESTATE). */
-typedef int32_t (*hbm_snapshot_sink)(void *user, int32_t slot, int64_t first, int64_t count, const void *rows);
+ * (FP32 or FP64), row-major, bytes in all, in host memory valid only during
+ * the call.  Return 0 to go on; any other value stops the run after the
+ * chunk in flight (run_cycles_streamed then returns HBM_ESTATE). */
+typedef int32_t (*hbm_snapshot_sink)(void *user, int32_t slot, int64_t first, int64_t count, const void *rows,
+                                     int64_t bytes);
+
+/* A ready sink: appends each batch of rows, as raw bytes, to the open file
+ * descriptor held in user (cast from intptr_t).  Returns nonzero (stopping
+ * the run) when the write fails. */
+HBM_API int32_t fd_sink(void *user, int32_t slot, int64_t first, int64_t count, const void *rows, int64_t bytes);
 
 /* run_cycles with every latent snapshot streamed to the host as it is taken
  * (the paper's compact-memory sampler, Appendix A, keeps samples off the

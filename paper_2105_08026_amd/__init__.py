@@ -27,7 +27,7 @@ HBM_FP64, HBM_FP32 = 1, 2
 
 EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
             "ram_sweep", "pop_loglik", "marginal_loglik", "theta_step", "run_cycles", "run_cycles_streamed",
-            "get_samples", "get_theta", "set_theta",
+            "fd_sink", "get_samples", "get_theta", "set_theta",
             "ram_sweep_trace", "get_state", "set_state", "get_stats", "set_launch", "autotune", "kernel_timing",
             "read_kernel_timing", "last_error", "destroy_chains")
 
@@ -105,6 +105,8 @@ def lib():
             "kernel_timing": [P, i32],
             "read_kernel_timing": [P, P, P],
         }
+        L.fd_sink.argtypes = [P, i32, i64, i64, P, i64]
+        L.fd_sink.restype = i32
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
@@ -218,24 +220,34 @@ def run_cycles(ctx, n_cycles: int, use_graph: bool = True):
     _check(lib().run_cycles(ctx, n_cycles, int(use_graph)), ctx)
 
 
-# int32 sink(void *user, int32 slot, int64 first, int64 count, const void *rows)
+# int32 sink(void *user, int32 slot, int64 first, int64 count, const void *rows, int64 bytes)
 SNAPSHOT_SINK = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
-                                 ctypes.c_void_p)
+                                 ctypes.c_void_p, ctypes.c_int64)
 
 
-def run_cycles_streamed(ctx, n_cycles: int, chunk_cycles: int, on_rows, row_shape, dtype):
+def run_cycles_streamed(ctx, n_cycles: int, chunk_cycles: int, on_rows, row_shape, dtype, copy: bool = True):
     """Runs n_cycles cycles streaming every latent snapshot: on_rows(slot, first,
-    rows) receives each slot's new snapshots as a [count][d][N] array it owns
-    (row_shape(slot) gives (d, N)); returning True stops the run."""
+    rows) receives each slot's new snapshots as a [count][d][N] array
+    (row_shape(slot) gives (d, N)) -- its own copy, or with copy=False a view
+    of the library's staging valid only during the call; returning True
+    stops the run."""
     itemsize = np.dtype(dtype).itemsize
 
-    def _sink(_user, slot, first, count, ptr):
+    def _sink(_user, slot, first, count, ptr, nbytes):
         d, n = row_shape(slot)
-        buf = (ctypes.c_char * (count * d * n * itemsize)).from_address(ptr)
-        rows = np.frombuffer(buf, dtype=dtype).reshape(count, d, n).copy()
-        return 1 if on_rows(slot, first, rows) else 0
+        assert nbytes == count * d * n * itemsize
+        buf = (ctypes.c_char * nbytes).from_address(ptr)
+        rows = np.frombuffer(buf, dtype=dtype).reshape(count, d, n)
+        return 1 if on_rows(slot, first, rows.copy() if copy else rows) else 0
     cb = SNAPSHOT_SINK(_sink)
     _check(lib().run_cycles_streamed(ctx, n_cycles, chunk_cycles, cb, None), ctx)
+
+
+def run_cycles_to_fd(ctx, n_cycles: int, chunk_cycles: int, fd: int):
+    """Streams every latent snapshot, as raw rows, to an open file descriptor
+    through the library's own sink (no Python on the data path)."""
+    sink = ctypes.cast(lib().fd_sink, SNAPSHOT_SINK)
+    _check(lib().run_cycles_streamed(ctx, n_cycles, chunk_cycles, sink, ctypes.c_void_p(fd)), ctx)
 
 
 def get_samples(ctx, slot: int, first: int, count: int, p: int, chi_shape=None, chi_dtype=None):
@@ -452,17 +464,29 @@ class Sampler(_Chains):
     def chi_snapshots(self, first: int, count: int) -> np.ndarray:
         return get_samples(self.ctx, 0, first, count, self.p, (self.d, self.n), self.npdtype)[1]
 
-    def run_streamed(self, n: int, chunk: int, on_rows=None):
+    def run_streamed(self, n: int, chunk: int, on_rows=None, copy: bool = True):
         """n cycles with every latent snapshot streamed to the host through a
         ring of snap_rows device rows; on_rows(first, rows) receives each
-        chunk's snapshots (default: collect them and return [count][d][N])."""
+        chunk's snapshots (default: collect them and return [count][d][N];
+        copy=False hands on_rows a view valid only during the call)."""
         got = []
         cb = (lambda slot, first, rows: on_rows(first, rows)) if on_rows else \
             (lambda slot, first, rows: got.append((first, rows)) and False)
-        run_cycles_streamed(self.ctx, n, chunk, cb, lambda slot: (self.d, self.n), self.npdtype)
+        run_cycles_streamed(self.ctx, n, chunk, cb, lambda slot: (self.d, self.n), self.npdtype,
+                            copy=copy or on_rows is None)
         if on_rows is None:
             return np.concatenate([r for _, r in got]) if got else np.zeros((0, self.d, self.n), self.npdtype)
         return None
+
+    def run_to_file(self, n: int, chunk: int, path: str):
+        """n cycles appending every latent snapshot to the file at path as raw
+        [d][N] rows of the context's precision."""
+        import os
+        fd = os.open(path, os.O_WRONLY | os.O_CREAT | os.O_APPEND, 0o644)
+        try:
+            run_cycles_to_fd(self.ctx, n, chunk, fd)
+        finally:
+            os.close(fd)
 
     def trace_sweep(self) -> np.ndarray:
         """One sweep returning per-object (log pi(X), log pi(Y), accepted, Y[0..d-1]) as float64 [3 + d][N]."""

@@ -18,7 +18,10 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <cerrno>
 #include <climits>
 #include <cstddef>
 #include <cmath>
@@ -1002,7 +1005,7 @@ hbm_status set_snap_ring(CtxImpl *c, int32_t on)
 struct ChunkPiece {
     int32_t slot;
     int64_t first, count;
-    size_t offset;             // into the chunk's staging
+    size_t offset, bytes;      // into the chunk's staging
 };
 
 // The body of run_cycles_streamed (arguments checked).
@@ -1029,7 +1032,8 @@ hbm_status stream_cycles(CtxImpl *c, int64_t n_cycles, int32_t chunk_cycles, siz
         const int b = static_cast<int>(q & 1);
         HIPCHK(c, hipEventSynchronize(c->copied[b]));
         for (const ChunkPiece &pc : pieces[b])
-            if (!stop && sink(user, pc.slot, pc.first, pc.count, static_cast<char *>(staging[b]) + pc.offset) != 0)
+            if (!stop && sink(user, pc.slot, pc.first, pc.count, static_cast<char *>(staging[b]) + pc.offset,
+                              static_cast<int64_t>(pc.bytes)) != 0)
                 stop = true;
         pieces[b].clear();
         return HBM_OK;
@@ -1054,16 +1058,21 @@ hbm_status stream_cycles(CtxImpl *c, int64_t n_cycles, int32_t chunk_cycles, siz
             const int64_t first = k0[j] / sl.thin, end = sl.k / sl.thin;
             if (end <= first) continue;
             const size_t row_bytes = static_cast<size_t>(c->d) * sl.n * c->esize;
-            pieces[b].push_back(ChunkPiece{j, first, end - first, off});
+            pieces[b].push_back(ChunkPiece{j, first, end - first, off, static_cast<size_t>(end - first) * row_bytes});
             for (int64_t r = first; r < end;) {
                 // a run of consecutive ring rows: one strided copy of its d x N blocks
                 const int64_t ring = r % sl.snap_cap;
                 const int64_t run = std::min<int64_t>(end - r, sl.snap_cap - ring);
                 const char *src = static_cast<const char *>(c->buf.chi_samples) +
                                   (static_cast<size_t>(ring) * c->d * c->cap + sl.obj_start) * c->esize;
-                HIPCHK(c, hipMemcpy2DAsync(static_cast<char *>(staging[b]) + off, sl.n * c->esize, src,
-                                           c->cap * c->esize, sl.n * c->esize, run * c->d, hipMemcpyDeviceToHost,
-                                           c->copy_stream));
+                if (sl.n == c->cap)         // rows back to back: one linear copy
+                    HIPCHK(c, hipMemcpyAsync(static_cast<char *>(staging[b]) + off, src,
+                                             static_cast<size_t>(run) * row_bytes, hipMemcpyDeviceToHost,
+                                             c->copy_stream));
+                else
+                    HIPCHK(c, hipMemcpy2DAsync(static_cast<char *>(staging[b]) + off, sl.n * c->esize, src,
+                                               c->cap * c->esize, sl.n * c->esize, run * c->d,
+                                               hipMemcpyDeviceToHost, c->copy_stream));
                 off += static_cast<size_t>(run) * row_bytes;
                 r += run;
             }
@@ -1380,6 +1389,20 @@ hbm_status run_cycles_streamed(hbm_ctx *ctx, int64_t n_cycles, int32_t chunk_cyc
         }
         return stream_cycles(c, n_cycles, chunk_cycles, chunk_bytes, sink, user);
     });
+}
+
+int32_t fd_sink(void *user, int32_t, int64_t, int64_t, const void *rows, int64_t bytes)
+{
+    const int fd = static_cast<int>(reinterpret_cast<intptr_t>(user));
+    const char *p = static_cast<const char *>(rows);
+    while (bytes > 0) {
+        const ssize_t w = ::write(fd, p, static_cast<size_t>(bytes));
+        if (w < 0 && errno == EINTR) continue;
+        if (w <= 0) return 1;
+        p += w;
+        bytes -= w;
+    }
+    return 0;
 }
 
 hbm_status get_samples(hbm_ctx *ctx, int32_t slot, int64_t first, int64_t count, double *theta_out, void *chi_out,

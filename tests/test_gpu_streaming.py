@@ -7,6 +7,7 @@ taken, through a small device ring).
 * the theta chain is unchanged by streaming;
 * a pool streams each resident job's snapshots (jobs admitted at different
   sweeps, one stopped by its budget mid-chunk) equal to each job run alone;
+* the library's file-descriptor sink writes the same rows to a file;
 * the sink can stop a run; a ring smaller than two chunks is refused.
 """
 import sys
@@ -95,4 +96,19 @@ def test_sink_stops_and_ring_checks(hbm):
     assert seen and seen[-1] >= 8
     with pytest.raises(hbm.HbmError, match="snap_rows"):
         s.run_streamed(40, 9)           # ceil(9 / 2) = 5 rows per chunk: a ring of 8 is too small
+    s.close()
+
+
+def test_file_sink(hbm, tmp_path):
+    wl = synth.gamma_lf_1d(n=3000, seed=98, fth=389.75)
+    m, thin, chunk = 120, 5, 30
+    full = hbm.Sampler(wl, max_cycles=m, thin=thin)
+    full.run_cycles(m)
+    ref = full.chi_snapshots(0, m // thin)
+    s = hbm.Sampler(wl, max_cycles=m, thin=thin, snap_rows=12)
+    path = str(tmp_path / "chi.f32")
+    s.run_to_file(m, chunk, path)
+    got = np.fromfile(path, dtype=np.float32).reshape(-1, wl.d, wl.n)
+    assert np.array_equal(got, ref)
+    full.close()
     s.close()
