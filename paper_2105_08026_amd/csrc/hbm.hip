@@ -48,7 +48,7 @@ struct Launch {
     hbm_status (*check_init)(CtxImpl *);      // slots flagged in c->which
     hbm_status (*quadrature)(CtxImpl *);      // reference Gauss-Legendre rule
     hbm_status (*marginal)(CtxImpl *, int32_t slot, int32_t n_theta, const double *theta, double *out,
-                           double *partials, double *terms);   // device arguments
+                           double *partials, double *th, double *terms);   // device arguments
 };
 
 // Host mirror of one slot.  Every field follows from the calls made, so the
@@ -360,14 +360,18 @@ struct Ops {
     }
 
     static hbm_status marginal(CtxImpl *c, int32_t slot, int32_t n_theta, const double *theta, double *out,
-                               double *partials, double *terms)
+                               double *partials, double *th, double *terms)
     {
         if constexpr (HasMarg<M>::value) {
             using R = typename Marg<M>::R;
+            hipLaunchKernelGGL((marginal_prep_kernel<M>), dim3((n_theta + 63) / 64), dim3(64), 0, c->stream, theta,
+                               th, n_theta);
+            LAUNCHCHK(c, "marginal_prep_kernel");
             MargArgs a;
             a.data = c->buf.data;
             a.rule = c->marg_rule + (R::kGraded > 0 ? 0 : kMargShapeNodes);
             a.theta = theta;
+            a.th = th;
             a.partials = partials;
             a.terms = terms;
             a.st = c->st + slot;
@@ -391,7 +395,7 @@ struct Ops {
             LAUNCHCHK(c, "marginal_finish_kernel");
             return HBM_OK;
         } else {
-            (void)slot; (void)n_theta; (void)theta; (void)out; (void)partials; (void)terms;
+            (void)slot; (void)n_theta; (void)theta; (void)out; (void)partials; (void)th; (void)terms;
             return fail(c, HBM_EINVAL, "the marginal likelihood needs a model with a 1-D latent");
         }
     }
@@ -1313,7 +1317,8 @@ hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const do
         if ((st = ensure_marg_rule(c)) != HBM_OK) return st;
         const int64_t nb = marg_blocks(c->slots[slot].n);
         const size_t n_th = static_cast<size_t>(n_theta) * c->p, n_part = static_cast<size_t>(n_theta) * nb;
-        const size_t need = sizeof(double) * (n_th + n_theta + n_part);
+        const size_t n_pre = static_cast<size_t>(n_theta) * kMargThWords;
+        const size_t need = sizeof(double) * (n_th + n_theta + n_part + n_pre);
         if (need > c->marg_bytes) {
             HIPCHK(c, hipStreamSynchronize(c->stream));
             if (c->marg_buf) HIPCHK(c, hipFree(c->marg_buf));
@@ -1324,9 +1329,9 @@ hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const do
             c->marg_buf = static_cast<double *>(p);
             c->marg_bytes = need;
         }
-        double *d_theta = c->marg_buf, *d_out = d_theta + n_th, *d_part = d_out + n_theta;
+        double *d_theta = c->marg_buf, *d_out = d_theta + n_th, *d_part = d_out + n_theta, *d_pre = d_part + n_part;
         HIPCHK(c, hipMemcpyAsync(d_theta, theta, sizeof(double) * n_th, hipMemcpyHostToDevice, c->stream));
-        if ((st = c->ops->marginal(c, slot, n_theta, d_theta, d_out, d_part, terms)) != HBM_OK) return st;
+        if ((st = c->ops->marginal(c, slot, n_theta, d_theta, d_out, d_part, d_pre, terms)) != HBM_OK) return st;
         HIPCHK(c, hipMemcpyAsync(out, d_out, sizeof(double) * n_theta, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return HBM_OK;

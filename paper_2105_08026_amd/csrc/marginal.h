@@ -278,10 +278,26 @@ __device__ __forceinline__ MargGeo marg_geo(const typename G::Obj &o, const type
     else return G::geo(o, t, s);
 }
 
+// Doubles reserved per theta row for the model's per-theta scalars (Th).
+constexpr int kMargThWords = 8;
+
+// Per-theta scalars (lnGamma, ln C ...) once per row, ahead of the main kernel.
+template <class M>
+__global__ void marginal_prep_kernel(const double *theta, double *th, int32_t n_theta)
+{
+    using G = Marg<M>;
+    static_assert(sizeof(typename G::Th) <= kMargThWords * sizeof(double), "Th must fit its slot");
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_theta) return;
+    *reinterpret_cast<typename G::Th *>(th + static_cast<int64_t>(j) * kMargThWords) =
+        G::prep(theta + static_cast<int64_t>(j) * M::P);
+}
+
 struct MargArgs {
     const void *data;          // the context's packed data [components][cap]
     const MargNode *rule;      // per node q: see MargRuleShape / MargRuleProduct
     const double *theta;       // [n_theta][p]
+    const double *th;          // [n_theta][kMargThWords]: each row's Th, from marginal_prep_kernel
     double *partials;          // [n_theta][n_blocks]
     double *terms;             // [n_theta][n] or nullptr
     const Statics *st;         // the slot's statics
@@ -386,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void marginal_kernel(MargArgs a)
     __shared__ double red[1][kWavesPerBlock];
     const Statics &s = *a.st;
     const int it = blockIdx.y;
-    const typename G::Th t = G::prep(a.theta + static_cast<int64_t>(it) * M::P);
+    const typename G::Th t = *reinterpret_cast<const typename G::Th *>(a.th + static_cast<int64_t>(it) * kMargThWords);
     const int64_t il = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / kMargLanes;
     const int sub = threadIdx.x % kMargLanes, lane = threadIdx.x % kWave;
     const bool valid = il < s.n;
