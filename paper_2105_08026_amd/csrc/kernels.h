@@ -35,6 +35,8 @@ struct Precomp {
     double ln_u;
     double eta_next;
     double zraw;      // quadrature sum of ln Z at the judged proposal (before its shift)
+    double logz_used; // ln Z at the judged proposal (0 without selection or support)
+    double dconst;    // N times the object-independent part of its log f change (dlf_const)
 };
 static_assert(sizeof(Precomp) % 8 == 0, "Precomp is copied in 8-byte words");
 
@@ -134,7 +136,7 @@ __device__ void prepare_next(CycleState &c, const Statics &s, const Precomp &pc)
 // judges (lane 0): the proposal the sweep used, its ln Z, log prior and
 // aux scalars, and sum_i [log f(chi_i; theta') - log f(chi_i; theta)].
 template <class M, bool kStats = false>
-__device__ void finish_sweep(CycleState &c, const Statics &s, const double *v, double zraw, const Precomp &pc)
+__device__ void finish_sweep(CycleState &c, const Statics &s, const double *v, const Precomp &pc)
 {
     c.k += 1;
     c.sum_lf = v[0];
@@ -154,15 +156,12 @@ __device__ void finish_sweep(CycleState &c, const Statics &s, const double *v, d
     c.aux_used[0] = pc.aux_used[0];
     c.aux_used[1] = pc.aux_used[1];
     c.lprior_used = pc.lprior_used;
-    c.logZ_used = 0.0;
+    // ln Z(theta') and N dlf_const come from the sweep's side workgroup
+    c.logZ_used = pc.logz_used;
     c.sum_dlf = v[1];
     if (c.used_valid) {
-        if (M::kSelection) {
-            c.logZ_used = zraw - M::logz_shift(c.aux_used);
-            if (!(c.logZ_used > -HUGE_VAL && c.logZ_used < HUGE_VAL)) c.flags |= kFlagBadZ;
-        }
-        if constexpr (!kStats)
-            c.sum_dlf = v[1] - static_cast<double>(s.n) * M::dlf_const(c.theta, c.used_prop, c.aux_cur, c.aux_used);
+        if (M::kSelection && !(c.logZ_used > -HUGE_VAL && c.logZ_used < HUGE_VAL)) c.flags |= kFlagBadZ;
+        if constexpr (!kStats) c.sum_dlf = v[1] - pc.dconst;
     }
     if constexpr (kStats) c.sum_dlf = 0.0;
     c.eta_used = c.eta_next;
@@ -528,6 +527,14 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
         precompute<M>(sd, cs->k + 1, judged, valid, st);
         if (threadIdx.x == 0) sd.zraw = zraw;
         __syncthreads();
+        // the judged proposal's ln Z and constant log f change, off the
+        // epilogue's serial path (they need its aux scalars from wave 0)
+        if (threadIdx.x == 0) {
+            sd.logz_used = (valid && M::kSelection) ? zraw - M::logz_shift(sd.aux_used) : 0.0;
+            sd.dconst = valid ? static_cast<double>(st.n) * M::dlf_const(cs->theta, judged, cs->aux_cur, sd.aux_used)
+                              : 0.0;
+        }
+        __syncthreads();
         const uint64_t *src = reinterpret_cast<const uint64_t *>(&sd);
         uint64_t *dst = reinterpret_cast<uint64_t *>(a.side + ds);
         for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
@@ -664,9 +671,24 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
     const int32_t t0 = kSingle ? 0 : st.tile_start, nt = kSingle ? ntt : st.n_tiles;
     // Every load is issued before the dataset's flag is looked at (it arrives
     // with the staged state); the values of a dataset that is off are unused.
-    // tile partials of this dataset, structure of arrays [3][n_tiles_total]:
+    // The state and the side values are loaded first, into registers, so
+    // their latency overlaps the partials' (loads complete in issue order).
+    constexpr int kCsWords = static_cast<int>(sizeof(CycleState) / 8), kPcWords = static_cast<int>(sizeof(Precomp) / 8);
+    constexpr int kCsPer = (kCsWords + kBlock - 1) / kBlock;
+    static_assert(kPcWords <= kBlock, "one side word per thread");
+    uint64_t csw[kCsPer], pcw = 0;
+    {
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(a.cs + ds);
+#pragma unroll
+        for (int u = 0; u < kCsPer; ++u) {
+            const int j = u * kBlock + static_cast<int>(threadIdx.x);
+            csw[u] = j < kCsWords ? src[j] : 0;
+        }
+        if (static_cast<int>(threadIdx.x) < kPcWords) pcw = reinterpret_cast<const uint64_t *>(a.side + ds)[threadIdx.x];
+    }
+    // tile partials of this dataset, structure of arrays [NCOL][n_tiles_total]:
     // lane t adds tiles t, t + 256, t + 512, ... in that order; the loads of
-    // up to 8 such tiles are issued together before any is added
+    // up to G such tiles are issued together before any is added
     double v[NCOL];
 #pragma unroll
     for (int col = 0; col < NCOL; ++col) v[col] = 0.0;
@@ -688,15 +710,19 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
         }
     }
     {
-        const uint64_t *src = reinterpret_cast<const uint64_t *>(a.side + ds);
-        uint64_t *dst = reinterpret_cast<uint64_t *>(&pc);
-        for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
+        uint64_t *dc = reinterpret_cast<uint64_t *>(&c);
+#pragma unroll
+        for (int u = 0; u < kCsPer; ++u) {
+            const int j = u * kBlock + static_cast<int>(threadIdx.x);
+            if (j < kCsWords) dc[j] = csw[u];
+        }
+        if (static_cast<int>(threadIdx.x) < kPcWords) reinterpret_cast<uint64_t *>(&pc)[threadIdx.x] = pcw;
     }
-    stage_in(c, a.cs + ds);              // its barrier also publishes pc
+    __syncthreads();
     if (!c.active) return;               // uniform: read from LDS after the barrier
     block_sum<NCOL>(v, red);
     if constexpr (kStats) {
-        if (threadIdx.x == 0) finish_sweep<M, true>(c, st, v, pc.zraw, pc);
+        if (threadIdx.x == 0) finish_sweep<M, true>(c, st, v, pc);
         if constexpr (kFull) {
             __syncthreads();
             const int64_t qo = static_cast<int64_t>(ds) * a.nq;
@@ -705,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
         }
         if (threadIdx.x == 0) prepare_next<M>(c, st, pc);
     } else if (threadIdx.x == 0) {
-        finish_sweep<M>(c, st, v, pc.zraw, pc);
+        finish_sweep<M>(c, st, v, pc);
         if (kFull) theta_mh<M>(c, st, a.theta_trace + ds * a.trace_stride * M::P, pc.ln_u);
         prepare_next<M>(c, st, pc);
     }
