@@ -69,11 +69,21 @@ class TileAllocator:
 
 
 class PoolExecutor:
-    """Runs the loop's decisions on a :class:`paper_2105_08026_amd.Pool`."""
+    """Runs the loop's decisions on a :class:`paper_2105_08026_amd.Pool`.
 
-    def __init__(self, pool, make_workload: Callable[[Job], object], chunk: int = 32):
+    cfg: extra dataset settings for every job (e.g. thin, theta_substeps).
+    on_rows(job, first, rows): when given, every chunk is a streamed run and
+    each job's latent snapshots reach it as they are taken (the pool then
+    needs only snap_rows = 2 ceil(chunk / thin) rows of device memory).
+    """
+
+    def __init__(self, pool, make_workload: Callable[[Job], object], chunk: int = 32, cfg: Optional[dict] = None,
+                 on_rows: Optional[Callable] = None):
         self.pool, self.make, self.chunk = pool, make_workload, chunk
         self.max_tiles = pool.tiles.size
+        self.cfg = dict(cfg or {})
+        self.on_rows = on_rows
+        self.jobs = {}
 
     def fits(self, job: Job) -> bool:
         return self.pool.fits(job.n)
@@ -82,17 +92,23 @@ class PoolExecutor:
         return -(-job.n // 256) > self.max_tiles or job.sweeps > self.pool.max_cycles
 
     def admit(self, job: Job, wl) -> int:
-        (slot,) = self.pool.admit([wl], [job.sweeps])
+        (slot,) = self.pool.admit([wl], [job.sweeps], **self.cfg)
         assert slot is not None
+        self.jobs[slot] = job
         return slot
 
     def run(self) -> List[int]:
         import torch
-        self.pool.run_cycles(self.chunk)
+        if self.on_rows is None:
+            self.pool.run_cycles(self.chunk)
+        else:
+            self.pool.run_streamed(self.chunk, self.chunk,
+                                   lambda slot, first, rows: self.on_rows(self.jobs[slot], first, rows))
         torch.cuda.synchronize(self.pool.device)
         return self.pool.finished()
 
     def retire(self, slot: int) -> np.ndarray:
+        self.jobs.pop(slot, None)
         return self.pool.retire(slot)
 
 

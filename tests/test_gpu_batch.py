@@ -217,6 +217,35 @@ def test_request_loop_results_same_alone_and_in_the_mix(hbm):
         assert np.array_equal(j.trace, tr), j.id
 
 
+def test_request_loop_streams_each_jobs_snapshots(hbm):
+    """Serving with streamed latent snapshots: a pool with a ring of two
+    chunks of rows; every job's snapshots reach the host as they are taken
+    and equal the snapshots of the job run alone."""
+    from paper_2105_08026_amd import serve as sv
+    specs = [(0.00, 3200, 900, 96), (0.01, 3201, 2600, 64), (0.03, 3202, 300, 80), (0.06, 3203, 1500, 48)]
+    jobs = [sv.Job(i, t, seed, n, sw) for i, (t, seed, n, sw) in enumerate(specs)]
+    thin, chunk = 4, 16
+    rows = {}
+
+    def make(job):
+        return synth.gamma_lf_1d(n=job.n, seed=job.seed, fth=FTH)
+
+    def on_rows(job, first, r):
+        rows.setdefault(job.id, []).append((first, r))
+    pool = hbm.Pool(hbm.HBM_GAMMA_LF_1D, capacity=4096, n_slots=3, max_cycles=200, snap_rows=2 * (chunk // thin))
+    res = sv.serve(jobs, sv.PoolExecutor(pool, make, chunk=chunk, cfg={"thin": thin}, on_rows=on_rows))
+    pool.close()
+    assert len(res["jobs"]) == len(jobs)
+    for j in res["jobs"]:
+        alone = hbm.Sampler(make(j), max_cycles=j.sweeps, thin=thin)
+        alone.run_cycles(j.sweeps)
+        ref = alone.chi_snapshots(0, j.sweeps // thin)
+        got = np.concatenate([r for _, r in rows[j.id]])
+        assert [f for f, _ in rows[j.id]][0] == 0 and np.array_equal(got, ref), j.id
+        assert np.array_equal(j.trace, alone.theta_trace()), j.id
+        alone.close()
+
+
 @pytest.mark.parametrize("make", [lambda: synth.gamma_lf_1d(n=3000, seed=72, fth=FTH),
                                   lambda: synth.normal_normal_3d(n=700, seed=9)], ids=["lf1d", "nn3d"])
 def test_checkpoint_resume_continues_exactly(hbm, make):
