@@ -448,6 +448,15 @@ def bench_streaming(args, torch, synth, hbm):
     st.set_launch(1)
     t_stream = timed(st, lambda: st.run_streamed(steps, chunk, count, copy=False))
     st.close()
+    hr = hbm.Sampler(wl, device="cuda:0", max_cycles=total, thin=thin, snap_rows=ring, snap_host=True)
+    hr.set_launch(1)
+    got_h = {"rows": 0}
+
+    def count_h(first, rows):
+        got_h["rows"] += rows.shape[0]
+        return False
+    t_hring = timed(hr, lambda: hr.run_streamed(steps, chunk, count_h, copy=False))
+    hr.close()
     fs = hbm.Sampler(wl, device="cuda:0", max_cycles=total, thin=thin, snap_rows=ring)
     fs.set_launch(1)
     fd, path = tempfile.mkstemp(dir=os.environ.get("TMPDIR", "/tmp"), suffix=".f32")
@@ -466,10 +475,13 @@ def bench_streaming(args, torch, synth, hbm):
         "config": {"workload": "streaming_gamma_lf_1d", "n_objects": wl.n, "thin": thin, "chunk_cycles": chunk,
                    "ring_rows": ring},
         "us_per_cycle": {"no_snapshots": 1e6 * t_plain / steps, "full_device_buffer": 1e6 * t_full / steps,
-                         "streamed_to_host": 1e6 * t_stream / steps, "streamed_to_file": 1e6 * t_file / steps},
+                         "streamed_to_host": 1e6 * t_stream / steps, "streamed_to_file": 1e6 * t_file / steps,
+                         "host_ring_zero_copy": 1e6 * t_hring / steps},
         "snapshot_device_bytes": {"full_device_buffer": full_rows * row_bytes, "streamed_ring": ring * row_bytes},
-        "rows_delivered": got["rows"], "rows_expected": rows_streamed, "file_bytes": file_bytes,
+        "rows_delivered": got["rows"], "rows_delivered_host_ring": got_h["rows"], "rows_expected": rows_streamed,
+        "file_bytes": file_bytes,
         "d2h_GBps_streamed": rows_streamed * row_bytes / t_stream / 1e9,
+        "d2h_GBps_host_ring": rows_streamed * row_bytes / t_hring / 1e9,
         "d2h_GBps_to_file": rows_streamed * row_bytes / t_file / 1e9,
     }
     print(json.dumps(out), flush=True)

@@ -371,7 +371,7 @@ def packed_offsets(ns):
 class _Chains:
     """Shared plumbing: torch-owned packed device buffers and a context."""
 
-    def _alloc(self, model: int, cap: int, snap_rows: int, device, stream):
+    def _alloc(self, model: int, cap: int, snap_rows: int, device, stream, snap_host: bool = False):
         d, p, m, prec = _MODEL_DIMS[model]
         self.model, self.d, self.p, self.m, self.cap = model, d, p, m, cap
         self.dtype = torch.float64 if prec == HBM_FP64 else torch.float32
@@ -383,8 +383,11 @@ class _Chains:
             self.chi = torch.zeros((d, cap), dtype=self.dtype, device=self.device)
             self.chol = torch.empty((d * (d + 1) // 2, cap), dtype=self.dtype, device=self.device)
             self.acc = torch.empty((cap,), dtype=torch.int32, device=self.device)
-            self.snaps = (torch.empty((snap_rows, d, cap), dtype=self.dtype, device=self.device)
-                          if snap_rows > 0 else None)
+            # snapshots in HBM, or in pinned host memory the sweep writes through its device mapping
+            self.snaps = None
+            if snap_rows > 0:
+                self.snaps = (torch.empty((snap_rows, d, cap), dtype=self.dtype, pin_memory=True) if snap_host else
+                              torch.empty((snap_rows, d, cap), dtype=self.dtype, device=self.device))
         self.buffers = Buffers(self.data.data_ptr(), self.chi.data_ptr(), self.chol.data_ptr(), self.acc.data_ptr(),
                                self.snaps.data_ptr() if self.snaps is not None else None)
 
@@ -420,10 +423,10 @@ class Sampler(_Chains):
     def __init__(self, wl, device: str = "cuda:0", max_cycles: int = 10000, thin: int = 0, s0: float = 1.0,
                  adapt_theta: bool = True, n_quad: int = 512, gamma: float = 2.0 / 3.0,
                  alpha_star_theta: float = 0.4, stream: Optional[torch.cuda.Stream] = None, seed=None,
-                 theta_substeps: int = 0, snap_rows: int = 0):
+                 theta_substeps: int = 0, snap_rows: int = 0, snap_host: bool = False):
         self.wl, self.n = wl, wl.n
         rows = (snap_rows if snap_rows > 0 else max_cycles // thin) if thin > 0 else 0
-        self._alloc(wl.model, wl.n, rows, device, stream)
+        self._alloc(wl.model, wl.n, rows, device, stream, snap_host)
         with torch.no_grad():
             self.data.copy_(torch.as_tensor(np.ascontiguousarray(wl.data), dtype=self.dtype))
         self.config = make_config(wl, max_cycles, thin, s0, adapt_theta, n_quad, gamma, alpha_star_theta, seed,

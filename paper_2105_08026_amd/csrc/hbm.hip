@@ -98,6 +98,10 @@ struct CtxImpl {
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t graph_len = 0;
+    // latent snapshots: the pointer kernels write through (chi_samples, or its
+    // device mapping when the caller gave pinned host memory)
+    void *snaps_dev = nullptr;
+    bool snaps_host = false;
     // streamed runs: the copy stream and its events
     hipStream_t copy_stream = nullptr;
     hipEvent_t swept[2] = {nullptr, nullptr}, copied[2] = {nullptr, nullptr};
@@ -188,7 +192,7 @@ struct Ops {
         a.chol = static_cast<T *>(c->buf.chol);
         a.acc = c->buf.acc;
         a.dd = static_cast<const T *>(c->dd);
-        a.snaps = static_cast<T *>(c->buf.chi_samples);
+        a.snaps = static_cast<T *>(c->snaps_dev);
         a.trace = static_cast<T *>(trace);
         a.partials = c->partials;
         a.side = c->side;
@@ -646,6 +650,22 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
     if (!c) return fail(nullptr, HBM_ENOMEM, "host allocation failed");
     c->pool = *pool;
     c->buf = *buffers;
+    c->snaps_dev = buffers->chi_samples;
+    if (buffers->chi_samples) {
+        // pinned host memory (hipHostMalloc): the sweep writes the snapshots
+        // straight to the host through its device mapping
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, buffers->chi_samples) == hipSuccess && at.type == hipMemoryTypeHost) {
+            void *dp = nullptr;
+            if (hipHostGetDevicePointer(&dp, buffers->chi_samples, 0) != hipSuccess || !dp) {
+                delete static_cast<hbm_ctx *>(c);
+                return fail(nullptr, HBM_EINVAL, "chi_samples in host memory must be pinned and mapped (hipHostMalloc)");
+            }
+            c->snaps_dev = dp;
+            c->snaps_host = true;
+        }
+        (void)hipGetLastError();     // a pointer HIP does not know leaves only a non-sticky error
+    }
     c->d = mi.d;
     c->p = mi.p;
     c->m = mi.m;
@@ -1012,49 +1032,80 @@ struct ChunkPiece {
     size_t offset, bytes;      // into the chunk's staging
 };
 
-// The body of run_cycles_streamed (arguments checked).
+// The body of run_cycles_streamed (arguments checked).  Device ring: each
+// chunk's rows are copied on the copy stream into pinned staging.  Host ring
+// (chi_samples in pinned host memory): the sweeps already wrote the rows to
+// the host; a slot whose rows are back to back is handed to the sink in
+// place, any other is packed on the host first.
 hbm_status stream_cycles(CtxImpl *c, int64_t n_cycles, int32_t chunk_cycles, size_t chunk_bytes,
                          hbm_snapshot_sink sink, void *user)
 {
-    if (!c->copy_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+    const bool host = c->snaps_host;
+    if (!host && !c->copy_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
     for (int b = 0; b < 2; ++b) {
         if (!c->swept[b]) HIPCHK(c, hipEventCreateWithFlags(&c->swept[b], hipEventDisableTiming));
-        if (!c->copied[b]) HIPCHK(c, hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming));
+        if (!host && !c->copied[b]) HIPCHK(c, hipEventCreateWithFlags(&c->copied[b], hipEventDisableTiming));
     }
     void *staging[2] = {nullptr, nullptr};
-    for (int b = 0; b < 2; ++b)
-        if (chunk_bytes > 0 && hipHostMalloc(&staging[b], chunk_bytes, hipHostMallocDefault) != hipSuccess) {
-            if (staging[0]) (void)hipHostFree(staging[0]);
-            return fail(c, HBM_ENOMEM, "hipHostMalloc: snapshot staging");
-        }
+    std::vector<char> packed;               // host ring: rows of a slot that are not back to back
+    if (!host)
+        for (int b = 0; b < 2; ++b)
+            if (chunk_bytes > 0 && hipHostMalloc(&staging[b], chunk_bytes, hipHostMallocDefault) != hipSuccess) {
+                if (staging[0]) (void)hipHostFree(staging[0]);
+                return fail(c, HBM_ENOMEM, "hipHostMalloc: snapshot staging");
+            }
     std::vector<ChunkPiece> pieces[2];
     hbm_status st = set_snap_ring(c, 1);
     bool stop = false;
     const int64_t n_chunks = (n_cycles + chunk_cycles - 1) / chunk_cycles;
-    // hands chunk q's rows to the sink once its copy has landed
+    // hands chunk q's rows to the sink once they have landed
     auto deliver = [&](int64_t q) -> hbm_status {
         const int b = static_cast<int>(q & 1);
-        HIPCHK(c, hipEventSynchronize(c->copied[b]));
-        for (const ChunkPiece &pc : pieces[b])
-            if (!stop && sink(user, pc.slot, pc.first, pc.count, static_cast<char *>(staging[b]) + pc.offset,
-                              static_cast<int64_t>(pc.bytes)) != 0)
-                stop = true;
+        HIPCHK(c, hipEventSynchronize(host ? c->swept[b] : c->copied[b]));
+        for (const ChunkPiece &pc : pieces[b]) {
+            if (stop) break;
+            const void *rows = nullptr;
+            if (!host) {
+                rows = static_cast<char *>(staging[b]) + pc.offset;
+            } else {
+                const Slot &sl = c->slots[pc.slot];
+                const int64_t ring = pc.first % sl.snap_cap;
+                const size_t row_bytes = static_cast<size_t>(c->d) * sl.n * c->esize;
+                const char *base = static_cast<const char *>(c->buf.chi_samples);
+                if (sl.n == c->cap && ring + pc.count <= sl.snap_cap) {
+                    rows = base + static_cast<size_t>(ring) * row_bytes;
+                } else {
+                    packed.resize(pc.bytes);
+                    for (int64_t r = 0; r < pc.count; ++r)
+                        for (int j = 0; j < c->d; ++j) {
+                            const int64_t rr = (pc.first + r) % sl.snap_cap;
+                            std::memcpy(packed.data() + (static_cast<size_t>(r) * c->d + j) * sl.n * c->esize,
+                                        base + ((static_cast<size_t>(rr) * c->d + j) * c->cap + sl.obj_start) *
+                                                   c->esize,
+                                        sl.n * c->esize);
+                        }
+                    rows = packed.data();
+                }
+            }
+            if (sink(user, pc.slot, pc.first, pc.count, rows, static_cast<int64_t>(pc.bytes)) != 0) stop = true;
+        }
         pieces[b].clear();
         return HBM_OK;
     };
     for (int64_t q = 0; q < n_chunks && st == HBM_OK && !stop; ++q) {
         const int b = static_cast<int>(q & 1);
         const int64_t len = std::min<int64_t>(chunk_cycles, n_cycles - q * chunk_cycles);
-        // the rows chunk q - 2 left in the ring must be copied before this chunk overwrites them
-        if (q >= 2) HIPCHK(c, hipStreamWaitEvent(c->stream, c->copied[b], 0));
+        // device ring: the rows chunk q - 2 left must be copied before this chunk
+        // overwrites them (host ring: they were delivered before this chunk was issued)
+        if (!host && q >= 2) HIPCHK(c, hipStreamWaitEvent(c->stream, c->copied[b], 0));
         std::vector<int64_t> k0(c->n_slots);
         for (int32_t j = 0; j < c->n_slots; ++j) k0[j] = c->slots[j].k;
         if ((st = issue_cycles(c, len, true)) != HBM_OK) break;
         for (Slot &sl : c->slots) after_theta_steps(sl, cycles_taken(sl, len));
         HIPCHK(c, hipEventRecord(c->swept[b], c->stream));
         if (q >= 1 && (st = deliver(q - 1)) != HBM_OK) break;
-        // this chunk's snapshots, slot by slot, into staging[b]
-        HIPCHK(c, hipStreamWaitEvent(c->copy_stream, c->swept[b], 0));
+        // this chunk's snapshots, slot by slot
+        if (!host) HIPCHK(c, hipStreamWaitEvent(c->copy_stream, c->swept[b], 0));
         size_t off = 0;
         for (int32_t j = 0; j < c->n_slots; ++j) {
             const Slot &sl = c->slots[j];
@@ -1063,8 +1114,9 @@ hbm_status stream_cycles(CtxImpl *c, int64_t n_cycles, int32_t chunk_cycles, siz
             if (end <= first) continue;
             const size_t row_bytes = static_cast<size_t>(c->d) * sl.n * c->esize;
             pieces[b].push_back(ChunkPiece{j, first, end - first, off, static_cast<size_t>(end - first) * row_bytes});
+            if (host) continue;
             for (int64_t r = first; r < end;) {
-                // a run of consecutive ring rows: one strided copy of its d x N blocks
+                // a run of consecutive ring rows: one copy of its d x N blocks
                 const int64_t ring = r % sl.snap_cap;
                 const int64_t run = std::min<int64_t>(end - r, sl.snap_cap - ring);
                 const char *src = static_cast<const char *>(c->buf.chi_samples) +
@@ -1081,16 +1133,17 @@ hbm_status stream_cycles(CtxImpl *c, int64_t n_cycles, int32_t chunk_cycles, siz
                 r += run;
             }
         }
-        HIPCHK(c, hipEventRecord(c->copied[b], c->copy_stream));
+        if (!host) HIPCHK(c, hipEventRecord(c->copied[b], c->copy_stream));
         if (q == n_chunks - 1 || stop) st = deliver(q);
     }
     hbm_status st2 = HBM_OK;
     {
-        hipError_t e1 = hipStreamSynchronize(c->copy_stream), e2 = hipStreamSynchronize(c->stream);
+        hipError_t e1 = host ? hipSuccess : hipStreamSynchronize(c->copy_stream);
+        hipError_t e2 = hipStreamSynchronize(c->stream);
         if (e1 != hipSuccess) st2 = hip_fail(c, e1, "copy stream");
         else if (e2 != hipSuccess) st2 = hip_fail(c, e2, "stream");
     }
-    if (st2 == HBM_OK && (st2 = set_snap_ring(c, 0)) != HBM_OK) {}
+    if (st2 == HBM_OK) st2 = set_snap_ring(c, 0);
     for (void *p : staging)
         if (p) (void)hipHostFree(p);
     if (st != HBM_OK) return st;
@@ -1438,7 +1491,7 @@ hbm_status get_samples(hbm_ctx *ctx, int32_t slot, int64_t first, int64_t count,
                 const char *src = static_cast<const char *>(c->buf.chi_samples) +
                                   pitch * static_cast<size_t>(first * c->d) + c->esize * sl.obj_start;
                 HIPCHK(c, hipMemcpy2D(chi_out, w, src, pitch, w, static_cast<size_t>(count * c->d),
-                                      hipMemcpyDeviceToHost));
+                                      hipMemcpyDefault));
             }
         }
         if (n_written) *n_written = count;

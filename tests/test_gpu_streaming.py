@@ -8,6 +8,8 @@ taken, through a small device ring).
 * a pool streams each resident job's snapshots (jobs admitted at different
   sweeps, one stopped by its budget mid-chunk) equal to each job run alone;
 * the library's file-descriptor sink writes the same rows to a file;
+* a ring in pinned host memory (the sweep writes the snapshots through its
+  device mapping) streams the same rows, with no copies;
 * the sink can stop a run; a ring smaller than two chunks is refused.
 """
 import sys
@@ -112,3 +114,27 @@ def test_file_sink(hbm, tmp_path):
     assert np.array_equal(got, ref)
     full.close()
     s.close()
+
+
+@pytest.mark.parametrize("make,thin,chunk,m", [
+    (lambda: synth.gamma_lf_1d(n=5000, seed=99, fth=389.75), 3, 16, 200),
+    (lambda: synth.normal_normal_3d(n=700, seed=100), 5, 21, 160),
+])
+def test_host_ring(hbm, make, thin, chunk, m):
+    wl = make()
+    ring = 2 * (-(-chunk // thin))
+    full = hbm.Sampler(wl, max_cycles=m, thin=thin)
+    full.run_cycles(m)
+    ref = full.chi_snapshots(0, m // thin)
+    hs = hbm.Sampler(wl, max_cycles=m, thin=thin, snap_rows=ring, snap_host=True)
+    assert not hs.snaps.is_cuda and hs.snaps.is_pinned()
+    got = hs.run_streamed(m, chunk)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(hs.theta_trace(), full.theta_trace())
+    full.close()
+    hs.close()
+    # a plain run with the host buffer keeps the first rows, read back by get_samples
+    hp = hbm.Sampler(wl, max_cycles=m, thin=thin, snap_host=True)
+    hp.run_cycles(m)
+    assert np.array_equal(hp.chi_snapshots(0, m // thin), ref)
+    hp.close()
