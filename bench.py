@@ -184,11 +184,16 @@ def bench_batch(args, torch, synth, hbm):
     trial = 64
     total = 3 * (32 + trial) + args.warmup + 2 * args.steps
     b = hbm.Batch(wls, device="cuda:0", max_cycles=total)
-    pick, us = b.autotune(trial)
-    b.run_cycles(args.warmup)
+    use_graph = not args.no_graph
+    if args.launch_shape == "auto":
+        pick, us = b.autotune(trial)
+    else:
+        pick, us = int(args.launch_shape), [None, None, None]
+        b.set_launch(pick)
+    b.run_cycles(args.warmup, use_graph=use_graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.run_cycles(args.steps)
+    b.run_cycles(args.steps, use_graph=use_graph)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     hbm.kernel_timing(b.ctx, True)
@@ -223,7 +228,7 @@ def bench_batch(args, torch, synth, hbm):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (256 seeded gamma-LF catalogs, N log-uniform on [1e3, 1e5])",
         "config": {"workload": "gamma_lf_batch256", "n_datasets": 256, "n_objects_total": n_tot,
-                   "job_sweeps": args.job_sweeps, "graph": True, "tiles_per_workgroup": pick},
+                   "job_sweeps": args.job_sweeps, "graph": use_graph, "tiles_per_workgroup": pick},
         "jobs_per_hour": jobs_h, "sequential_jobs_per_hour": jobs_h_seq, "batch_speedup": jobs_h / jobs_h_seq,
         "sequential_ms_per_cycle_sum": 1e3 * seq,
         "autotune_us_per_cycle": {"1": us[0], "2": us[1], "4": us[2]},

@@ -132,6 +132,14 @@ __device__ __forceinline__ double accept_prob(double delta) { return delta >= 0.
 // result is always positive definite because 1 + beta >= 1 - alpha* > 0.
 // L is packed lower, row-major: element (r, c) at r (r + 1) / 2 + c.
 // ---------------------------------------------------------------------------
+// FP32 factors take the hardware square root and reciprocal (within 1 ulp;
+// the correctly rounded library forms cost ~20 and ~10 instructions each);
+// FP64 factors keep the correctly rounded forms.
+__device__ __forceinline__ float ram_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ double ram_sqrt(double v) { return sqrt(v); }
+__device__ __forceinline__ float ram_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double ram_rcp(double v) { return 1.0 / v; }
+
 template <typename T, int D>
 __device__ __forceinline__ void chol_rank1(T *L, T *x, T beta)
 {
@@ -140,9 +148,9 @@ __device__ __forceinline__ void chol_rank1(T *L, T *x, T beta)
         const int jj = j * (j + 1) / 2 + j;
         const T ljj = L[jj];
         const T xj = x[j];
-        const T r = sqrt(ljj * ljj + beta * xj * xj);
-        const T inv_r = static_cast<T>(1) / r;
-        const T ratio = xj / ljj;
+        const T r = ram_sqrt(ljj * ljj + beta * xj * xj);
+        const T inv_r = ram_rcp(r);
+        const T ratio = xj * ram_rcp(ljj);
 #pragma unroll
         for (int i = j + 1; i < D; ++i) {
             const int ij = i * (i + 1) / 2 + j;
@@ -161,14 +169,14 @@ template <typename T, int D>
 __device__ __forceinline__ void ram_adapt(T *S, const T *U, T c)
 {
     if (D == 1) {
-        S[0] = S[0] * sqrt(static_cast<T>(1) + c);
+        S[0] = S[0] * ram_sqrt(static_cast<T>(1) + c);
         return;
     }
     T n2 = 0;
 #pragma unroll
     for (int j = 0; j < D; ++j) n2 += U[j] * U[j];
     if (!(n2 > static_cast<T>(0))) return;
-    const T inv_n = static_cast<T>(1) / sqrt(n2);
+    const T inv_n = ram_rcp(ram_sqrt(n2));
     T v[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -185,13 +193,16 @@ __device__ __forceinline__ void ram_adapt(T *S, const T *U, T c)
 // workgroup adds its four wave sums in fixed order.  The result depends only
 // on the values and their lane positions, never on timing.
 // ---------------------------------------------------------------------------
-// One DPP move of a double (both 32-bit halves), all rows and banks enabled.
-template <int kCtrl>
+// One DPP move of a double (both 32-bit halves) into the rows of kRowMask.
+// Lanes of other rows keep whatever their destination register held: callers
+// read only lanes of enabled rows.  The quad permutations and row rotations
+// used here take every lane's source from an active lane of its own row.
+template <int kCtrl, int kRowMask = 0xf>
 __device__ __forceinline__ double dpp_f64(double v)
 {
     const uint64_t bits = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits & 0xffffffffu), kCtrl, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(bits >> 32), kCtrl, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(bits & 0xffffffffu), kCtrl, kRowMask, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(bits >> 32), kCtrl, kRowMask, 0xf, false);
     return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
                                           static_cast<uint32_t>(lo));
 }
@@ -205,16 +216,20 @@ __device__ __forceinline__ double lane_f64(double v, int lane)
 }
 
 // Wavefront sum in a fixed order: within each quad (DPP quad_perm swaps),
-// then across the four quads of each 16-lane row (DPP row rotations), then
-// the four row sums read from lanes 0, 16, 32, 48 and added pairwise.  The
-// value read from each row's lane 0 is ((q0 + q1) + (q2 + q3)) of its quads.
+// then across the four quads of each 16-lane row (DPP row rotations), which
+// leaves every lane of a row holding that row's sum; then row broadcasts:
+// lane 15 of rows 0 and 2 is added into rows 1 and 3, lane 31 into rows 2
+// and 3 (row 2's lanes are not read).  Lane 63 ends with (r3 + r2) + (r1 +
+// r0) of the row sums, read once.
 __device__ __forceinline__ double wave_sum(double v)
 {
     v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
     v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
     v += dpp_f64<0x124>(v);   // row_ror:4
     v += dpp_f64<0x128>(v);   // row_ror:8
-    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+    v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return lane_f64(v, 63);
 }
 
 // Sums NV values over the workgroup; result valid in thread 0.
