@@ -100,7 +100,30 @@ def measured_traffic(workload: str, n: int):
         return None
     fetch = float(vals["fetch_bytes_per_launch"]) / float(vals["copy_fetch_scale"])
     write = float(vals["write_bytes_per_launch"]) / float(vals["copy_write_scale"])
-    return {"bytes_per_launch": fetch + write, "source": os.path.relpath(path, ROOT)}
+    out = {"bytes_per_launch": fetch + write, "source": os.path.relpath(path, ROOT)}
+    if "valu_wave_instructions_per_launch" in vals:
+        out["valu_wave_instructions"] = float(vals["valu_wave_instructions_per_launch"])
+    return out
+
+
+# VALU issue capacity: each of the 1024 SIMDs (256 CUs x 4) issues one wave64
+# instruction every 4 cycles (16 lanes per cycle) at 2.4 GHz, i.e. 64 lane
+# operations per CU per cycle.
+SIMDS, VALU_CYCLES_PER_WAVE_INSTR, CLOCK_HZ = 1024, 4, 2.4e9
+VALU_PEAK_TOPS = 256 * 64 * CLOCK_HZ / 1e12
+
+
+def valu_roof(traffic, kern_ms):
+    """VALU issue figures of the sweep kernel from the counter summary's
+    SQ_INSTS_VALU, or None without one."""
+    if not traffic or "valu_wave_instructions" not in traffic or not kern_ms:
+        return None
+    wi = traffic["valu_wave_instructions"]
+    t_issue = wi * VALU_CYCLES_PER_WAVE_INSTR / (SIMDS * CLOCK_HZ)
+    achieved = wi * 64 / (kern_ms * 1e-3) / 1e12
+    return {"wave_instructions_per_launch": wi, "issue_time_us": 1e6 * t_issue,
+            "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "T lane-instructions/s",
+            "frac": achieved / VALU_PEAK_TOPS}
 
 
 def accuracy_vs_oracle(wl, s, o):
@@ -222,6 +245,21 @@ def bench_batch(args, torch, synth, hbm):
     jobs_h_seq = 256 * 3600.0 / (args.job_sweeps * seq)
     bpu = BYTES_PER_UPDATE["gamma_lf_1d"]
     achieved = bpu * n_tot / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    traffic = measured_traffic("gamma_lf_batch256", n_tot)
+    valu = valu_roof(traffic, kern_ms)
+    hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+           "traffic": (traffic["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9) if traffic else None,
+           "traffic_bytes_per_launch": traffic["bytes_per_launch"] if traffic else None,
+           "algorithmic_bytes_per_launch": bpu * n_tot, "bytes_per_update": bpu}
+    if valu is not None:
+        # the sweep issues VALU instructions at the SIMDs' rate: that is its roof
+        roof = {"bound": "alu", "achieved": valu["achieved"], "peak": valu["peak"], "unit": valu["unit"],
+                "frac": valu["frac"], "traffic": hbm["traffic"], "valu": valu, "hbm": hbm}
+    else:
+        roof = dict(hbm, traffic_source="no counter summary for the current kernel sources")
+    roof.update({"kernel": "sweep_kernel<gamma_lf_1d, dataset table>", "launches_timed": n_launch,
+                 "kernel_ms": kern_ms})
     out = {
         "metric": METRIC, "value": n_tot * args.steps / wall, "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_cycle, "higher_is_better": True,
@@ -232,10 +270,7 @@ def bench_batch(args, torch, synth, hbm):
         "jobs_per_hour": jobs_h, "sequential_jobs_per_hour": jobs_h_seq, "batch_speedup": jobs_h / jobs_h_seq,
         "sequential_ms_per_cycle_sum": 1e3 * seq,
         "autotune_us_per_cycle": {"1": us[0], "2": us[1], "4": us[2]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
-                     "kernel": "sweep_kernel<gamma_lf_1d>", "bytes_per_update": bpu, "launches_timed": n_launch,
-                     "kernel_ms": kern_ms},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(wls, args.cpu_seconds)
@@ -610,7 +645,7 @@ def main():
                      "algorithmic_bytes_per_launch": bpu * wl.n, "traffic_source": traffic["source"] if traffic else
                      "no counter summary for the current kernel sources",
                      "kernel": f"sweep_kernel<{wl.name}>", "bytes_per_update": bpu,
-                     "launches_timed": n_launch},
+                     "launches_timed": n_launch, "valu": valu_roof(traffic, kern_ms)},
         "accept_rate_last_sweep": stats["n_acc"] / wl.n,
         "theta_last": th[-1].tolist(),
     }
