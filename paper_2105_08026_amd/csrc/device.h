@@ -33,8 +33,9 @@ __device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
         // one 32x32 -> 64-bit multiply each (a single v_mad_u64_u32)
         const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
         const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-        const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ key0;
-        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ key1;
+        // three-way XORs: one v_bitop3_b32 each (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pb >> 32), c1, key0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(pa >> 32), c3, key1, 0x96);
         c0 = n0;
         c1 = static_cast<uint32_t>(pb);
         c2 = n2;
@@ -71,6 +72,45 @@ __device__ __forceinline__ T uniform24(const Block4 &b, int j)
 // instruction), v_log_f32 is log2.  The per-object log densities keep the
 // correctly rounded library functions.
 __device__ __forceinline__ float ln_fast(float u) { return __builtin_amdgcn_logf(u) * 0.693147180559945309f; }
+
+// exp and expm1 in single precision for the per-object log densities.  Both
+// reduce x = k ln 2 + r with k = rint(x log2 e).  exp: 2^k times the hardware
+// exp2 of (x log2 e - k), the product carried in two parts (log2 e split into
+// its float value and the float of the remainder), ~1 ulp.  expm1: 2^k
+// (expm1(r) + 1) - 1 = fma(2^k, expm1(r), 2^k - 1) with r = x - k ln 2 (ln 2
+// in two parts) and expm1(r) from its Taylor series through r^7 (|r| <=
+// ln 2 / 2: truncation below 2e-8 relative), so small arguments keep full
+// relative accuracy.  Arguments are first clamped (one v_med3) to where the
+// reductions stay exact: exp gives 0 below -104 and +inf above 88.73, expm1
+// gives -1 below -88 and a finite 1.65e38 above 88; no other special cases.
+__device__ __forceinline__ float exp_fin(float x)
+{
+    constexpr float kL2e = 1.44269504088896341f;
+    constexpr float kL2eLo = 1.92596299e-08f;        // log2 e - kL2e
+    x = __builtin_amdgcn_fmed3f(x, -104.0f, 89.0f);
+    const float ph = x * kL2e;
+    const float pl = fmaf(x, kL2eLo, fmaf(x, kL2e, -ph));
+    const float k = __builtin_rintf(ph);
+    return ldexpf(__builtin_amdgcn_exp2f((ph - k) + pl), static_cast<int>(k));
+}
+
+__device__ __forceinline__ float expm1_fin(float x)
+{
+    constexpr float kL2e = 1.44269504088896341f;
+    constexpr float kLn2Hi = 0.693145751953125f;     // ln 2 to 16 significant bits
+    constexpr float kLn2Lo = 1.42860682e-06f;        // ln 2 - kLn2Hi
+    x = __builtin_amdgcn_fmed3f(x, -88.0f, 88.0f);
+    const float k = __builtin_rintf(x * kL2e);
+    const float r = fmaf(-k, kLn2Lo, fmaf(-k, kLn2Hi, x));
+    float q = fmaf(r, 1.0f / 5040.0f, 1.0f / 720.0f);
+    q = fmaf(r, q, 1.0f / 120.0f);
+    q = fmaf(r, q, 1.0f / 24.0f);
+    q = fmaf(r, q, 1.0f / 6.0f);
+    q = fmaf(r, q, 0.5f);
+    const float p = fmaf(r * r, q, r);
+    const float t = ldexpf(1.0f, static_cast<int>(k));
+    return fmaf(t, p, t - 1.0f);
+}
 
 template <typename T, int NZ>
 __device__ __forceinline__ void normals(const Block4 &b, T *z);

@@ -337,8 +337,8 @@ struct LF1D {
     {
         Eval<T> e;
         e.q = (x[0] - kc[1]) - kc[2];
-        e.eq = expf(e.q);
-        const float z = -o.a * expm1f((x[0] - o.c) - o.e);
+        e.eq = exp_fin(e.q);
+        const float z = -o.a * expm1_fin((x[0] - o.c) - o.e);
         const float lm = -0.5f * z * z;
         const float g = kc[0] * e.q - e.eq;
         e.lpv = lm + g;
@@ -446,10 +446,10 @@ struct LF3D {
     {
         Eval<T> e;
         e.q = (x[0] - kc[1]) - kc[2];
-        e.eq = expf(e.q);
+        e.eq = exp_fin(e.q);
         const float d0 = x[0] - o.c1, d1 = x[1] - o.c2;
-        const float zF = -o.a * expm1f((d0 - 2.0f * d1) - o.e1);
-        const float zr = -s.mf[0] * expm1f(d1 - o.e2);
+        const float zF = -o.a * expm1_fin((d0 - 2.0f * d1) - o.e1);
+        const float zr = -s.mf[0] * expm1_fin(d1 - o.e2);
         const float zc = (x[2] - o.ch) * s.mf[1];
         const float lm = -0.5f * (zF * zF + zr * zr + zc * zc);
         // colour residual c - a - b ln L around the object's centre: the
