@@ -353,7 +353,7 @@ def bench_serving(args, torch, synth, hbm):
 # counters of the marginal bench command, per launch, divided by N x theta
 # rows (theta near the truth; the count depends on how many objects need the
 # region below the datum).
-FLOPS_PER_INTEGRAL = {"marginal_gamma_lf_1d": 8262, "marginal_bb1_lf": 55725, "marginal_normal_normal_1d": 3318}
+FLOPS_PER_INTEGRAL = {"marginal_gamma_lf_1d": 8250, "marginal_bb1_lf": 55670, "marginal_normal_normal_1d": 3310}
 FP64_PEAK_TFLOPS = 78.6
 NODES_PER_OBJECT = {"marginal_gamma_lf_1d": 216, "marginal_bb1_lf": 216, "marginal_normal_normal_1d": 48}
 
