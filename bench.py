@@ -530,8 +530,9 @@ def bench_streaming(args, torch, synth, hbm):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sampler's multi-GPU sharding is "
-              "described in DESIGN.md and not launched here", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding a catalog's objects over "
+              "several GPUs (one all-gather of tile partials per cycle) is a design, not launched here",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
