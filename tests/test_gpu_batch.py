@@ -182,6 +182,37 @@ def test_launch_shape_does_not_change_the_chain(hbm, make):
         s.close()
 
 
+def test_full_batch_sampled_datasets(hbm):
+    """The 256-catalog batch at its full size (sum N ~ 6e6), autotuned and
+    graph-replayed as the bench runs it: the smallest, the largest and a
+    middle dataset equal, bit for bit, the same datasets run alone, and the
+    largest one's population log-likelihood matches the oracle at the batch's
+    latents."""
+    wls = synth.gamma_lf_batch(256)
+    ns = np.array([w.n for w in wls])
+    _say(f"full batch: 256 datasets, sum N = {ns.sum()}")
+    trial, cycles = 8, 30
+    total = 3 * (32 + trial) + cycles
+    b = hbm.Batch(wls, max_cycles=total)
+    pick, _ = b.autotune(trial)
+    b.run_cycles(cycles)
+    picks = sorted({int(np.argmin(ns)), int(np.argmax(ns)), int(np.argsort(ns)[len(ns) // 2])})
+    for j in picks:
+        _say(f"  dataset {j}: N = {wls[j].n}, shape {pick}")
+        tr, chi = _alone(hbm, wls[j], total)
+        assert np.array_equal(b.theta_trace(j), tr), j
+        assert np.array_equal(b.latents(j), chi), j
+    j = int(np.argmax(ns))
+    th = np.array([w.theta_true for w in wls])
+    got = b.pop_loglik(th)
+    o = oracle.Oracle(wls[j])
+    chi = b.latents(j)
+    ref = o.pop_loglik(th[j], chi)
+    scale = np.sum(np.abs(o.pop_terms(th[j], chi)))
+    assert abs(got[j] - ref) <= 1e-6 * scale + 1e-12 * wls[j].n, (got[j], ref)
+    b.close()
+
+
 def test_autotune_batch_keeps_chains(hbm):
     wls = _lf_set(5, 1300, 300, 4000)
     _say(f"autotune on a batch N={[w.n for w in wls]}")

@@ -126,6 +126,24 @@ def test_lf1d_full_catalog_lockstep_after_graph_cycles(hbm):
     assert np.all(np.isfinite(th))
 
 
+def test_lf3d_full_catalog_lockstep_after_graph_cycles(hbm):
+    """The 3-D colour catalog at its full size (N = 10^6) in the launch shape
+    the bench picks: autotuned burn-in and graph-replayed cycles, then whole
+    sweeps in lockstep with the oracle (every object checked)."""
+    _say("lf3d full catalog N=1000000: autotune + 100 graph cycles, then 2 lockstep steps")
+    wl = synth.gamma_lf_3d()
+    s = hbm.Sampler(wl, max_cycles=3 * (32 + 16) + 110)
+    pick, _ = s.autotune(16)
+    _say(f"  launch shape: {pick} tile(s) per workgroup")
+    s.run_cycles(100, use_graph=True)
+    o = oracle.Oracle(wl)
+    for _ in range(2):
+        r = lockstep_step(s, o, "f32")
+        _say(f"  lp err {max(r.max_rel_lpx, r.max_rel_lpy):.2e} chol {r.max_chol_rel:.2e} near-ties {r.near_ties}")
+    assert np.all(np.isfinite(s.theta_trace()))
+    s.close()
+
+
 @pytest.mark.parametrize("make", [lambda: synth.normal_normal_1d(n=1000),
                                   lambda: synth.gamma_lf_1d(n=5000, seed=53, fth=389.75),
                                   lambda: synth.gamma_lf_3d(n=2000, seed=54, fth=389.75),
