@@ -51,6 +51,22 @@ def test_bb1_lockstep(hbm, n):
                  f"dtheta {r.theta_delta_gpu - r.theta_delta_orc:.2e}")
 
 
+def test_bb1_full_catalog_lockstep_after_graph_cycles(hbm):
+    """The case-study catalog at its full size (N = 10^5) in the bench's launch
+    shape: autotuned burn-in and graph-replayed cycles, then whole sweeps in
+    lockstep with the oracle."""
+    wl = synth.bb1_lf(n=100_000)
+    _say(f"bb1 full catalog N={wl.n}: autotune + 100 graph cycles, then 3 lockstep steps")
+    s = hbm.Sampler(wl, max_cycles=3 * (32 + 16) + 110)
+    pick, _ = s.autotune(16)
+    s.run_cycles(100, use_graph=True)
+    o = oracle.Oracle(wl)
+    for _ in range(3):
+        r = lockstep_step(s, o, "f32")
+        _say(f"  shape {pick}: lp err {max(r.max_rel_lpx, r.max_rel_lpy):.2e} near-ties {r.near_ties}")
+    s.close()
+
+
 def test_bb1_pop_loglik(hbm):
     wl = synth.bb1_lf(n=4000, seed=62, chunk=1_000_000)
     _say(f"bb1 pop_loglik N={wl.n}")

@@ -119,6 +119,22 @@ def test_full_size_gamma_lf_sampled(hbm):
     s.close()
 
 
+def test_full_size_bb1_sampled(hbm):
+    wl = synth.bb1_lf(n=100_000)
+    _say(f"marginal full size BB1 N={wl.n}")
+    s = hbm.Sampler(wl, max_cycles=4)
+    th = np.array(wl.theta_true, dtype=np.float64)
+    out, terms = s.marginal_loglik(th, terms=True)
+    rng = np.random.default_rng(6)
+    idx = np.sort(np.concatenate([rng.choice(wl.n, 600, replace=False), np.arange(wl.n - 40, wl.n)]))
+    ref = oracle.Oracle(_subset(wl, idx)).marginal_terms(th)
+    err = np.max(np.abs(terms[0][idx] - ref))
+    _say(f"  sampled {len(idx)} objects: max |term - oracle| = {err:.2e}")
+    assert err < TERM_TOL
+    assert np.all(np.isfinite(terms[0]))
+    s.close()
+
+
 def test_theta_rows_are_independent_and_deterministic(hbm):
     wl = synth.bb1_lf(n=5000, seed=74, chunk=1_000_000)
     s = hbm.Sampler(wl, max_cycles=4)
