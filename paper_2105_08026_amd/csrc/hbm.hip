@@ -98,6 +98,10 @@ struct CtxImpl {
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t graph_len = 0;
+    // launch extent of the cycle kernels in a multi-slot context: side and
+    // epilogue workgroups for slots [0, ext_slots), tile workgroups for tiles
+    // [0, ext_tiles), up to the last loaded slot and occupied tile
+    int32_t ext_slots = 1, ext_tiles = 0;
     // latent snapshots: the pointer kernels write through (chi_samples, or its
     // device mapping when the caller gave pinned host memory)
     void *snaps_dev = nullptr;
@@ -204,11 +208,15 @@ struct Ops {
         a.tile_ds = c->tile_ds;
         a.n_total = c->cap;
         a.n_tiles_total = c->n_tiles;
-        a.n_ds = c->n_slots;
+        // a multi-slot context launches only up to its last loaded slot and
+        // occupied tile: the workgroups beyond would find nothing to do
+        const bool whole = single(c);
+        a.n_ds = whole ? c->n_slots : c->ext_slots;
+        const int32_t n_t = whole ? c->n_tiles : c->ext_tiles;
         a.nq = c->nq;
         // traced sweeps (a checking aid) always take one tile per workgroup
         const int tpw = trace ? 1 : c->tpw;
-        const dim3 grid(static_cast<unsigned>(c->n_slots + (c->n_tiles + tpw - 1) / tpw));
+        const dim3 grid(static_cast<unsigned>(a.n_ds + (n_t + tpw - 1) / tpw));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (c->timing) {
             // the runtime takes both timestamps from the dispatch itself
@@ -241,12 +249,12 @@ struct Ops {
         if (full && one)
             hipLaunchKernelGGL((epilogue_kernel<M, true, true, kStats>), dim3(1), dim3(kBlock), 0, c->stream, e);
         else if (full)
-            hipLaunchKernelGGL((epilogue_kernel<M, true, false, kStats>), dim3(c->n_slots), dim3(kBlock), 0,
+            hipLaunchKernelGGL((epilogue_kernel<M, true, false, kStats>), dim3(c->ext_slots), dim3(kBlock), 0,
                                c->stream, e);
         else if (one)
             hipLaunchKernelGGL((epilogue_kernel<M, false, true, kStats>), dim3(1), dim3(kBlock), 0, c->stream, e);
         else
-            hipLaunchKernelGGL((epilogue_kernel<M, false, false, kStats>), dim3(c->n_slots), dim3(kBlock), 0,
+            hipLaunchKernelGGL((epilogue_kernel<M, false, false, kStats>), dim3(c->ext_slots), dim3(kBlock), 0,
                                c->stream, e);
         LAUNCHCHK(c, "epilogue_kernel");
         return HBM_OK;
@@ -641,6 +649,23 @@ hbm_status drop_graph(CtxImpl *c)
     return HBM_OK;
 }
 
+// Recomputes the launch extent of a multi-slot context from its loaded
+// slots; a captured graph holds the extent, so it is dropped on a change.
+hbm_status update_extent(CtxImpl *c)
+{
+    int32_t es = 1, et = 0;
+    for (int32_t j = 0; j < c->n_slots; ++j) {
+        const Slot &sl = c->slots[j];
+        if (!sl.loaded) continue;
+        es = j + 1;
+        et = std::max(et, sl.tile_start + sl.n_tiles);
+    }
+    if (es == c->ext_slots && et == c->ext_tiles) return HBM_OK;
+    c->ext_slots = es;
+    c->ext_tiles = et;
+    return drop_graph(c);
+}
+
 hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, void *hip_stream, CtxImpl **out)
 {
     ModelInfo mi;
@@ -874,7 +899,7 @@ hbm_status load(CtxImpl *c, int32_t count, const int32_t *slots, const int64_t *
         sl.snap_cap = hs[q].snap_cap;
         sl.thin = hs[q].thin;
     }
-    return HBM_OK;
+    return update_extent(c);
 }
 
 // Theta steps a slot takes in n more full cycles.
@@ -1187,7 +1212,7 @@ hbm_status unload_dataset(hbm_ctx *ctx, int32_t slot)
         if ((s = put_field<int32_t>(c, slot, offsetof(CycleState, active), 0)) != HBM_OK) return s;
         sl = Slot{};
         if (c->n_slots == 1 && (s = drop_graph(c)) != HBM_OK) return s;
-        return HBM_OK;
+        return update_extent(c);
     });
 }
 
