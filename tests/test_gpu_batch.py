@@ -137,6 +137,32 @@ def test_pool_jobs_match_alone_runs(hbm):
     pool.close()
 
 
+def test_pool_launch_extent_follows_the_last_job(hbm):
+    """Cycles launch only up to the last loaded slot and occupied tile: the
+    extent shrinks when the highest job retires and grows when a later job
+    lands beyond it; every job still equals its run alone."""
+    wls = [synth.gamma_lf_1d(n=n, seed=1500 + j, fth=FTH) for j, n in enumerate((3000, 1200, 2600, 5000))]
+    budgets = [72, 48, 16, 32]
+    pool = hbm.Pool(hbm.HBM_GAMMA_LF_1D, capacity=65536, n_slots=6, max_cycles=100)
+    sa, sb, sc = pool.admit(wls[:3], budgets[:3])
+    pool.run_cycles(16)                       # the third job (highest slot and tiles) finishes here
+    assert pool.finished() == [sc]
+    done = {2: (pool.retire(sc), None)}
+    pool.run_cycles(8)                        # extent: the first two jobs only
+    (sd,) = pool.admit([wls[3]], [budgets[3]])
+    pool.run_cycles(40)                       # extent grows again to the new job
+    for slot, j in ((sb, 1), (sd, 3)):
+        assert slot in pool.finished()
+        done[j] = (pool.retire(slot), None)
+    pool.run_cycles(16)
+    assert pool.finished() == [sa]
+    done[0] = (pool.retire(sa), None)
+    for j, w in enumerate(wls):
+        tr, _ = _alone(hbm, w, budgets[j])
+        assert np.array_equal(done[j][0], tr), j
+    pool.close()
+
+
 def test_pool_rejects_bad_loads(hbm):
     _say("pool: invalid placements and slots are rejected, the pool stays usable")
     w = synth.gamma_lf_1d(n=300, seed=3, fth=FTH)
