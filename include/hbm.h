@@ -21,7 +21,9 @@
  * `capacity` object positions.  A loaded slot holds one dataset (one
  * catalog with its own seed, theta chain and configuration) whose objects
  * occupy positions [obj_start, obj_start + N) of every buffer, obj_start a
- * multiple of 256.  Every launch advances all active slots together; a
+ * multiple of 256.  Every launch advances all active slots together,
+ * covering slots and 256-object tiles up to the last loaded slot and the
+ * last occupied tile (so placing datasets low keeps launches small); a
  * slot's chain is bit-identical to the same dataset run alone, wherever it
  * sits.  init_chains makes a one-slot pool (capacity N, obj_start 0), and the
  * functions below then behave as for a single dataset.  init_batch packs
