@@ -149,6 +149,21 @@ def accuracy_vs_oracle(wl, s, o):
             "theta": theta.tolist()}
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "logical_cpus_usable": usable}
+
+
 def cpu_baseline(wl, seconds: float, sampler=None):
     """The oracle as it stands, timed on the host on a bounded sample of the
     workload (and, given the GPU sampler, the accuracy of its results)."""
@@ -165,7 +180,8 @@ def cpu_baseline(wl, seconds: float, sampler=None):
         done += 5
     dt = time.perf_counter() - t0
     out = {"value": wl.n * done / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-           "sample": f"{done} full MWG cycles of the N={wl.n} catalog ({dt:.1f} s, FP64, OpenMP over objects)"}
+           "sample": f"{done} full MWG cycles of the N={wl.n} catalog ({dt:.1f} s, FP64, OpenMP over objects)",
+           "host": host_cpu()}
     # the same on one core, for a quarter of the time
     cores = oracle.num_threads()
     oracle.set_num_threads(1)
@@ -196,7 +212,8 @@ def cpu_baseline_batch(wls, seconds: float):
         used += 1
     dt = time.perf_counter() - t0
     return {"value": done_updates / dt, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"20 full MWG cycles of each of the first {used} datasets ({dt:.1f} s incl. setup, FP64)"}
+            "sample": f"20 full MWG cycles of each of the first {used} datasets ({dt:.1f} s incl. setup, FP64)",
+            "host": host_cpu()}
 
 
 def bench_batch(args, torch, synth, hbm):
@@ -379,7 +396,7 @@ def cpu_baseline_marginal(wl, theta, seconds: float):
     dt = time.perf_counter() - t0
     return {"value": m * done / dt, "unit": "object integrals/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} evaluations of the first {m} objects' marginal terms at one theta ({dt:.1f} s, FP64, "
-                      "one thread)"}
+                      "one thread)", "host": host_cpu()}
 
 
 def bench_marginal(args, torch, synth, hbm):
