@@ -558,9 +558,16 @@ static int cholesky_dense(int q, const double *mat, double *low)
 }
 
 /* S_n = chol(S (I + c U U^T / |U|^2) S^T), S dense lower q x q, in place.
- * A zero |U| leaves S unchanged. */
+ * For q = 1 the matrix U U^T / |U|^2 is 1 whatever the nonzero U, so
+ * S_n = S sqrt(1 + c); U = 0 (the variate map reaches it when u0 = 1) takes
+ * that same value, the limit of eq 2.6 as U -> 0.  For q > 1 the direction
+ * U / |U| has no limit at U = 0, and a zero |U| leaves S unchanged. */
 static void ram_adapt(int q, double *s_mat, const double *u, double cadapt)
 {
+    if (q == 1) {
+        s_mat[0] *= sqrt(1.0 + cadapt);
+        return;
+    }
     double nrm2 = 0.0;
     for (int j = 0; j < q; j++)
         nrm2 += u[j] * u[j];

@@ -64,8 +64,13 @@ def test_one_ram_step_algebra(oracle_lib, wl_fn):
         np.testing.assert_allclose(st.chi[:, i], y if acc else x, rtol=1e-14, atol=1e-14)
         n_acc += acc
         c = eta * (tr[i, 4] - wl.alpha_star)
-        target = s_old @ (np.eye(d) + c * np.outer(uvec, uvec) / uvec.dot(uvec)) @ s_old.T
         s_new = _packed_to_dense(st.chol, i, d)
+        if not uvec.dot(uvec) > 0.0:
+            # U = 0: the limit of eq 2.6 in 1-D, no change in more dimensions
+            want = s_old * math.sqrt(1 + c) if d == 1 else s_old
+            np.testing.assert_allclose(s_new, want, rtol=1e-14)
+            continue
+        target = s_old @ (np.eye(d) + c * np.outer(uvec, uvec) / uvec.dot(uvec)) @ s_old.T
         np.testing.assert_allclose(s_new, np.linalg.cholesky(target), rtol=1e-12, atol=1e-14)
         assert np.all(np.diag(s_new) > 0) and np.allclose(np.triu(s_new, 1), 0)
         # determinant identity of eq (2.6)
@@ -75,6 +80,40 @@ def test_one_ram_step_algebra(oracle_lib, wl_fn):
             assert s_new[0, 0] == pytest.approx(s_old[0, 0] * math.sqrt(1 + c), rel=1e-14)
     assert np.array_equal(st.acc - before.acc, (tr[:, 3] > 0).astype(np.uint32))
     assert 0 < n_acc < n
+
+
+def test_zero_proposal_direction_in_1d(oracle_lib):
+    """The 24-bit variate map reaches u0 = 1 (field 0xFFFFFF), where the
+    Box-Muller radius and so U are exactly 0.  Key 1 (the 300,000-object
+    luminosity-function catalog), object 153325, sweep 63 is such a draw.
+    There Y = X, so Delta = 0 and alpha = 1, and eq 2.6 in one dimension
+    gives the limit of chol(S (1 + c U^2 / U^2) S) as U -> 0: S sqrt(1 + c)
+    with c = eta_63 (1 - alpha*).  The limit is taken here from the matrix
+    definition itself at a tiny nonzero U (numpy's Cholesky), not from the
+    oracle's formula."""
+    i, k = 153325, 63
+    u, z = oracle_lib.variates(1, [i, k, 0, 0])
+    assert u[0] == 1.0 and z[0] == 0.0
+    wl = synth.gamma_lf_1d(n=i + 1, seed=1, fth=389.75)
+    o = oracle_lib.Oracle(wl)
+    st = o.initial_state(s0=0.3)
+    st.k = k - 1
+    x0 = st.chi[0, i]
+    tr = o.sweep(st, trace=True)
+    assert st.k == k
+    assert tr[i, 1] == tr[i, 0] and tr[i, 4] == 1.0          # Y = X: Delta = 0, alpha = 1
+    assert st.chi[0, i] == x0
+    c = (k + 1) ** (-2.0 / 3.0) * (1.0 - wl.alpha_star)
+    tiny = 1e-150
+    limit = np.linalg.cholesky(np.array([[0.3 * (1.0 + c * tiny * tiny / (tiny * tiny)) * 0.3]]))[0, 0]
+    assert st.chol[0, i] == pytest.approx(limit, rel=1e-15)
+    assert st.chol[0, i] == pytest.approx(0.3 * 1.01734, rel=1e-5)    # the 1.7 % step a skip would miss
+    # every other object of the sweep still follows the matrix definition
+    for j in (0, 1, i - 1):
+        _, zj = oracle_lib.variates(1, [j, k, 0, 0])
+        assert zj[0] != 0.0
+        cj = (k + 1) ** (-2.0 / 3.0) * (tr[j, 4] - wl.alpha_star)
+        assert st.chol[0, j] == pytest.approx(0.3 * math.sqrt(1.0 + cj), rel=1e-14)
 
 
 def _nn1_fixed_theta_run(oracle_lib, n_sweeps, thin):
