@@ -42,6 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # written; 3-D normal-normal (FP64): 24+48+4+24 read, 76 written.
 BYTES_PER_UPDATE = {"gamma_lf_1d": 36, "normal_normal_1d": 56, "gamma_lf_color_3d": 104, "normal_normal_3d": 176,
                     "bb1_lf": 36}
+# The same per-object state traffic as first planned: the latent, factor, a
+# cached log-likelihood and the accept counter read and written, plus the
+# data words read (FP32: 1-D 40 B, 3-D 100 B).  The kernels keep no cached
+# log-likelihood and read derived data instead, hence BYTES_PER_UPDATE.
+PLANNED_BYTES_PER_UPDATE = {"gamma_lf_1d": 40, "gamma_lf_color_3d": 100, "bb1_lf": 40}
 
 
 def parse():
@@ -61,7 +66,9 @@ def parse():
     ap.add_argument("--job-sweeps", type=int, default=2000, help="batch workload: sweeps that make one job")
     ap.add_argument("--n", type=int, default=None,
                     help="objects (default: 300,000; 1,000,000 for the 3-D catalog; 100,000 for BB1)")
-    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="plain launches (sweep + epilogue kernel per cycle)")
+    ap.add_argument("--graph-cycles", action="store_true",
+                    help="graph replays of the two-kernel cycle instead of the persistent launch")
     ap.add_argument("--launch-shape", default="auto", choices=["auto", "1", "2", "4"],
                     help="tiles per sweep workgroup; auto runs the autotuner during burn-in")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -74,11 +81,13 @@ def parse():
     ap.add_argument("--thetas", type=int, default=64,
                     help="marginal workloads: theta rows evaluated per call (one step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side-c2", action="store_true",
+                    help="skip the short 3-D colour catalog run (N = 10^6) reported beside the default workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ("device.h", "models.h", "kernels.h")
+KERNEL_SOURCES = ("device.h", "models.h", "kernels.h", "cycles.h")
 
 
 def kernel_source_digest() -> str:
@@ -90,11 +99,12 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, n: int):
-    """HBM bytes per sweep-kernel launch from the committed rocprofv3 counter
-    summary for this workload, or None when the summary is missing or was
-    taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"sweep_{workload}_n{n}_hbm_counters.md")
+def measured_traffic(workload: str, n: int, kernel: str = "sweep"):
+    """HBM bytes per cycle of the sweep kernel (kernel="sweep", one cycle per
+    launch) or of the persistent cycle kernel (kernel="cycles") from the
+    committed rocprofv3 counter summary for this workload, or None when the
+    summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_n{n}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -105,11 +115,12 @@ def measured_traffic(workload: str, n: int):
                 vals[key] = val
     if vals.get("kernel_source_digest") != kernel_source_digest():
         return None
-    fetch = float(vals["fetch_bytes_per_launch"]) / float(vals["copy_fetch_scale"])
-    write = float(vals["write_bytes_per_launch"]) / float(vals["copy_write_scale"])
+    per = float(vals.get("cycles_per_launch", 1))
+    fetch = float(vals["fetch_bytes_per_launch"]) / float(vals["copy_fetch_scale"]) / per
+    write = float(vals["write_bytes_per_launch"]) / float(vals["copy_write_scale"]) / per
     out = {"bytes_per_launch": fetch + write, "source": os.path.relpath(path, ROOT)}
     if "valu_wave_instructions_per_launch" in vals:
-        out["valu_wave_instructions"] = float(vals["valu_wave_instructions_per_launch"])
+        out["valu_wave_instructions"] = float(vals["valu_wave_instructions_per_launch"]) / per
     return out
 
 
@@ -131,6 +142,62 @@ def valu_roof(traffic, kern_ms):
     return {"wave_instructions_per_launch": wi, "issue_time_us": 1e6 * t_issue,
             "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "T lane-instructions/s",
             "frac": achieved / VALU_PEAK_TOPS}
+
+
+def tune_table(hbm, us):
+    """The autotuner's microseconds per cycle by candidate (None: not timed)."""
+    if us is None:
+        return None
+    return {k: (None if not np.isfinite(v) else float(v)) for k, v in zip(hbm.tune_labels(), us)}
+
+
+def planned_frac(name: str, n: int, kern_ms: float) -> dict:
+    """The roofline fraction with the planned per-object bytes (PLANNED_BYTES_PER_UPDATE)."""
+    pb = PLANNED_BYTES_PER_UPDATE.get(name)
+    if not pb or not kern_ms:
+        return {}
+    gbs = pb * n / (kern_ms * 1e-3) / 1e9
+    return {"planned_bytes_per_update": pb, "achieved_planned_bytes": gbs, "frac_planned_bytes": gbs / HBM_PEAK_GBS}
+
+
+def side_c2(torch, synth, hbm, n: int = 1_000_000, cycles: int = 64):
+    """The 3-D colour catalog at N = 10^6, briefly: cycles per second (one
+    persistent launch; graph replays of the two-kernel cycle beside it) and
+    the sweep kernel's mean duration (HIP events on its stream, plain
+    launches) with its fraction of HBM peak."""
+    wl = synth.gamma_lf_3d(n=n)
+    s = hbm.Sampler(wl, device="cuda:0", max_cycles=hbm.autotune_cycles(32) + 32 + 4 * cycles)
+    s.set_cycle_mode(hbm.HBM_CYCLES_GRAPH)
+    pick, tuned = s.autotune(32)                 # the two-kernel cycle's shape
+    s.set_cycle_mode(hbm.HBM_CYCLES_AUTO)
+    s.run_cycles(32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run_cycles(cycles)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    persistent = s.launch_counts()["persistent_cycles"] >= cycles
+    s.set_cycle_mode(hbm.HBM_CYCLES_GRAPH)
+    s.prepare_cycles(cycles)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.run_cycles(cycles)
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t1
+    hbm.kernel_timing(s.ctx, True)
+    s.run_cycles(cycles, use_graph=False)
+    n_launch, kern_ms = hbm.read_kernel_timing(s.ctx)
+    hbm.kernel_timing(s.ctx, False)
+    assert np.all(np.isfinite(s.theta_trace()))
+    s.close()
+    bpu = BYTES_PER_UPDATE[wl.name]
+    gbs = bpu * n / (kern_ms * 1e-3) / 1e9
+    return {"workload": wl.name, "n_objects": n, "cycles_timed": cycles, "us_per_cycle": 1e6 * wall / cycles,
+            "persistent_launch": persistent, "us_per_cycle_graph_replay": 1e6 * wall_graph / cycles,
+            "updates_per_s": n * cycles / wall, "tiles_per_workgroup": pick["tiles_per_group"],
+            "groups_per_cu_cap": pick["groups_per_cu"], "autotune_us_per_cycle": tune_table(hbm, tuned),
+            "sweep_kernel_us": 1e3 * kern_ms, "launches_timed": n_launch, "bytes_per_update": bpu,
+            "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS, **planned_frac(wl.name, n, kern_ms)}
 
 
 def accuracy_vs_oracle(wl, s, o):
@@ -229,14 +296,14 @@ def bench_batch(args, torch, synth, hbm):
     wls = synth.gamma_lf_batch(256)
     n_tot = sum(w.n for w in wls)
     trial = 64
-    total = 3 * (32 + trial) + args.warmup + 2 * args.steps
+    total = hbm.autotune_cycles(trial) + args.warmup + 2 * args.steps
     b = hbm.Batch(wls, device="cuda:0", max_cycles=total)
     use_graph = not args.no_graph
     if args.launch_shape == "auto":
         pick, us = b.autotune(trial)
     else:
-        pick, us = int(args.launch_shape), [None, None, None]
-        b.set_launch(pick)
+        pick, us = {"tiles_per_group": int(args.launch_shape), "groups_per_cu": 0, "persistent": False}, None
+        b.set_launch(pick["tiles_per_group"])
     b.run_cycles(args.warmup, use_graph=use_graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -290,10 +357,11 @@ def bench_batch(args, torch, synth, hbm):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (256 seeded gamma-LF catalogs, N log-uniform on [1e3, 1e5])",
         "config": {"workload": "gamma_lf_batch256", "n_datasets": 256, "n_objects_total": n_tot,
-                   "job_sweeps": args.job_sweeps, "graph": use_graph, "tiles_per_workgroup": pick},
+                   "job_sweeps": args.job_sweeps, "graph": use_graph,
+                   "tiles_per_workgroup": pick["tiles_per_group"], "groups_per_cu_cap": pick["groups_per_cu"]},
         "jobs_per_hour": jobs_h, "sequential_jobs_per_hour": jobs_h_seq, "batch_speedup": jobs_h / jobs_h_seq,
         "sequential_ms_per_cycle_sum": 1e3 * seq,
-        "autotune_us_per_cycle": {"1": us[0], "2": us[1], "4": us[2]},
+        "autotune_us_per_cycle": tune_table(hbm, us),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -592,30 +660,44 @@ def main():
     gen, n_default = make[args.workload]
     wl = gen(n=args.n or n_default)
     trial = 64
-    total = 3 * (32 + trial) + args.warmup + 2 * args.steps
+    total = hbm.autotune_cycles(trial) + args.warmup + 4 * args.steps
     s = hbm.Sampler(wl, device="cuda:0", max_cycles=total, theta_substeps=args.theta_substeps)
     use_graph = not args.no_graph
+    if args.graph_cycles:
+        s.set_cycle_mode(hbm.HBM_CYCLES_GRAPH)
 
-    # burn-in: the launch-shape autotuner's cycles (or a fixed shape), then plain warm-up cycles
+    # burn-in: the launch-shape autotuner's cycles (or a fixed shape), then warm-up cycles
     if args.launch_shape == "auto":
         pick, tuned = s.autotune(trial)
     else:
-        pick, tuned = int(args.launch_shape), [None, None, None]
-        s.set_launch(pick)
+        pick, tuned = {"tiles_per_group": int(args.launch_shape), "groups_per_cu": 0, "persistent": None}, None
+        s.set_launch(pick["tiles_per_group"])
     s.run_cycles(args.warmup, use_graph=use_graph)
+    if use_graph:
+        s.prepare_cycles(args.steps)          # any graph capture happens outside the timed region
     torch.cuda.synchronize()
 
-    # Timed region 1: the figure of merit (fused cycles, graph replay).
+    # Timed region 1: the figure of merit -- one persistent launch of all the
+    # cycles where the context allows it, else graph replays.
+    lc0 = s.launch_counts()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.run_cycles(args.steps, use_graph=use_graph)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    lc1 = s.launch_counts()
+    issued = {key: lc1[key] - lc0[key] for key in lc0}
+    assert issued["replayed_cycles"] + issued["plain_cycles"] + issued["persistent_cycles"] == args.steps, issued
+    persistent = issued["persistent_launches"] > 0
 
-    # Timed region 2: the same cycles with every sweep-kernel launch bracketed
-    # by HIP events on the sampler's stream (plain launches), for the
-    # kernel's own duration.
+    # Timed region 2: the same way of issuing, each launch bracketed by HIP
+    # events on the sampler's stream, for the dominant kernel's duration (the
+    # persistent kernel; with graphs, the sweep kernel of plain launches).
     hbm.kernel_timing(s.ctx, True)
+    s.run_cycles(args.steps, use_graph=use_graph)
+    n_launch_dom, dom_ms = hbm.read_kernel_timing(s.ctx)
+    # Timed region 3: the two-kernel cycle as plain launches, for the sweep
+    # kernel's own duration.
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s.run_cycles(args.steps, use_graph=False)
@@ -623,13 +705,24 @@ def main():
     wall_ev = time.perf_counter() - t1
     n_launch, kern_ms = hbm.read_kernel_timing(s.ctx)
     hbm.kernel_timing(s.ctx, False)
+    # The two-kernel cycle replayed from graphs, for comparison.
+    mode_graph = None
+    if persistent:
+        s.set_cycle_mode(hbm.HBM_CYCLES_GRAPH)
+        s.prepare_cycles(args.steps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        s.run_cycles(args.steps)
+        torch.cuda.synchronize()
+        mode_graph = time.perf_counter() - t2
+        s.set_cycle_mode(hbm.HBM_CYCLES_AUTO)
 
     th = s.theta_trace()
     assert np.all(np.isfinite(th)), "non-finite theta"
     stats = s.stats()
-    # effective samples of theta per second over the graph-timed cycles
-    # (variance over the squared batch-means standard error)
-    tw = th[len(th) - 2 * args.steps:len(th) - args.steps]
+    # effective samples of theta per second over the cycles of timed region 1
+    i_fom = hbm.autotune_cycles(trial) + args.warmup if args.launch_shape == "auto" else args.warmup
+    tw = th[i_fom:i_fom + args.steps]
     ess = []
     for j in range(wl.p):
         b = max(2, int(np.sqrt(len(tw))))
@@ -639,8 +732,37 @@ def main():
 
     updates = wl.n * args.steps / wall
     bpu = BYTES_PER_UPDATE[wl.name]
-    achieved = bpu * wl.n / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
-    traffic = measured_traffic(wl.name, wl.n)
+    sweep_gbs = bpu * wl.n / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
+    sweep_traffic = measured_traffic(wl.name, wl.n, "sweep")
+    sweep_roof = {"kernel": f"sweep_kernel<{wl.name}>", "kernel_ms": kern_ms, "launches_timed": n_launch,
+                  "achieved": sweep_gbs, "frac": sweep_gbs / HBM_PEAK_GBS if sweep_gbs else None,
+                  "traffic": (sweep_traffic["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9) if sweep_traffic else None,
+                  "traffic_source": sweep_traffic["source"] if sweep_traffic else
+                  "no counter summary for the current kernel sources",
+                  "valu": valu_roof(sweep_traffic, kern_ms), **planned_frac(wl.name, wl.n, kern_ms)}
+    if persistent:
+        # one persistent launch = args.steps cycles = N x steps object-updates
+        cyc_ms = dom_ms / args.steps if dom_ms > 0 else 0.0
+        achieved = bpu * wl.n / (cyc_ms * 1e-3) / 1e9 if cyc_ms > 0 else None
+        traffic = measured_traffic(wl.name, wl.n, "cycles")
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": (traffic["bytes_per_launch"] / (cyc_ms * 1e-3) / 1e9) if traffic else None,
+                "traffic_bytes_per_cycle": traffic["bytes_per_launch"] if traffic else None,
+                "algorithmic_bytes_per_launch": bpu * wl.n * args.steps, "bytes_per_update": bpu,
+                "traffic_source": traffic["source"] if traffic else "no counter summary for the current kernel sources",
+                "kernel": f"cycles_kernel<{wl.name}>", "cycles_per_launch": args.steps,
+                "launch_ms": dom_ms, "us_per_cycle_in_kernel": 1e3 * cyc_ms, "launches_timed": n_launch_dom,
+                "valu": valu_roof(traffic, cyc_ms), **planned_frac(wl.name, wl.n, cyc_ms),
+                "sweep_kernel_two_kernel_cycle": sweep_roof}
+    else:
+        roof = {"bound": "hbm", "achieved": sweep_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (sweep_gbs / HBM_PEAK_GBS) if sweep_gbs else None,
+                "traffic": sweep_roof["traffic"],
+                "traffic_bytes_per_launch": sweep_traffic["bytes_per_launch"] if sweep_traffic else None,
+                "algorithmic_bytes_per_launch": bpu * wl.n, "bytes_per_update": bpu,
+                "traffic_source": sweep_roof["traffic_source"], "kernel": f"sweep_kernel<{wl.name}>",
+                "launches_timed": n_launch, "valu": sweep_roof["valu"], **planned_frac(wl.name, wl.n, kern_ms)}
     out = {
         "metric": METRIC,
         "value": updates,
@@ -655,28 +777,30 @@ def main():
         "dtype": "f32" if wl.precision == "f32" else "f64",
         "data": f"synthetic (seeded {wl.name} catalog)",
         "config": {"workload": wl.name, "n_objects": wl.n, "latent_dim": wl.d, "theta_dim": wl.p,
-                   "selection_quadrature_nodes": 512 if wl.model in (2, 3, 5) else 0, "graph": use_graph,
-                   "sweeps_per_step": 1, "tiles_per_workgroup": pick,
+                   "selection_quadrature_nodes": 512 if wl.model in (2, 3, 5) else 0,
+                   "persistent_launch": persistent,
+                   "graph": issued["graph_replays"] > 0 and issued["plain_cycles"] == 0,
+                   "sweeps_per_step": 1, "tiles_per_workgroup": pick["tiles_per_group"],
+                   "groups_per_cu_cap": pick["groups_per_cu"], "autotune_picked_persistent": pick["persistent"],
                    "theta_substeps": args.theta_substeps},
+        "timed_cycles_issued": issued,
         "theta_ess_per_s": [e / wall if e else None for e in ess],
-        "autotune_us_per_cycle": {"1": tuned[0], "2": tuned[1], "4": tuned[2]},
+        "autotune_us_per_cycle": tune_table(hbm, tuned),
         "gibbs_sweeps_per_s": args.steps / wall,
         "breakdown_ms": {"step": 1e3 * wall / args.steps, "sweep_kernel": kern_ms,
-                         "step_with_event_timing": 1e3 * wall_ev / args.steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": (traffic["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9) if traffic else None,
-                     "traffic_bytes_per_launch": traffic["bytes_per_launch"] if traffic else None,
-                     "algorithmic_bytes_per_launch": bpu * wl.n, "traffic_source": traffic["source"] if traffic else
-                     "no counter summary for the current kernel sources",
-                     "kernel": f"sweep_kernel<{wl.name}>", "bytes_per_update": bpu,
-                     "launches_timed": n_launch, "valu": valu_roof(traffic, kern_ms)},
+                         "step_two_kernel_plain_launches_event_timed": 1e3 * wall_ev / args.steps,
+                         "step_two_kernel_graph_replay": 1e3 * mode_graph / args.steps if mode_graph else None,
+                         "persistent_launch_ms": dom_ms if persistent else None},
+        "roofline": roof,
         "accept_rate_last_sweep": stats["n_acc"] / wl.n,
         "theta_last": th[-1].tolist(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy_vs_oracle"] = cpu_baseline(wl, args.cpu_seconds, sampler=s)
     s.close()
+    if wl.name == "gamma_lf_1d" and not args.no_side_c2:
+        torch.cuda.empty_cache()
+        out["gamma_lf_color_3d_n1000000"] = side_c2(torch, synth, hbm)
     print(json.dumps(out), flush=True)
 
 

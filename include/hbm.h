@@ -116,6 +116,10 @@ typedef int32_t hbm_status;
 #define HBM_FP64 1
 #define HBM_FP32 2
 
+/* How run_cycles issues fused cycles (set_cycle_mode). */
+#define HBM_CYCLES_AUTO  0  /* one persistent launch where possible, else graphs */
+#define HBM_CYCLES_GRAPH 1  /* always graphs (or plain launches) */
+
 typedef struct hbm_config {
     int32_t model;               /* HBM_* model id */
     int32_t precision;           /* HBM_FP64 or HBM_FP32; must match the model */
@@ -253,6 +257,7 @@ HBM_API hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out);
 HBM_API hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const double *theta, double *out,
                                    double *terms);
 
+
 /* One Metropolis-Hastings step on theta of every active slot, for the
  * sweep just done: the
  * pending proposal theta' = theta + S_theta z (z from block (0, k, 1, b)) is
@@ -266,14 +271,39 @@ HBM_API hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, 
  * accepted, 0 if not, -1 for slots that took no step.  Synchronous. */
 HBM_API hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted);
 
-/* n_cycles full cycles (sweep then theta step) of every active slot: each
- * cycle is the sweep kernel followed by an epilogue kernel that reduces the
- * partials and takes the theta step on the device, so no host round trip
- * happens between cycles; the sequence is replayed from a captured hipGraph
- * when use_graph != 0.  A slot whose budget is reached stops at that cycle.
- * Results are identical to alternating ram_sweep(1) and theta_step.
- * Asynchronous. */
+/* n_cycles full cycles (sweep then theta step) of every active slot, with
+ * no host round trip between cycles.  Three ways to issue them, all giving
+ * bit-identical chains (and the chain of alternating ram_sweep(1) and
+ * theta_step):
+ *   - use_graph == 0: per cycle, the sweep kernel and an epilogue kernel
+ *     that reduces the tile partials and takes the theta step on the device;
+ *   - use_graph != 0, a one-dataset context (init_chains) in mode
+ *     HBM_CYCLES_AUTO, on a device that holds the grid: one persistent
+ *     cooperative launch of 256 (or 128, 64) workgroups that stay resident
+ *     for all n cycles, each sweeping a fixed set of tiles and taking the
+ *     theta step itself after an exchange of the per-lane partial sums
+ *     (no kernel boundary between cycles);
+ *   - otherwise with use_graph != 0: replays of captured hipGraphs,
+ *     floor(n / 32) of a 32-cycle graph and one of a graph of the remaining
+ *     n mod 32 cycles (captured on first need, again when the remainder
+ *     changes; prepare_cycles captures ahead).
+ * A slot whose budget is reached stops at that cycle.  Asynchronous. */
 HBM_API hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph);
+
+/* Captures the graphs run_cycles(ctx, n_cycles, 1) would replay when it
+ * uses graphs, without running any cycle, so that a later run_cycles of
+ * that length spends no time on capture.  Synchronous. */
+HBM_API hbm_status prepare_cycles(hbm_ctx *ctx, int64_t n_cycles);
+
+/* mode: HBM_CYCLES_AUTO (default) lets run_cycles use the persistent
+ * launch where it can; HBM_CYCLES_GRAPH restricts it to graphs. */
+HBM_API hbm_status set_cycle_mode(hbm_ctx *ctx, int32_t mode);
+
+/* How run_cycles has issued cycles since the context was created:
+ * out[0] graph replays, out[1] cycles inside those replays, out[2] cycles
+ * issued as plain kernel launches, out[3] graphs captured, out[4]
+ * persistent launches, out[5] cycles inside those. */
+HBM_API hbm_status launch_counts(hbm_ctx *ctx, int64_t out[6]);
 
 /* Receives streamed latent snapshots of one slot: its snapshots number
  * first .. first + count - 1 (snapshot r is the state after sweep
@@ -360,20 +390,39 @@ HBM_API hbm_status get_stats(hbm_ctx *ctx, int32_t slot, double out[8]);
  * do not depend on the shape.  Drops the captured graph.  Synchronous. */
 HBM_API hbm_status set_launch(hbm_ctx *ctx, int32_t tiles_per_group);
 
-/* Autotuner of the launch shape: for each shape, 32 warm-up cycles then
- * trial_cycles timed cycles (graph replay, hipEvents on the context's
- * stream); keeps the fastest.  The cycles are real cycles of every active
- * slot (3 (32 + trial_cycles) of them, counted against max_cycles), and
- * since results do not depend on the shape, tuning during burn-in changes
- * no chain.  out_tiles_per_group (nullable): the choice; out_us (nullable):
- * [3] microseconds per cycle for shapes 1, 2, 4.  Synchronous. */
-HBM_API hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t *out_tiles_per_group, double out_us[3]);
+/* Occupancy of the sweep kernel: at most groups_per_cu of its 256-thread
+ * workgroups resident per compute unit (so at most groups_per_cu waves per
+ * SIMD), enforced by dynamic LDS the kernel does not use; 0 removes the cap
+ * (as many as registers and LDS allow: 8 per SIMD for the sweep kernels).
+ * Results do not depend on it.  Drops the captured graphs.  Synchronous. */
+HBM_API hbm_status set_occupancy(hbm_ctx *ctx, int32_t groups_per_cu);
 
-/* Per-launch duration of the sweep and marginal kernels: when enabled, every
- * launch of either carries a start and a stop hipEvent that the runtime
- * records from the dispatch itself (hipExtLaunchKernel), and run_cycles issues plain
- * launches instead of replaying its graph.  read returns the launches timed
- * and their mean duration in ms and resets the counters.  Synchronous read. */
+/* Autotuner of how cycles run.  HBM_TUNE_CANDIDATES candidates, in this
+ * order: the two-kernel cycle replayed from graphs with tiles per workgroup
+ * 1, 2, 4 under no occupancy cap (candidates 0-2), a cap of 4 (3-5) and a
+ * cap of 2 workgroups per compute unit (6-8); then the persistent launch
+ * (9; one-dataset contexts in mode HBM_CYCLES_AUTO, else not timed).  Each
+ * runs 8 warm-up cycles then trial_cycles cycles timed by hipEvents on the
+ * context's stream; the fastest is kept: its shape and cap, and the cycle
+ * mode (HBM_CYCLES_AUTO when the persistent launch won, else
+ * HBM_CYCLES_GRAPH).  The cycles are real cycles of every active slot
+ * (HBM_TUNE_CANDIDATES (8 + trial_cycles) of them, counted against
+ * max_cycles); results do not depend on the choice, so tuning during burn-in
+ * changes no chain.  out_choice (nullable): [3] tiles per workgroup,
+ * workgroups-per-CU cap (0: none), persistent (0/1); out_us (nullable):
+ * [HBM_TUNE_CANDIDATES] microseconds per cycle (NaN: not timed).
+ * Synchronous. */
+#define HBM_TUNE_CANDIDATES 10
+HBM_API hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t out_choice[3],
+                            double out_us[HBM_TUNE_CANDIDATES]);
+
+/* Per-launch duration of the sweep, persistent-cycle and marginal kernels:
+ * when enabled, every launch of the sweep or marginal kernel carries a start
+ * and a stop hipEvent that the runtime records from the dispatch itself
+ * (hipExtLaunchKernel), every persistent launch is bracketed by events
+ * recorded on the stream, and run_cycles issues plain launches where it
+ * would replay graphs.  read returns the launches timed and their mean
+ * duration in ms and resets the counters.  Synchronous read. */
 HBM_API hbm_status kernel_timing(hbm_ctx *ctx, int32_t enable);
 HBM_API hbm_status read_kernel_timing(hbm_ctx *ctx, int64_t *n_launches, double *mean_ms);
 

@@ -159,6 +159,7 @@ class Oracle:
         self.wl = wl
         self.n, self.d, self.p = wl.n, wl.d, wl.p
         self.alpha_star = wl.alpha_star if alpha_star is None else alpha_star
+        self.gamma = gamma
         data = np.ascontiguousarray(wl.data, dtype=np.float64)
         consts = np.ascontiguousarray(wl.consts, dtype=np.float64)
         self.seed = wl.seed if seed is None else seed

@@ -24,11 +24,12 @@ from .serve import TileAllocator
 HBM_OK, HBM_EINVAL, HBM_ENOMEM, HBM_EHIP, HBM_EDOMAIN, HBM_ESTATE, HBM_ENOSPACE = 0, -1, -2, -3, -4, -5, -6
 HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_3D, HBM_BB1_LF = 1, 2, 3, 4, 5
 HBM_FP64, HBM_FP32 = 1, 2
+HBM_CYCLES_AUTO, HBM_CYCLES_GRAPH = 0, 1
 
 EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
-            "ram_sweep", "pop_loglik", "marginal_loglik", "theta_step", "run_cycles", "run_cycles_streamed",
+            "ram_sweep", "pop_loglik", "marginal_loglik", "theta_step", "run_cycles", "prepare_cycles", "set_cycle_mode", "launch_counts", "run_cycles_streamed",
             "fd_sink", "get_samples", "get_theta", "set_theta",
-            "ram_sweep_trace", "get_state", "set_state", "get_stats", "set_launch", "autotune", "kernel_timing",
+            "ram_sweep_trace", "get_state", "set_state", "get_stats", "set_launch", "set_occupancy", "autotune", "kernel_timing",
             "read_kernel_timing", "last_error", "destroy_chains")
 
 TILE = 256   # objects per tile: datasets in a pool start on multiples of this
@@ -92,6 +93,9 @@ def lib():
             "marginal_loglik": [P, i32, i32, P, P, P],
             "theta_step": [P, P],
             "run_cycles": [P, i64, i32],
+            "prepare_cycles": [P, i64],
+            "set_cycle_mode": [P, i32],
+            "launch_counts": [P, P],
             "run_cycles_streamed": [P, i64, i32, SNAPSHOT_SINK, P],
             "get_samples": [P, i32, i64, i64, P, P, P],
             "get_theta": [P, i32, P, P, P],
@@ -101,6 +105,7 @@ def lib():
             "get_state": [P, P, P],
             "set_state": [P, P, ctypes.c_size_t],
             "set_launch": [P, i32],
+            "set_occupancy": [P, i32],
             "autotune": [P, i32, P, P],
             "kernel_timing": [P, i32],
             "read_kernel_timing": [P, P, P],
@@ -220,6 +225,21 @@ def run_cycles(ctx, n_cycles: int, use_graph: bool = True):
     _check(lib().run_cycles(ctx, n_cycles, int(use_graph)), ctx)
 
 
+def prepare_cycles(ctx, n_cycles: int):
+    _check(lib().prepare_cycles(ctx, n_cycles), ctx)
+
+
+def set_cycle_mode(ctx, mode: int):
+    _check(lib().set_cycle_mode(ctx, mode), ctx)
+
+
+def launch_counts(ctx) -> dict:
+    out = np.zeros(6, dtype=np.int64)
+    _check(lib().launch_counts(ctx, _ptr(out)), ctx)
+    return dict(zip(("graph_replays", "replayed_cycles", "plain_cycles", "graph_captures", "persistent_launches",
+                     "persistent_cycles"), out.tolist()))
+
+
 # int32 sink(void *user, int32 slot, int64 first, int64 count, const void *rows, int64 bytes)
 SNAPSHOT_SINK = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int64)
@@ -309,12 +329,31 @@ def set_launch(ctx, tiles_per_group: int):
     _check(lib().set_launch(ctx, tiles_per_group), ctx)
 
 
+def set_occupancy(ctx, groups_per_cu: int):
+    _check(lib().set_occupancy(ctx, groups_per_cu), ctx)
+
+
+TUNE_CANDIDATES = 10      # HBM_TUNE_CANDIDATES
+TUNE_WARM = 8             # warm-up cycles per candidate
+
+
+def autotune_cycles(trial_cycles: int) -> int:
+    """Cycles (theta-trace rows) one autotune call runs."""
+    return TUNE_CANDIDATES * (TUNE_WARM + trial_cycles)
+
+
+def tune_labels():
+    """Names of the autotuner's candidates, in its order."""
+    return [f"tpw{t}_cap{c}" for c in (0, 4, 2) for t in (1, 2, 4)] + ["persistent"]
+
+
 def autotune(ctx, trial_cycles: int = 64):
-    """Runs 3 x (32 + trial_cycles) real cycles; returns (chosen tiles per workgroup, us/cycle for 1, 2, 4)."""
-    pick = ctypes.c_int32()
-    us = np.zeros(3)
-    _check(lib().autotune(ctx, trial_cycles, ctypes.byref(pick), _ptr(us)), ctx)
-    return pick.value, us
+    """Runs autotune_cycles(trial_cycles) real cycles; returns (choice dict,
+    us/cycle per candidate in tune_labels() order, NaN where not timed)."""
+    ch = np.zeros(3, dtype=np.int32)
+    us = np.zeros(TUNE_CANDIDATES)
+    _check(lib().autotune(ctx, trial_cycles, _ptr(ch), _ptr(us)), ctx)
+    return {"tiles_per_group": int(ch[0]), "groups_per_cu": int(ch[1]), "persistent": bool(ch[2])}, us
 
 
 def kernel_timing(ctx, enable: bool):
@@ -405,11 +444,23 @@ class _Chains:
     def run_cycles(self, n: int, use_graph: bool = True):
         run_cycles(self.ctx, n, use_graph)
 
+    def prepare_cycles(self, n: int):
+        prepare_cycles(self.ctx, n)
+
+    def launch_counts(self) -> dict:
+        return launch_counts(self.ctx)
+
+    def set_cycle_mode(self, mode: int):
+        set_cycle_mode(self.ctx, mode)
+
     def autotune(self, trial_cycles: int = 64):
         return autotune(self.ctx, trial_cycles)
 
     def set_launch(self, tiles_per_group: int):
         set_launch(self.ctx, tiles_per_group)
+
+    def set_occupancy(self, groups_per_cu: int):
+        set_occupancy(self.ctx, groups_per_cu)
 
 
 class Sampler(_Chains):

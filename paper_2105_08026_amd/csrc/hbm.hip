@@ -12,6 +12,7 @@
 // its theta-step budget is spent, so a captured graph stays valid while
 // datasets come and go.
 #include "hbm.h"
+#include "cycles.h"
 #include "kernels.h"
 #include "marginal.h"
 
@@ -27,6 +28,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -36,6 +38,13 @@ using namespace hbm;
 namespace {
 
 thread_local std::string g_init_error;
+
+// exchange words of the persistent cycle kernel: [2][kXchCols][2][256]
+constexpr size_t kXchBytes = sizeof(uint64_t) * 2 * kXchCols * 2 * kBlock;
+// bound on one wait inside the persistent kernel: 2 s of s_memrealtime (100 MHz)
+constexpr int64_t kSpinTicks = 200000000;
+// warm-up cycles of each autotuner candidate before its timed cycles
+constexpr int64_t kTuneWarm = 8;
 
 struct CtxImpl;
 
@@ -48,7 +57,10 @@ struct Launch {
     hbm_status (*check_init)(CtxImpl *);      // slots flagged in c->which
     hbm_status (*quadrature)(CtxImpl *);      // reference Gauss-Legendre rule
     hbm_status (*marginal)(CtxImpl *, int32_t slot, int32_t n_theta, const double *theta, double *out,
-                           double *partials, double *th, double *terms);   // device arguments
+                           double *partials, double *th, double *terms, const MargNode *rule);   // device arguments
+    // n full cycles as one persistent cooperative launch; *launched = false
+    // (and nothing enqueued) when the context or device cannot take it
+    hbm_status (*cycles)(CtxImpl *, int64_t n, bool *launched);
 };
 
 // Host mirror of one slot.  Every field follows from the calls made, so the
@@ -73,9 +85,13 @@ struct CtxImpl {
     int32_t n_slots = 0;
     int32_t nq = 1;
     int32_t tpw = 1;                // tiles per sweep workgroup (1, 2 or 4)
+    int32_t occ_cap = 0;            // most sweep workgroups per compute unit (0: as many as fit)
+    // dynamic LDS that holds a sweep kernel to occ_cap workgroups per CU, per (kernel, cap)
+    std::vector<std::pair<std::pair<const void *, int32_t>, size_t>> occ_lds;
     bool stats_mode = false;        // theta steps from sufficient statistics
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
+    int device = -1;                // ordinal of the device holding the buffers
     void *dd = nullptr;             // [md][cap] derived per-object data
     double *partials = nullptr;     // [2 + kMaxStats][n_tiles]: tile sums, then accepted counts
     double *pout = nullptr;         // [n_slots][2] results of pop_loglik
@@ -94,10 +110,24 @@ struct CtxImpl {
     bool poisoned = false;
     std::string err;
     const Launch *ops = nullptr;
-    // graph of consecutive full cycles
+    // graphs of consecutive full cycles: kGraphCycles of them, and one of
+    // the remainder a run_cycles call last needed
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
     int64_t graph_len = 0;
+    hipGraphExec_t tail_exec = nullptr;
+    hipGraph_t tail = nullptr;
+    int64_t tail_len = 0;
+    // cycles issued by run_cycles: graph replays, cycles inside them, plain cycles, graph captures,
+    // persistent launches and the cycles inside them
+    int64_t n_replays = 0, n_replayed_cycles = 0, n_plain_cycles = 0, n_captures = 0;
+    int64_t n_persistent = 0, n_persistent_cycles = 0;
+    // persistent cycle kernel: exchange words, the next cycle's tag, its
+    // grid (0: not yet decided, -1: unavailable) and whether it may be used
+    uint64_t *xch = nullptr;
+    uint32_t xch_tag = 1;
+    int32_t persist_groups = 0;
+    int32_t cycle_mode = HBM_CYCLES_AUTO;
     // launch extent of the cycle kernels in a multi-slot context: side and
     // epilogue workgroups for slots [0, ext_slots), tile workgroups for tiles
     // [0, ext_tiles), up to the last loaded slot and occupied tile
@@ -185,11 +215,67 @@ int32_t marg_blocks(int64_t n)
 constexpr int kMargShapeNodes = 2 * MargRuleShape::kCore + MargRuleShape::kGraded + MargRuleShape::kTail;
 constexpr int kMargProductNodes = 2 * MargRuleProduct::kCore;
 
+// Dynamic LDS (unused by the kernel) that limits fn to c->occ_cap resident
+// workgroups per compute unit: the smallest multiple of 256 bytes at which
+// the occupancy calculator reports no more than the cap (the largest the
+// device allows, if even that leaves more).  Cached per kernel and cap.
+size_t occupancy_lds(CtxImpl *c, const void *fn)
+{
+    const auto key = std::make_pair(fn, c->occ_cap);
+    for (const auto &e : c->occ_lds)
+        if (e.first == key) return e.second;
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+        max_lds = 65536;
+    auto fits = [&](size_t lds) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return nb <= c->occ_cap;
+    };
+    size_t lo = 0, hi = static_cast<size_t>(max_lds) / 256;   // in units of 256 bytes
+    size_t pick = 0;
+    if (!fits(0)) {
+        if (!fits(hi * 256)) {
+            pick = hi * 256;
+        } else {
+            while (hi - lo > 1) {
+                const size_t mid = (lo + hi) / 2;
+                if (fits(mid * 256)) hi = mid;
+                else lo = mid;
+            }
+            pick = hi * 256;
+        }
+    }
+    (void)hipGetLastError();
+    c->occ_lds.push_back(std::make_pair(key, pick));
+    return pick;
+}
+
+// Workgroups of the persistent cycle kernel: the largest of 256, 128 and 64
+// that the device holds at once (cooperative launch), or -1.
+int32_t persistent_groups(CtxImpl *c, const void *fn)
+{
+    int coop = 0, cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess || !coop ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    const int64_t fit = static_cast<int64_t>(cus) * per_cu;
+    for (int32_t w : {256, 128, 64})
+        if (w <= fit) return w;
+    return -1;
+}
+
 template <class M>
 struct Ops {
     using T = typename M::T;
 
-    static hbm_status sweep(CtxImpl *c, bool full, void *trace)
+    static SweepArgs<T> sweep_args(CtxImpl *c, void *trace)
     {
         SweepArgs<T> a;
         a.chi = static_cast<T *>(c->buf.chi);
@@ -210,10 +296,16 @@ struct Ops {
         a.n_tiles_total = c->n_tiles;
         // a multi-slot context launches only up to its last loaded slot and
         // occupied tile: the workgroups beyond would find nothing to do
-        const bool whole = single(c);
-        a.n_ds = whole ? c->n_slots : c->ext_slots;
-        const int32_t n_t = whole ? c->n_tiles : c->ext_tiles;
+        a.n_ds = single(c) ? c->n_slots : c->ext_slots;
         a.nq = c->nq;
+        return a;
+    }
+
+    static hbm_status sweep(CtxImpl *c, bool full, void *trace)
+    {
+        const SweepArgs<T> a = sweep_args(c, trace);
+        const bool whole = single(c);
+        const int32_t n_t = whole ? c->n_tiles : c->ext_tiles;
         // traced sweeps (a checking aid) always take one tile per workgroup
         const int tpw = trace ? 1 : c->tpw;
         const dim3 grid(static_cast<unsigned>(a.n_ds + (n_t + tpw - 1) / tpw));
@@ -263,11 +355,15 @@ struct Ops {
     template <bool kTrace, int TPW, bool kSingle, bool kStats>
     static void launch_sweep(CtxImpl *c, dim3 grid, const SweepArgs<T> &a, hipEvent_t e0, hipEvent_t e1)
     {
+        const size_t lds = c->occ_cap > 0 ? occupancy_lds(c, reinterpret_cast<const void *>(
+                                                                 &sweep_kernel<M, kTrace, TPW, kSingle, kStats>))
+                                          : 0;
         if (e0)
-            hipExtLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle, kStats>), grid, dim3(kBlock), 0, c->stream,
-                                  e0, e1, 0, a);
+            hipExtLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle, kStats>), grid, dim3(kBlock), lds,
+                                  c->stream, e0, e1, 0, a);
         else
-            hipLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle, kStats>), grid, dim3(kBlock), 0, c->stream, a);
+            hipLaunchKernelGGL((sweep_kernel<M, kTrace, TPW, kSingle, kStats>), grid, dim3(kBlock), lds, c->stream,
+                               a);
     }
 
     static EpiArgs epi_args(CtxImpl *c)
@@ -372,7 +468,7 @@ struct Ops {
     }
 
     static hbm_status marginal(CtxImpl *c, int32_t slot, int32_t n_theta, const double *theta, double *out,
-                               double *partials, double *th, double *terms)
+                               double *partials, double *th, double *terms, const MargNode *rule)
     {
         if constexpr (HasMarg<M>::value) {
             using R = typename Marg<M>::R;
@@ -381,7 +477,7 @@ struct Ops {
             LAUNCHCHK(c, "marginal_prep_kernel");
             MargArgs a;
             a.data = c->buf.data;
-            a.rule = c->marg_rule + (R::kGraded > 0 ? 0 : kMargShapeNodes);
+            a.rule = rule + (R::kGraded > 0 ? 0 : kMargShapeNodes);
             a.theta = theta;
             a.th = th;
             a.partials = partials;
@@ -407,14 +503,74 @@ struct Ops {
             LAUNCHCHK(c, "marginal_finish_kernel");
             return HBM_OK;
         } else {
-            (void)slot; (void)n_theta; (void)theta; (void)out; (void)partials; (void)th; (void)terms;
+            (void)slot; (void)n_theta; (void)theta; (void)out; (void)partials; (void)th; (void)terms; (void)rule;
             return fail(c, HBM_EINVAL, "the marginal likelihood needs a model with a 1-D latent");
         }
     }
 
+    static hbm_status cycles(CtxImpl *c, int64_t n, bool *launched)
+    {
+        *launched = false;
+        if (c->cycle_mode != HBM_CYCLES_AUTO || !single(c)) return HBM_OK;
+        if constexpr (M::NS > 0) {
+            if (c->stats_mode) return cycles_as<true>(c, n, launched);
+        }
+        if (c->stats_mode) return HBM_OK;
+        return cycles_as<false>(c, n, launched);
+    }
+
+    template <bool kStats>
+    static hbm_status cycles_as(CtxImpl *c, int64_t n, bool *launched)
+    {
+        // tiles per register batch: four single-precision 1-D objects, else two
+        constexpr int B = (M::D == 1 && sizeof(T) == 4) ? 4 : 2;
+        const void *fn = reinterpret_cast<const void *>(&cycles_kernel<M, B, kStats>);
+        if (c->persist_groups == 0) c->persist_groups = persistent_groups(c, fn);
+        if (c->persist_groups < 0) return HBM_OK;
+        CyclesArgs<T> a;
+        a.sw = sweep_args(c, nullptr);
+        a.theta_trace = c->theta_trace;
+        a.xch = c->xch;
+        a.n_cycles = n;
+        a.spin_ticks = kSpinTicks;
+        a.tag0 = c->xch_tag;
+        a.n_groups = c->persist_groups;
+        void *args[] = {&a};
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->timing) {
+            e0 = take_event(c);
+            e1 = take_event(c);
+            if (!e0 || !e1) return fail(c, HBM_ENOMEM, "hipEventCreate failed");
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+        }
+        const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(static_cast<unsigned>(a.n_groups)), dim3(kBlock), args,
+                                                        0, c->stream);
+        if (e != hipSuccess) {
+            // the device would not take the grid: graphs from now on
+            (void)hipGetLastError();
+            c->persist_groups = -1;
+            if (e0) c->ev_free.push_back(e0);
+            if (e1) c->ev_free.push_back(e1);
+            return HBM_OK;
+        }
+        if (c->timing) {
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            c->ev_pending.push_back(e0);
+            c->ev_pending.push_back(e1);
+        }
+        // tags never repeat within 2^32 cycles; 0 (the buffer's initial words) is skipped
+        const uint32_t next = c->xch_tag + static_cast<uint32_t>(n);
+        c->xch_tag = next < c->xch_tag || next == 0 ? 1u : next;
+        c->n_persistent += 1;
+        c->n_persistent_cycles += n;
+        *launched = true;
+        return HBM_OK;
+    }
+
     static const Launch *table()
     {
-        static const Launch t{&sweep, &theta, &set_theta, &poplik, &prepare, &check_init, &quadrature, &marginal};
+        static const Launch t{&sweep, &theta, &set_theta, &poplik, &prepare, &check_init, &quadrature, &marginal,
+                              &cycles};
         return &t;
     }
 };
@@ -511,6 +667,8 @@ void release(CtxImpl *c)
     if (c->stream || c->cs) (void)hipStreamSynchronize(c->stream);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->tail_exec) (void)hipGraphExecDestroy(c->tail_exec);
+    if (c->tail) (void)hipGraphDestroy(c->tail);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->copy_stream) {
         (void)hipStreamSynchronize(c->copy_stream);
@@ -521,7 +679,7 @@ void release(CtxImpl *c)
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
     void *ptrs[] = {c->dd, c->partials, c->pout, c->theta_in, c->side, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
-                    c->cs, c->st, c->theta_trace, c->tile_ds, c->which, c->marg_rule, c->marg_buf};
+                    c->cs, c->st, c->theta_trace, c->tile_ds, c->which, c->marg_rule, c->marg_buf, c->xch};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete static_cast<hbm_ctx *>(c);
@@ -643,9 +801,14 @@ hbm_status drop_graph(CtxImpl *c)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
     if (c->graph) HIPCHK(c, hipGraphDestroy(c->graph));
+    if (c->tail_exec) HIPCHK(c, hipGraphExecDestroy(c->tail_exec));
+    if (c->tail) HIPCHK(c, hipGraphDestroy(c->tail));
     c->graph_exec = nullptr;
     c->graph = nullptr;
     c->graph_len = 0;
+    c->tail_exec = nullptr;
+    c->tail = nullptr;
+    c->tail_len = 0;
     return HBM_OK;
 }
 
@@ -705,6 +868,15 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
     c->stats_mode = pool->stats_theta != 0;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->ops = mi.ops;
+    {
+        // the device of the caller's buffers (else the current one)
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, buffers->data) == hipSuccess && at.type == hipMemoryTypeDevice)
+            c->device = at.device;
+        else if (hipGetDevice(&c->device) != hipSuccess)
+            c->device = -1;
+        (void)hipGetLastError();
+    }
     c->slots.assign(c->n_slots, Slot{});
     c->h_tile_ds.assign(c->n_tiles, -1);
     c->h_which.assign(c->n_slots, 0);
@@ -740,7 +912,8 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
         (s = alloc(reinterpret_cast<void **>(&c->theta_trace),
                    sizeof(double) * c->p * static_cast<size_t>(pool->max_cycles) * ns)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->tile_ds), sizeof(int32_t) * c->n_tiles)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->which), sizeof(int32_t) * ns)) != HBM_OK)
+        (s = alloc(reinterpret_cast<void **>(&c->which), sizeof(int32_t) * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->xch), kXchBytes)) != HBM_OK)
         return bail(s);
     // every slot starts empty: zero statics (n = 0) and inactive states
     std::vector<Statics> hs(ns);
@@ -752,6 +925,7 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
             hipSuccess ||
         (e = hipMemcpyAsync(c->tile_ds, c->h_tile_ds.data(), sizeof(int32_t) * c->n_tiles, hipMemcpyHostToDevice,
                             c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->xch, 0, kXchBytes, c->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
         hip_fail(c, e, "pool initialisation copies");
         return bail(HBM_EHIP);
@@ -941,11 +1115,12 @@ void host_gauss_legendre(int n, double *t, double *w)
     }
 }
 
-// Node tables of the marginal likelihood (the layouts marginal.h documents).
-hbm_status ensure_marg_rule(CtxImpl *c)
+// Node tables of the marginal likelihood (the layouts marginal.h documents),
+// built once per process on the host.
+constexpr int kMargRuleNodes = kMargShapeNodes + kMargProductNodes;
+
+hbm_status build_marg_rule(CtxImpl *c, MargNode *r)
 {
-    if (c->marg_rule) return HBM_OK;
-    std::vector<MargNode> r(kMargShapeNodes + kMargProductNodes);
     double t[64], w[64];
     using S = MargRuleShape;
     host_gauss_legendre(S::kCore, t, w);
@@ -969,11 +1144,38 @@ hbm_status ensure_marg_rule(CtxImpl *c)
     host_gauss_legendre(MargRuleProduct::kCore, t, w);
     for (int j = 0; j < kMargProductNodes; ++j)
         r[q++] = MargNode{t[j % MargRuleProduct::kCore], w[j % MargRuleProduct::kCore], 0.0, 0.0};
+    return HBM_OK;
+}
+
+std::mutex g_rule_mu;
+MargNode g_host_rule[kMargRuleNodes];
+bool g_host_rule_ready = false;
+
+// The host table, built on first use (no heap allocation).
+hbm_status host_marg_rule(CtxImpl *c, const MargNode **out)
+{
+    std::lock_guard<std::mutex> lk(g_rule_mu);
+    if (!g_host_rule_ready) {
+        hbm_status st = build_marg_rule(c, g_host_rule);
+        if (st != HBM_OK) return st;
+        g_host_rule_ready = true;
+    }
+    *out = g_host_rule;
+    return HBM_OK;
+}
+
+// The context's own device copy of the rule (marginal_loglik).
+hbm_status ensure_marg_rule(CtxImpl *c)
+{
+    if (c->marg_rule) return HBM_OK;
+    const MargNode *hr = nullptr;
+    hbm_status st = host_marg_rule(c, &hr);
+    if (st != HBM_OK) return st;
     void *p = nullptr;
-    if (hipMalloc(&p, sizeof(MargNode) * r.size()) != hipSuccess)
+    if (hipMalloc(&p, sizeof(MargNode) * kMargRuleNodes) != hipSuccess)
         return fail(c, HBM_ENOMEM, "hipMalloc: marginal rule");
     c->marg_rule = static_cast<MargNode *>(p);
-    HIPCHK(c, hipMemcpyAsync(c->marg_rule, r.data(), sizeof(MargNode) * r.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->marg_rule, hr, sizeof(MargNode) * kMargRuleNodes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HBM_OK;
 }
@@ -989,6 +1191,46 @@ bool marg_density_ok(int model, const double *th)
     }
 }
 
+// Argument checks shared by the marginal-likelihood entry points.
+hbm_status check_marginal_args(CtxImpl *c, int32_t slot, int32_t n_theta, const double *theta, const double *out)
+{
+    hbm_status st = check_slot(c, slot, true);
+    if (st != HBM_OK) return st;
+    if (c->d != 1) return fail(c, HBM_EINVAL, "the marginal likelihood needs a model with a 1-D latent");
+    if (n_theta < 1 || n_theta > 65535) return fail(c, HBM_EINVAL, "n_theta must be in [1, 65535]");
+    if (!theta || !out) return fail(c, HBM_EINVAL, "theta and out must be non-NULL");
+    for (int64_t j = 0; j < static_cast<int64_t>(n_theta) * c->p; ++j)
+        if (!std::isfinite(theta[j])) return fail(c, HBM_EINVAL, "theta must be finite");
+    for (int32_t j = 0; j < n_theta; ++j)
+        if (!marg_density_ok(c->pool.model, theta + static_cast<size_t>(j) * c->p))
+            return fail(c, HBM_EDOMAIN, "theta outside the domain of the population density");
+    return HBM_OK;
+}
+
+// Device scratch of one marginal-likelihood call, in doubles: theta rows,
+// results, per-workgroup partial sums, per-row scalars.
+size_t marginal_scratch_bytes(const CtxImpl *c, int32_t slot, int32_t n_theta)
+{
+    const size_t nb = static_cast<size_t>(marg_blocks(c->slots[slot].n)), nt = static_cast<size_t>(n_theta);
+    return sizeof(double) * (nt * c->p + nt + nt * nb + nt * kMargThWords);
+}
+
+// One marginal-likelihood evaluation with its scratch at `buf` (laid out as
+// marginal_scratch_bytes counts it) and the node rule at `rule`.
+hbm_status run_marginal(CtxImpl *c, int32_t slot, int32_t n_theta, const double *theta, double *out, double *terms,
+                        double *buf, const MargNode *rule)
+{
+    const size_t nb = static_cast<size_t>(marg_blocks(c->slots[slot].n));
+    const size_t n_th = static_cast<size_t>(n_theta) * c->p, n_part = static_cast<size_t>(n_theta) * nb;
+    double *d_theta = buf, *d_out = d_theta + n_th, *d_part = d_out + n_theta, *d_pre = d_part + n_part;
+    HIPCHK(c, hipMemcpyAsync(d_theta, theta, sizeof(double) * n_th, hipMemcpyHostToDevice, c->stream));
+    hbm_status st = c->ops->marginal(c, slot, n_theta, d_theta, d_out, d_part, d_pre, terms, rule);
+    if (st != HBM_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(out, d_out, sizeof(double) * n_theta, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HBM_OK;
+}
+
 // Checks that n_cycles full cycles can run now.
 hbm_status check_cycles(CtxImpl *c, int64_t n_cycles)
 {
@@ -1002,38 +1244,99 @@ hbm_status check_cycles(CtxImpl *c, int64_t n_cycles)
     return HBM_OK;
 }
 
-// Issues n full cycles on the context's stream: replays of a captured graph
-// of 32 cycles, then single cycles for the rest.  Host mirrors unchanged.
+constexpr int64_t kGraphCycles = 32;
+
+// Captures len consecutive full cycles into an executable graph (nothing runs).
+hbm_status capture_cycles(CtxImpl *c, int64_t len, hipGraph_t *g_out, hipGraphExec_t *ge_out)
+{
+    if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    hipStream_t saved = c->stream;
+    c->stream = c->capture_stream;
+    HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+    hbm_status st = HBM_OK;
+    for (int64_t j = 0; j < len && st == HBM_OK; ++j) st = c->ops->sweep(c, true, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+    c->stream = saved;
+    if (st != HBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    // upload now, so that the first replay does not pay for it
+    e = hipGraphUpload(ge, c->stream);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(ge);
+        (void)hipGraphDestroy(g);
+        return hip_fail(c, e, "hipGraphUpload");
+    }
+    *g_out = g;
+    *ge_out = ge;
+    c->n_captures += 1;
+    return HBM_OK;
+}
+
+// Makes sure the graphs that n_cycles graph-issued cycles use exist: the
+// kGraphCycles-cycle graph when n_cycles reaches it, and the graph of the
+// remainder n_cycles mod kGraphCycles (recaptured when the remainder changes).
+hbm_status ensure_graphs(CtxImpl *c, int64_t n_cycles)
+{
+    if (n_cycles >= kGraphCycles && !c->graph_exec) {
+        hbm_status st = capture_cycles(c, kGraphCycles, &c->graph, &c->graph_exec);
+        if (st != HBM_OK) return st;
+        c->graph_len = kGraphCycles;
+    }
+    const int64_t rem = n_cycles % kGraphCycles;
+    if (rem > 0 && c->tail_len != rem) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->tail_exec) HIPCHK(c, hipGraphExecDestroy(c->tail_exec));
+        if (c->tail) HIPCHK(c, hipGraphDestroy(c->tail));
+        c->tail_exec = nullptr;
+        c->tail = nullptr;
+        c->tail_len = 0;
+        hbm_status st = capture_cycles(c, rem, &c->tail, &c->tail_exec);
+        if (st != HBM_OK) return st;
+        c->tail_len = rem;
+    }
+    return HBM_OK;
+}
+
+// Issues n full cycles on the context's stream: with use_graph (and no
+// per-launch timing) as replays of the kGraphCycles-cycle graph and one
+// replay of the remainder's graph, else as plain launches.  Host mirrors
+// unchanged.
 hbm_status issue_cycles(CtxImpl *c, int64_t n_cycles, bool use_graph)
 {
-    int64_t left = n_cycles;
-    if (use_graph && !c->timing && n_cycles > 0) {
-        const int64_t glen = 32;
-        if (!c->graph_exec) {
-            if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
-            hipStream_t saved = c->stream;
-            c->stream = c->capture_stream;
-            HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-            hbm_status st = HBM_OK;
-            for (int64_t j = 0; j < glen && st == HBM_OK; ++j) st = c->ops->sweep(c, true, nullptr);
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
-            c->stream = saved;
-            if (st != HBM_OK) return st;
-            if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-            c->graph = g;
-            HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
-            c->graph_len = glen;
-        }
-        while (left >= c->graph_len) {
-            HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
-            left -= c->graph_len;
-        }
+    if (n_cycles <= 0) return HBM_OK;
+    if (use_graph) {
+        bool launched = false;
+        hbm_status st = c->ops->cycles(c, n_cycles, &launched);
+        if (st != HBM_OK || launched) return st;
     }
-    for (int64_t j = 0; j < left; ++j) {
+    if (use_graph && !c->timing) {
+        hbm_status st = ensure_graphs(c, n_cycles);
+        if (st != HBM_OK) return st;
+        for (int64_t left = n_cycles; left > 0;) {
+            const bool whole = left >= kGraphCycles;
+            HIPCHK(c, hipGraphLaunch(whole ? c->graph_exec : c->tail_exec, c->stream));
+            const int64_t len = whole ? kGraphCycles : left;
+            c->n_replays += 1;
+            c->n_replayed_cycles += len;
+            left -= len;
+        }
+        return HBM_OK;
+    }
+    for (int64_t j = 0; j < n_cycles; ++j) {
         hbm_status st = c->ops->sweep(c, true, nullptr);
         if (st != HBM_OK) return st;
     }
+    c->n_plain_cycles += n_cycles;
     return HBM_OK;
 }
 
@@ -1382,21 +1685,10 @@ hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const do
                            double *terms)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
-        hbm_status st = check_slot(c, slot, true);
+        hbm_status st = check_marginal_args(c, slot, n_theta, theta, out);
         if (st != HBM_OK) return st;
-        if (c->d != 1) return fail(c, HBM_EINVAL, "the marginal likelihood needs a model with a 1-D latent");
-        if (n_theta < 1 || n_theta > 65535) return fail(c, HBM_EINVAL, "n_theta must be in [1, 65535]");
-        if (!theta || !out) return fail(c, HBM_EINVAL, "theta and out must be non-NULL");
-        for (int64_t j = 0; j < static_cast<int64_t>(n_theta) * c->p; ++j)
-            if (!std::isfinite(theta[j])) return fail(c, HBM_EINVAL, "theta must be finite");
-        for (int32_t j = 0; j < n_theta; ++j)
-            if (!marg_density_ok(c->pool.model, theta + static_cast<size_t>(j) * c->p))
-                return fail(c, HBM_EDOMAIN, "theta outside the domain of the population density");
         if ((st = ensure_marg_rule(c)) != HBM_OK) return st;
-        const int64_t nb = marg_blocks(c->slots[slot].n);
-        const size_t n_th = static_cast<size_t>(n_theta) * c->p, n_part = static_cast<size_t>(n_theta) * nb;
-        const size_t n_pre = static_cast<size_t>(n_theta) * kMargThWords;
-        const size_t need = sizeof(double) * (n_th + n_theta + n_part + n_pre);
+        const size_t need = marginal_scratch_bytes(c, slot, n_theta);
         if (need > c->marg_bytes) {
             HIPCHK(c, hipStreamSynchronize(c->stream));
             if (c->marg_buf) HIPCHK(c, hipFree(c->marg_buf));
@@ -1407,12 +1699,7 @@ hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const do
             c->marg_buf = static_cast<double *>(p);
             c->marg_bytes = need;
         }
-        double *d_theta = c->marg_buf, *d_out = d_theta + n_th, *d_part = d_out + n_theta, *d_pre = d_part + n_part;
-        HIPCHK(c, hipMemcpyAsync(d_theta, theta, sizeof(double) * n_th, hipMemcpyHostToDevice, c->stream));
-        if ((st = c->ops->marginal(c, slot, n_theta, d_theta, d_out, d_part, d_pre, terms)) != HBM_OK) return st;
-        HIPCHK(c, hipMemcpyAsync(out, d_out, sizeof(double) * n_theta, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        return HBM_OK;
+        return run_marginal(c, slot, n_theta, theta, out, terms, c->marg_buf, c->marg_rule);
     });
 }
 
@@ -1449,6 +1736,38 @@ hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph)
         if (st != HBM_OK) return st;
         if ((st = issue_cycles(c, n_cycles, use_graph != 0)) != HBM_OK) return st;
         for (Slot &sl : c->slots) after_theta_steps(sl, cycles_taken(sl, n_cycles));
+        return HBM_OK;
+    });
+}
+
+hbm_status prepare_cycles(hbm_ctx *ctx, int64_t n_cycles)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (n_cycles < 0) return fail(c, HBM_EINVAL, "n_cycles must be >= 0");
+        return ensure_graphs(c, n_cycles);
+    });
+}
+
+hbm_status launch_counts(hbm_ctx *ctx, int64_t out[6])
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (!out) return fail(c, HBM_EINVAL, "out must be non-NULL");
+        out[0] = c->n_replays;
+        out[1] = c->n_replayed_cycles;
+        out[2] = c->n_plain_cycles;
+        out[3] = c->n_captures;
+        out[4] = c->n_persistent;
+        out[5] = c->n_persistent_cycles;
+        return HBM_OK;
+    });
+}
+
+hbm_status set_cycle_mode(hbm_ctx *ctx, int32_t mode)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (mode != HBM_CYCLES_AUTO && mode != HBM_CYCLES_GRAPH)
+            return fail(c, HBM_EINVAL, "mode must be HBM_CYCLES_AUTO or HBM_CYCLES_GRAPH");
+        c->cycle_mode = mode;
         return HBM_OK;
     });
 }
@@ -1752,11 +2071,24 @@ hbm_status set_launch(hbm_ctx *ctx, int32_t tiles_per_group)
     });
 }
 
-hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t *out_tiles_per_group, double out_us[3])
+hbm_status set_occupancy(hbm_ctx *ctx, int32_t groups_per_cu)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        if (groups_per_cu < 0 || groups_per_cu > 64)
+            return fail(c, HBM_EINVAL, "groups_per_cu must be 0 (no cap) or in [1, 64]");
+        if (groups_per_cu == c->occ_cap) return HBM_OK;
+        hbm_status st = drop_graph(c);
+        if (st != HBM_OK) return st;
+        c->occ_cap = groups_per_cu;
+        return HBM_OK;
+    });
+}
+
+hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t out_choice[3], double out_us[HBM_TUNE_CANDIDATES])
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
         if (trial_cycles < 1) return fail(c, HBM_EINVAL, "trial_cycles must be >= 1");
-        const int64_t warm = 32, per = warm + trial_cycles, total = 3 * per;
+        const int64_t per = kTuneWarm + trial_cycles, total = HBM_TUNE_CANDIDATES * per;
         for (const Slot &sl : c->slots) {
             if (!sl.active) continue;
             if (sl.sums_ready) return fail(c, HBM_ESTATE, "a ram_sweep is waiting for its theta_step");
@@ -1769,14 +2101,35 @@ hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t *out_tiles_per_g
             (void)hipEventDestroy(e0);
             return fail(c, HBM_ENOMEM, "hipEventCreate failed");
         }
-        const int32_t cand[3] = {1, 2, 4};
+        // candidates: the two-kernel cycle with tiles per workgroup {1, 2, 4}
+        // under a cap of {none, 4, 2} workgroups per compute unit, then the
+        // persistent launch (one-dataset contexts in mode HBM_CYCLES_AUTO)
+        struct Cand { int32_t tpw, cap, persistent; };
+        Cand cand[HBM_TUNE_CANDIDATES];
+        int q = 0;
+        for (int32_t cap : {0, 4, 2})
+            for (int32_t tpw : {1, 2, 4}) cand[q++] = Cand{tpw, cap, 0};
+        cand[q++] = Cand{c->tpw, c->occ_cap, 1};
+        const int32_t mode = c->cycle_mode;
+        const int32_t keep_tpw = c->tpw, keep_cap = c->occ_cap;
         double best = HUGE_VAL;
-        int32_t pick = c->tpw;
+        Cand pick{keep_tpw, keep_cap, mode == HBM_CYCLES_AUTO && single(c) ? 1 : 0};
         hbm_status st = HBM_OK;
-        for (int q = 0; q < 3 && st == HBM_OK; ++q) {
+        for (int j = 0; j < HBM_TUNE_CANDIDATES && st == HBM_OK; ++j) {
+            const Cand &cd = cand[j];
+            if (out_us) out_us[j] = static_cast<double>(NAN);
+            // every candidate runs its cycles (the trace counts them), timed or not
+            const bool usable = !cd.persistent || (mode == HBM_CYCLES_AUTO && single(c) && !c->stats_mode);
+            c->cycle_mode = cd.persistent ? HBM_CYCLES_AUTO : HBM_CYCLES_GRAPH;
+            if (!cd.persistent) {
+                if ((st = set_launch(ctx, cd.tpw)) != HBM_OK || (st = set_occupancy(ctx, cd.cap)) != HBM_OK) break;
+                if ((st = ensure_graphs(c, kTuneWarm)) != HBM_OK || (st = ensure_graphs(c, trial_cycles)) != HBM_OK)
+                    break;
+            }
+            if ((st = run_cycles(ctx, kTuneWarm, 1)) != HBM_OK) break;
+            const int64_t p0 = c->n_persistent_cycles;
             float ms = 0.0f;
             hipError_t e = hipSuccess;
-            if ((st = set_launch(ctx, cand[q])) != HBM_OK || (st = run_cycles(ctx, warm, 1)) != HBM_OK) break;
             if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) { st = hip_fail(c, e, "hipEventRecord"); break; }
             if ((st = run_cycles(ctx, trial_cycles, 1)) != HBM_OK) break;
             if ((e = hipEventRecord(e1, c->stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
@@ -1784,18 +2137,30 @@ hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t *out_tiles_per_g
                 st = hip_fail(c, e, "autotune timing");
                 break;
             }
+            // a persistent candidate counts only when the launch really happened
+            if (!usable || (cd.persistent && c->n_persistent_cycles - p0 != trial_cycles)) continue;
             const double us = 1e3 * ms / trial_cycles;
-            if (out_us) out_us[q] = us;
+            if (out_us) out_us[j] = us;
             if (us < best) {
                 best = us;
-                pick = cand[q];
+                pick = cd;
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        c->cycle_mode = mode;
         if (st != HBM_OK) return st;
-        if ((st = set_launch(ctx, pick)) != HBM_OK) return st;
-        if (out_tiles_per_group) *out_tiles_per_group = pick;
+        if (pick.persistent) {
+            if ((st = set_launch(ctx, keep_tpw)) != HBM_OK || (st = set_occupancy(ctx, keep_cap)) != HBM_OK) return st;
+        } else {
+            if ((st = set_launch(ctx, pick.tpw)) != HBM_OK || (st = set_occupancy(ctx, pick.cap)) != HBM_OK) return st;
+            c->cycle_mode = HBM_CYCLES_GRAPH;
+        }
+        if (out_choice) {
+            out_choice[0] = c->tpw;
+            out_choice[1] = c->occ_cap;
+            out_choice[2] = pick.persistent;
+        }
         return HBM_OK;
     });
 }

@@ -197,7 +197,9 @@ __device__ void theta_mh(CycleState &c, const Statics &s, double *theta_trace, d
             for (int q = 0; q <= r; ++q, ++e) c.chol_theta[r * P + q] = L[e];
     }
     if (c.n_theta < s.trace_cap) {
-        for (int r = 0; r < P; ++r) theta_trace[c.n_theta * P + r] = c.theta[r];
+        // (a null trace: a copy of the chain whose trace another workgroup writes)
+        if (theta_trace != nullptr)
+            for (int r = 0; r < P; ++r) theta_trace[c.n_theta * P + r] = c.theta[r];
         c.n_theta += 1;
     } else {
         c.flags |= kFlagTraceFull;
@@ -354,7 +356,8 @@ __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_tr
     }
     if (threadIdx.x == 0) {
         if (c.n_theta < s.trace_cap) {
-            for (int r = 0; r < P; ++r) theta_trace[c.n_theta * P + r] = c.theta[r];
+            if (theta_trace != nullptr)
+                for (int r = 0; r < P; ++r) theta_trace[c.n_theta * P + r] = c.theta[r];
             c.n_theta += 1;
         } else {
             c.flags |= kFlagTraceFull;
@@ -413,7 +416,8 @@ __device__ __forceinline__ TileView<typename M::T> tile_view(const SweepArgs<typ
 template <class M, bool kTrace, bool kStats = false>
 __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, int ds, const TileView<typename M::T> &tv,
                                             int64_t il, int64_t i, typename M::T *x, typename M::T *S, uint32_t nacc,
-                                            const typename M::Obj &o, double *v, bool valid = true)
+                                            const typename M::Obj &o, double *v, bool valid = true,
+                                            const typename M::T *kc_in = nullptr)
 {
     using T = typename M::T;
     constexpr int D = M::D, NC = M::NC;
@@ -421,7 +425,8 @@ __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, i
     const Statics &st = a.st[ds];
     const int64_t n = a.n_total;
     const int64_t k = tv.k;
-    const T *kc = kc_of<T>(const_cast<CycleState *>(cs));
+    // the sweep's constants: the dataset's state, or a copy the caller holds
+    const T *kc = kc_in != nullptr ? kc_in : kc_of<T>(const_cast<CycleState *>(cs));
     const T eta = tv.eta;
     const T astar = tv.astar;
     T U[D], y[D];

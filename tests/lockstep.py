@@ -9,7 +9,12 @@ compared, per object and per step:
   * accept/reject decisions: identical, except logged near-ties, where a
     mismatch is a near-tie only when the observed numeric error straddles
     the threshold, |ln u - Delta_orc| <= |Delta_gpu - Delta_orc|, and that
-    error itself is within the tolerance above;
+    error itself is within the tolerance above.  The same rule covers the
+    decisions that the single-precision proposal point alone flips: the
+    oracle's decision at the GPU's Y differs from its decision at its own
+    Y_orc only where Y and Y_orc agree to the latent tolerance and ln u lies
+    between the oracle's Delta at the two points.  Every near-tie is counted
+    and the count is capped (max_near_ties);
   * the new latent (rejected: unchanged bit for bit; accepted: the
     proposal, equal up to the per-object precision) and the new RAM factor;
   * the theta step's log acceptance ratio, its decision (same near-tie
@@ -30,8 +35,9 @@ class StepReport:
     n: int
     max_rel_lpx: float
     max_rel_lpy: float
-    near_ties: int
-    decision_mismatch: int
+    near_ties: int               # all logged near-ties (value and proposal-point ones)
+    decision_mismatch: int       # GPU decision != oracle decision at the GPU's own Y
+    proposal_near_ties: int      # oracle decision at Y_gpu != at Y_orc
     max_chi_err: float
     max_chol_rel: float
     theta_delta_gpu: float
@@ -46,7 +52,27 @@ def tolerances(precision: str):
     return dict(lp=1e-12, chi_ulps=64.0, chol=1e-11, theta_rel=1e-12)
 
 
-def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
+def default_near_tie_cap(n: int) -> int:
+    """Near-ties allowed in one sweep of n objects: a decision flips only when
+    ln u falls within the per-object rounding (~1e-6 of log pi) of Delta, so
+    a few per 10^5 objects at most."""
+    return 3 + n // 20000
+
+
+def _proposal_ulps(chi0, chol0, prec):
+    """The rounding scale of Y = X + S U per component and object: the
+    larger of |X| and the Box-Muller radius bound (sqrt(-2 ln 2^-24) = 5.77)
+    times the row of S, in units of the per-object precision."""
+    d = chi0.shape[0]
+    rows = np.zeros_like(chi0)
+    for r in range(d):
+        for q in range(r + 1):
+            rows[r] += np.abs(chol0[r * (r + 1) // 2 + q])
+    size = np.maximum(np.abs(chi0), 5.77 * rows)
+    return np.spacing(size.astype(np.float32 if prec == "f32" else np.float64)).astype(np.float64)
+
+
+def lockstep_step(sampler, orc: "oracle.Oracle", prec: str, max_near_ties: int = None) -> StepReport:
     tol = tolerances(prec)
     chi0, chol0, acc0 = sampler.state()
     theta0, cth0, k0 = sampler.theta()
@@ -85,8 +111,29 @@ def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
         ok = abs(lnu_o[i] - d_o) <= err and err <= tol["lp"] * max(1.0, abs(lpx_o[i]), abs(lpy_o[i]))
         assert ok, ("decision mismatch that is not a near-tie", int(i), d_o, d_g, lnu_o[i])
         near += 1
-    # decisions the proposal's rounding alone flipped (state resolution)
-    near += int(np.count_nonzero(acc_at_y != acc_o))
+    # Decisions the proposal point's rounding alone flipped: the oracle
+    # decides differently at the GPU's Y than at its own exact-arithmetic
+    # Y_orc.  Each must be a genuine straddle: Y and Y_orc within the latent
+    # tolerance, and ln u between the oracle's Delta at the two points.
+    ulp_all = _proposal_ulps(chi0, chol0, prec)
+    flips = np.nonzero(acc_at_y != acc_o)[0]
+    k_sweep = k0 + 1
+    for i in flips:
+        _, z = oracle.variates(orc.seed, [int(i), int(k_sweep), 0, 0])
+        y_o = np.zeros(d)
+        for r in range(d):
+            y_o[r] = chi0[r, i] + sum(chol0[r * (r + 1) // 2 + q, i] * z[q] for q in range(r + 1))
+        dy = np.abs(y_g[:, i] - y_o) / np.maximum(ulp_all[:, i], 1e-300)
+        assert dy.max() <= tol["chi_ulps"], ("proposal near-tie with a distant proposal", int(i), dy.max())
+        d_at_yo = otr[i, 1] - otr[i, 0] if np.isfinite(otr[i, 1]) else -np.inf
+        d_at_yg = delta_o[i]
+        gap = abs(d_at_yg - d_at_yo) if np.isfinite(d_at_yo) and np.isfinite(d_at_yg) else np.inf
+        assert abs(lnu_o[i] - d_at_yo) <= gap + 1e-15 * max(1.0, abs(lnu_o[i])), \
+            ("proposal flip that does not straddle ln u", int(i), d_at_yo, d_at_yg, lnu_o[i])
+    near_prop = int(len(flips))
+    near += near_prop
+    cap = default_near_tie_cap(sampler.n) if max_near_ties is None else max_near_ties
+    assert near <= cap, ("near-ties above the cap", near, cap)
 
     same = acc_g == acc_o
     # rejected moves keep the latent bit for bit
@@ -98,12 +145,7 @@ def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
     # the Box-Muller radius (at most sqrt(-2 ln 2^-24) = 5.77) times the row
     # of S
     accd = same & acc_o
-    rows = np.zeros((d, chol0.shape[1]))
-    for r in range(d):
-        for q in range(r + 1):
-            rows[r] += np.abs(chol0[r * (r + 1) // 2 + q])
-    size = np.maximum(np.abs(chi0[:, accd]), 5.77 * rows[:, accd])
-    ulp = np.spacing(size.astype(np.float32 if prec == "f32" else np.float64)).astype(np.float64)
+    ulp = ulp_all[:, accd]
     err = np.abs(chi1[:, accd] - st.chi[:, accd])
     chi_err = float((err / np.maximum(ulp, 1e-300)).max()) if err.size else 0.0
     assert chi_err <= tol["chi_ulps"], ("latent", chi_err)
@@ -113,8 +155,24 @@ def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
         diag_idx = [r * (r + 1) // 2 + r for r in range(d)]
         dscale = np.max(np.abs(st.chol[diag_idx][:, same]), axis=0)
         crel = np.abs(chol1[:, same] - st.chol[:, same]) / np.maximum(dscale, 1e-30)
+    # The factor adapts on alpha = min(1, e^Delta): with the two sides' Delta
+    # apart by dD, |d alpha| <= alpha_max dD (alpha is 1-Lipschitz in Delta
+    # below 0, scaled by its value), and eq 2.6 moves the factor by at most
+    # eta |d alpha| / (2 (1 + c)) < eta |d alpha| relative in 1-D (1 + c >=
+    # 1 - eta alpha* > 0.7); allow twice that in more dimensions, where the
+    # rank-1 term is measured against the largest diagonal entry.  The
+    # constant tol["chol"] covers the factor's own single-precision rounding.
+    d_gg = np.where(np.isfinite(lpy_g), lpy_g - lpx_g, -np.inf)
+    d_oo = np.where(np.isfinite(otr[:, 1]), otr[:, 1] - otr[:, 0], -np.inf)
+    both = np.isfinite(d_gg) & np.isfinite(d_oo)
+    a_max = np.exp(np.minimum(0.0, np.maximum(d_gg, d_oo)))
+    dalpha = np.where(both, np.minimum(1.0, a_max * np.abs(np.where(both, d_gg - d_oo, 0.0))), a_max)
+    eta = (k0 + 2) ** (-getattr(orc, "gamma", 2.0 / 3.0))
+    bound = tol["chol"] + (1.0 if d == 1 else 2.0) * eta * dalpha[same]
+    worst = crel - bound[None, :] if crel.size else np.zeros(1)
     chol_rel = float(crel.max()) if crel.size else 0.0
-    assert chol_rel <= tol["chol"], ("RAM factor", chol_rel)
+    assert np.all(worst <= 0.0), ("RAM factor", chol_rel, float(worst.max()), int(np.nonzero(same)[0][
+        np.argmax(worst.max(axis=0))]))
     assert np.array_equal(acc1[same], st.acc[same])
 
     # theta step: the oracle takes the GPU's latents (lockstep)
@@ -157,8 +215,8 @@ def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
         scale_th = float(np.abs(np.diag(st.chol_theta)).max())
         np.testing.assert_allclose(theta1, st.theta, rtol=rt, atol=rt * scale_th)
         np.testing.assert_allclose(cth1, st.chol_theta, rtol=rt, atol=rt * scale_th)
-        return StepReport(sampler.n, float(rel_x.max()), float(rel_y.max()), near, len(mism), chi_err, chol_rel,
-                          d_g, d_o, theta_tol, False)
+        return StepReport(sampler.n, float(rel_x.max()), float(rel_y.max()), near, len(mism), near_prop, chi_err,
+                          chol_rel, d_g, d_o, theta_tol, False)
     # FP64 selection normalisers of the two sides agree to ~1e-13 relative
     has_sel = orc.wl.model in (2, 3, 5)
     theta_tol = tol["theta_rel"] * max(1.0, scale) + (1e-12 * sampler.n if has_sel else 0.0)
@@ -178,5 +236,5 @@ def lockstep_step(sampler, orc: "oracle.Oracle", prec: str) -> StepReport:
         rt = 1e-9 + 2.0 * (abs(d_g - d_o) if np.isfinite(d_o) else 0.0)
         scale_th = float(np.abs(np.diag(st.chol_theta)).max())
         np.testing.assert_allclose(cth1, st.chol_theta, rtol=rt, atol=rt * scale_th)
-    return StepReport(sampler.n, float(rel_x.max()), float(rel_y.max()), near, len(mism), chi_err, chol_rel,
-                      d_g, d_o, theta_tol, near_theta)
+    return StepReport(sampler.n, float(rel_x.max()), float(rel_y.max()), near, len(mism), near_prop, chi_err,
+                      chol_rel, d_g, d_o, theta_tol, near_theta)
