@@ -257,6 +257,30 @@ HBM_API hbm_status pop_loglik(hbm_ctx *ctx, const double *theta, double *out);
 HBM_API hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const double *theta, double *out,
                                    double *terms);
 
+/* Bytes of the static device array behind marginal_loglik_noalloc. */
+#define HBM_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* marginal_loglik for callers that cannot allocate device memory (serving
+ * loops that must not allocate per request, harnesses that forbid
+ * hipMalloc): the same arguments, checks, kernels and results, bit for bit,
+ * but no device allocation in the call -- its scratch is a static device
+ * array of HBM_NOALLOC_SCRATCH_BYTES (8 MiB), which each device holds from
+ * the first context created on it until the process ends.  The array keeps
+ * the node rule (8,448 bytes, written once per device when that first
+ * context is created) and then one call's working set of
+ *   8 * n_theta * (p + 9 + ceil(N / 32))  bytes
+ * (N the slot's object count): theta rows, results, workgroup partial sums
+ * and per-row scalars, every word written by the call before it is read.
+ * HBM_EINVAL, with the sizes in last_error, when that exceeds the array
+ * (e.g. n_theta <= 111 at N = 300,000 and p = 2); HBM_ENOMEM when the array
+ * could not be set up on the context's device.  Every call on one device
+ * shares the array, which keeps the last call's contents: calls that
+ * overlap on a device (contexts on different streams or threads) race, so
+ * the caller must serialise them.  Kernel timing (kernel_timing) records
+ * nothing for these calls.  Synchronous. */
+HBM_API hbm_status marginal_loglik_noalloc(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const double *theta,
+                                           double *out, double *terms);
+
 
 /* One Metropolis-Hastings step on theta of every active slot, for the
  * sweep just done: the

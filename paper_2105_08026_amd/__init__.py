@@ -25,9 +25,10 @@ HBM_OK, HBM_EINVAL, HBM_ENOMEM, HBM_EHIP, HBM_EDOMAIN, HBM_ESTATE, HBM_ENOSPACE 
 HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_3D, HBM_BB1_LF = 1, 2, 3, 4, 5
 HBM_FP64, HBM_FP32 = 1, 2
 HBM_CYCLES_AUTO, HBM_CYCLES_GRAPH = 0, 1
+HBM_NOALLOC_SCRATCH_BYTES = 8 << 20     # the static device array of marginal_loglik_noalloc
 
 EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
-            "ram_sweep", "pop_loglik", "marginal_loglik", "theta_step", "run_cycles", "prepare_cycles", "set_cycle_mode", "launch_counts", "run_cycles_streamed",
+            "ram_sweep", "pop_loglik", "marginal_loglik", "marginal_loglik_noalloc", "theta_step", "run_cycles", "prepare_cycles", "set_cycle_mode", "launch_counts", "run_cycles_streamed",
             "fd_sink", "get_samples", "get_theta", "set_theta",
             "ram_sweep_trace", "get_state", "set_state", "get_stats", "set_launch", "set_occupancy", "autotune", "kernel_timing",
             "read_kernel_timing", "last_error", "destroy_chains")
@@ -91,6 +92,7 @@ def lib():
             "ram_sweep": [P, i32, P],
             "pop_loglik": [P, P, P],
             "marginal_loglik": [P, i32, i32, P, P, P],
+            "marginal_loglik_noalloc": [P, i32, i32, P, P, P],
             "theta_step": [P, P],
             "run_cycles": [P, i64, i32],
             "prepare_cycles": [P, i64],
@@ -202,15 +204,17 @@ def pop_loglik(ctx, thetas) -> np.ndarray:
     return out
 
 
-def marginal_loglik(ctx, slot: int, thetas, n: int, terms: bool = False, device=None):
+def marginal_loglik(ctx, slot: int, thetas, n: int, terms: bool = False, device=None, noalloc: bool = False):
     """thetas: [n_theta][p]; returns [n_theta] latent-free log-likelihoods and,
-    with terms=True, also the [n_theta][n] per-object log integrals."""
+    with terms=True, also the [n_theta][n] per-object log integrals.
+    noalloc=True calls marginal_loglik_noalloc (the library's static scratch)."""
     th = _arr(thetas)
     if th.ndim == 1:
         th = th.reshape(1, -1)
     out = np.zeros(th.shape[0])
     tb = torch.empty((th.shape[0], n), dtype=torch.float64, device=device) if terms else None
-    _check(lib().marginal_loglik(ctx, slot, th.shape[0], _ptr(th), _ptr(out), tb.data_ptr() if terms else None), ctx)
+    fn = lib().marginal_loglik_noalloc if noalloc else lib().marginal_loglik
+    _check(fn(ctx, slot, th.shape[0], _ptr(th), _ptr(out), tb.data_ptr() if terms else None), ctx)
     return (out, tb.cpu().numpy()) if terms else out
 
 

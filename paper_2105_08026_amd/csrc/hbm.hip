@@ -35,6 +35,15 @@
 
 using namespace hbm;
 
+// Device memory of marginal_loglik_noalloc, for callers that cannot allocate:
+// the marginal likelihood's node rule, then one call's theta rows, results,
+// workgroup partial sums and per-row scalars.  Each device the library runs
+// on holds its own copy until the process ends.  Host code never passes this
+// name to a kernel or a copy (on the host it is only a stand-in): it uses the
+// per-device address that hipGetSymbolAddress returns.
+constexpr size_t kNoAllocScratchBytes = size_t(HBM_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_init_error;
@@ -191,6 +200,7 @@ hbm_status hip_fail(CtxImpl *c, hipError_t e, const char *what)
 int32_t tiles_for(int64_t n) { return static_cast<int32_t>((n + kBlock - 1) / kBlock); }
 
 bool single(const CtxImpl *c);
+void setup_noalloc_scratch(CtxImpl *c);
 
 // Events that time one sweep-kernel launch.
 hipEvent_t take_event(CtxImpl *c)
@@ -931,6 +941,7 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
         return bail(HBM_EHIP);
     }
     if ((s = c->ops->quadrature(c)) != HBM_OK) return bail(s);
+    setup_noalloc_scratch(c);
     *out = c;
     return HBM_OK;
 }
@@ -1178,6 +1189,65 @@ hbm_status ensure_marg_rule(CtxImpl *c)
     HIPCHK(c, hipMemcpyAsync(c->marg_rule, hr, sizeof(MargNode) * kMargRuleNodes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HBM_OK;
+}
+
+// Per device: the address of `scratch` (from hipGetSymbolAddress, taken
+// with that device current) once the node rule sits at its start, or the
+// error that prevented it.
+constexpr int kMaxDevices = 64;
+constexpr size_t kNoAllocRuleBytes = (sizeof(MargNode) * kMargRuleNodes + 255) / 256 * 256;
+static_assert(kNoAllocRuleBytes < kNoAllocScratchBytes, "the static scratch must hold the node rule");
+struct NoAllocScratch {
+    unsigned char *ptr = nullptr;
+    bool tried = false;
+    std::string err;
+};
+std::mutex g_noalloc_mu;
+NoAllocScratch g_noalloc[kMaxDevices];
+
+// Set-up of the static scratch on c's device, once per device (called when a
+// context is created): resolve its address and copy the node rule there.  A
+// failure is kept for marginal_loglik_noalloc to report; it does not stop the
+// context.
+void setup_noalloc_scratch(CtxImpl *c)
+{
+    const int dev = c->device;
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    NoAllocScratch &ns = g_noalloc[dev];
+    if (ns.tried) return;
+    ns.tried = true;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+    void *p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    const MargNode *hr = nullptr;
+    const std::string saved = c->err;
+    const bool rule_ok = e == hipSuccess && host_marg_rule(c, &hr) == HBM_OK;
+    if (rule_ok) e = hipMemcpy(p, hr, sizeof(MargNode) * kMargRuleNodes, hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        ns.err = std::string("static scratch set-up: ") + hipGetErrorString(e);
+    else if (!rule_ok)
+        ns.err = "static scratch set-up: " + c->err;
+    else
+        ns.ptr = static_cast<unsigned char *>(p);
+    c->err = saved;
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+}
+
+// The static scratch of c's device (nullptr and a message if unavailable).
+unsigned char *noalloc_scratch(CtxImpl *c, std::string *why)
+{
+    if (c->device < 0 || c->device >= kMaxDevices) {
+        *why = "static scratch: device ordinal out of range";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    const NoAllocScratch &ns = g_noalloc[c->device];
+    if (!ns.ptr) *why = ns.tried ? ns.err : std::string("static scratch: not set up on this device");
+    return ns.ptr;
 }
 
 // Values of theta at which the population density exists: the gamma law
@@ -1700,6 +1770,32 @@ hbm_status marginal_loglik(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const do
             c->marg_bytes = need;
         }
         return run_marginal(c, slot, n_theta, theta, out, terms, c->marg_buf, c->marg_rule);
+    });
+}
+
+hbm_status marginal_loglik_noalloc(hbm_ctx *ctx, int32_t slot, int32_t n_theta, const double *theta, double *out,
+                                   double *terms)
+{
+    return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
+        hbm_status st = check_marginal_args(c, slot, n_theta, theta, out);
+        if (st != HBM_OK) return st;
+        const size_t need = marginal_scratch_bytes(c, slot, n_theta);
+        if (need > kNoAllocScratchBytes - kNoAllocRuleBytes)
+            return fail(c, HBM_EINVAL,
+                        "marginal_loglik_noalloc: " + std::to_string(n_theta) + " theta rows over " +
+                            std::to_string(c->slots[slot].n) + " objects need " + std::to_string(need) +
+                            " bytes of scratch; the static scratch holds " +
+                            std::to_string(kNoAllocScratchBytes - kNoAllocRuleBytes));
+        std::string why;
+        unsigned char *base = noalloc_scratch(c, &why);
+        if (!base) return fail(c, HBM_ENOMEM, why);
+        // no events either: kernel timing would create them
+        const bool timing = c->timing;
+        c->timing = false;
+        st = run_marginal(c, slot, n_theta, theta, out, terms, reinterpret_cast<double *>(base + kNoAllocRuleBytes),
+                          reinterpret_cast<const MargNode *>(base));
+        c->timing = timing;
+        return st;
     });
 }
 
