@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="plain launches (sweep + epilogue kernel per cycle)")
     ap.add_argument("--graph-cycles", action="store_true",
                     help="graph replays of the two-kernel cycle instead of the persistent launch")
+    ap.add_argument("--fused-cycles", action="store_true",
+                    help="graph replays of fused cycles (one launch per cycle) with the given --launch-shape")
     ap.add_argument("--launch-shape", default="auto", choices=["auto", "1", "2", "4"],
                     help="tiles per sweep workgroup; auto runs the autotuner during burn-in")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -394,7 +396,10 @@ def bench_serving(args, torch, synth, hbm):
     sv.serve(jobs_of([(0.0, 1, 2000, 64), (0.0, 2, 50000, 96)]), ex, prefetch=False)
 
     live = jobs_of(synth.serving_arrivals(rate=args.rate, horizon_s=args.horizon, seed=4))
-    res = sv.serve(live, ex)
+
+    def report(done, total, t):
+        print(f"poisson: {done}/{total} jobs done after {t:.0f} s", file=sys.stderr, flush=True)
+    res = sv.serve(live, ex, progress=report)
     print(f"poisson: {len(live)} jobs, p50 {res['p50_s']*1e3:.1f} ms, p99 {res['p99_s']*1e3:.1f} ms, "
           f"mean resident {res['mean_resident']:.2f}", file=sys.stderr, flush=True)
 
@@ -665,12 +670,15 @@ def main():
     use_graph = not args.no_graph
     if args.graph_cycles:
         s.set_cycle_mode(hbm.HBM_CYCLES_GRAPH)
+    if args.fused_cycles:
+        s.set_cycle_mode(hbm.HBM_CYCLES_FUSED)
 
     # burn-in: the launch-shape autotuner's cycles (or a fixed shape), then warm-up cycles
     if args.launch_shape == "auto":
         pick, tuned = s.autotune(trial)
     else:
-        pick, tuned = {"tiles_per_group": int(args.launch_shape), "groups_per_cu": 0, "persistent": None}, None
+        pick, tuned = {"tiles_per_group": int(args.launch_shape), "groups_per_cu": 0, "persistent": None,
+                       "fused": None}, None
         s.set_launch(pick["tiles_per_group"])
     s.run_cycles(args.warmup, use_graph=use_graph)
     if use_graph:
@@ -689,10 +697,12 @@ def main():
     issued = {key: lc1[key] - lc0[key] for key in lc0}
     assert issued["replayed_cycles"] + issued["plain_cycles"] + issued["persistent_cycles"] == args.steps, issued
     persistent = issued["persistent_launches"] > 0
+    fused = bool(pick.get("fused") or args.fused_cycles) and issued["replayed_cycles"] == args.steps
 
     # Timed region 2: the same way of issuing, each launch bracketed by HIP
     # events on the sampler's stream, for the dominant kernel's duration (the
-    # persistent kernel; with graphs, the sweep kernel of plain launches).
+    # persistent kernel; the fused-cycle kernel of plain fused launches; with
+    # two-kernel graphs, the sweep kernel of plain launches).
     hbm.kernel_timing(s.ctx, True)
     s.run_cycles(args.steps, use_graph=use_graph)
     n_launch_dom, dom_ms = hbm.read_kernel_timing(s.ctx)
@@ -707,7 +717,7 @@ def main():
     hbm.kernel_timing(s.ctx, False)
     # The two-kernel cycle replayed from graphs, for comparison.
     mode_graph = None
-    if persistent:
+    if persistent or fused:
         s.set_cycle_mode(hbm.HBM_CYCLES_GRAPH)
         s.prepare_cycles(args.steps)
         torch.cuda.synchronize()
@@ -715,7 +725,7 @@ def main():
         s.run_cycles(args.steps)
         torch.cuda.synchronize()
         mode_graph = time.perf_counter() - t2
-        s.set_cycle_mode(hbm.HBM_CYCLES_AUTO)
+        s.set_cycle_mode(hbm.HBM_CYCLES_FUSED if fused else hbm.HBM_CYCLES_AUTO)
 
     th = s.theta_trace()
     assert np.all(np.isfinite(th)), "non-finite theta"
@@ -755,6 +765,20 @@ def main():
                 "launch_ms": dom_ms, "us_per_cycle_in_kernel": 1e3 * cyc_ms, "launches_timed": n_launch_dom,
                 "valu": valu_roof(traffic, cyc_ms), **planned_frac(wl.name, wl.n, cyc_ms),
                 "sweep_kernel_two_kernel_cycle": sweep_roof}
+    elif fused:
+        # one fused launch = one cycle: the previous sweep's theta step in every
+        # workgroup, then the sweep of N objects
+        achieved = bpu * wl.n / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
+        traffic = measured_traffic(wl.name, wl.n, "fused")
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": (traffic["bytes_per_launch"] / (dom_ms * 1e-3) / 1e9) if traffic else None,
+                "traffic_bytes_per_launch": traffic["bytes_per_launch"] if traffic else None,
+                "algorithmic_bytes_per_launch": bpu * wl.n, "bytes_per_update": bpu,
+                "traffic_source": traffic["source"] if traffic else "no counter summary for the current kernel sources",
+                "kernel": f"fused_kernel<{wl.name}>", "kernel_ms": dom_ms, "launches_timed": n_launch_dom,
+                "valu": valu_roof(traffic, dom_ms), **planned_frac(wl.name, wl.n, dom_ms),
+                "sweep_kernel_two_kernel_cycle": sweep_roof}
     else:
         roof = {"bound": "hbm", "achieved": sweep_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (sweep_gbs / HBM_PEAK_GBS) if sweep_gbs else None,
@@ -778,10 +802,11 @@ def main():
         "data": f"synthetic (seeded {wl.name} catalog)",
         "config": {"workload": wl.name, "n_objects": wl.n, "latent_dim": wl.d, "theta_dim": wl.p,
                    "selection_quadrature_nodes": 512 if wl.model in (2, 3, 5) else 0,
-                   "persistent_launch": persistent,
+                   "persistent_launch": persistent, "fused_cycles": fused,
                    "graph": issued["graph_replays"] > 0 and issued["plain_cycles"] == 0,
                    "sweeps_per_step": 1, "tiles_per_workgroup": pick["tiles_per_group"],
                    "groups_per_cu_cap": pick["groups_per_cu"], "autotune_picked_persistent": pick["persistent"],
+                   "autotune_picked_fused": pick.get("fused"),
                    "theta_substeps": args.theta_substeps},
         "timed_cycles_issued": issued,
         "theta_ess_per_s": [e / wall if e else None for e in ess],
@@ -790,7 +815,8 @@ def main():
         "breakdown_ms": {"step": 1e3 * wall / args.steps, "sweep_kernel": kern_ms,
                          "step_two_kernel_plain_launches_event_timed": 1e3 * wall_ev / args.steps,
                          "step_two_kernel_graph_replay": 1e3 * mode_graph / args.steps if mode_graph else None,
-                         "persistent_launch_ms": dom_ms if persistent else None},
+                         "persistent_launch_ms": dom_ms if persistent else None,
+                         "fused_kernel": dom_ms if fused else None},
         "roofline": roof,
         "accept_rate_last_sweep": stats["n_acc"] / wl.n,
         "theta_last": th[-1].tolist(),

@@ -119,6 +119,7 @@ typedef int32_t hbm_status;
 /* How run_cycles issues fused cycles (set_cycle_mode). */
 #define HBM_CYCLES_AUTO  0  /* one persistent launch where possible, else graphs */
 #define HBM_CYCLES_GRAPH 1  /* always graphs (or plain launches) */
+#define HBM_CYCLES_FUSED 2  /* graphs of fused cycles (one launch per cycle) where possible */
 
 typedef struct hbm_config {
     int32_t model;               /* HBM_* model id */
@@ -296,7 +297,7 @@ HBM_API hbm_status marginal_loglik_noalloc(hbm_ctx *ctx, int32_t slot, int32_t n
 HBM_API hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted);
 
 /* n_cycles full cycles (sweep then theta step) of every active slot, with
- * no host round trip between cycles.  Three ways to issue them, all giving
+ * no host round trip between cycles.  Four ways to issue them, all giving
  * bit-identical chains (and the chain of alternating ram_sweep(1) and
  * theta_step):
  *   - use_graph == 0: per cycle, the sweep kernel and an epilogue kernel
@@ -310,7 +311,8 @@ HBM_API hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted);
  *   - otherwise with use_graph != 0: replays of captured hipGraphs,
  *     floor(n / 32) of a 32-cycle graph and one of a graph of the remaining
  *     n mod 32 cycles (captured on first need, again when the remainder
- *     changes; prepare_cycles captures ahead).
+ *     changes; prepare_cycles captures ahead); in mode HBM_CYCLES_FUSED a
+ *     one-dataset context's graphs hold fused cycles (set_cycle_mode).
  * A slot whose budget is reached stops at that cycle.  Asynchronous. */
 HBM_API hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph);
 
@@ -320,7 +322,15 @@ HBM_API hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph)
 HBM_API hbm_status prepare_cycles(hbm_ctx *ctx, int64_t n_cycles);
 
 /* mode: HBM_CYCLES_AUTO (default) lets run_cycles use the persistent
- * launch where it can; HBM_CYCLES_GRAPH restricts it to graphs. */
+ * launch where it can; HBM_CYCLES_GRAPH restricts it to graphs of the
+ * two-kernel cycle; HBM_CYCLES_FUSED makes the graphs of a one-dataset
+ * context (init_chains) hold fused cycles: after the first sweep kernel, one
+ * launch per cycle in which every workgroup takes the previous sweep's theta
+ * step itself (from that sweep's tile partials, in the epilogue's fixed
+ * order) and then sweeps its tiles, buffers alternating between cycles, and
+ * one epilogue at the end -- the same chain, bit for bit.  Contexts with
+ * several slots keep the two-kernel graphs.  Changing to or from
+ * HBM_CYCLES_FUSED drops the captured graphs.  Synchronous. */
 HBM_API hbm_status set_cycle_mode(hbm_ctx *ctx, int32_t mode);
 
 /* How run_cycles has issued cycles since the context was created:
@@ -425,28 +435,33 @@ HBM_API hbm_status set_occupancy(hbm_ctx *ctx, int32_t groups_per_cu);
  * order: the two-kernel cycle replayed from graphs with tiles per workgroup
  * 1, 2, 4 under no occupancy cap (candidates 0-2), a cap of 4 (3-5) and a
  * cap of 2 workgroups per compute unit (6-8); then the persistent launch
- * (9; one-dataset contexts in mode HBM_CYCLES_AUTO, else not timed).  Each
+ * (9; one-dataset contexts in mode HBM_CYCLES_AUTO, else not timed); then
+ * graphs of fused cycles with tiles per workgroup 1, 2, 4 and no cap
+ * (10-12; one-dataset contexts, else not timed).  Each
  * runs 8 warm-up cycles then trial_cycles cycles timed by hipEvents on the
  * context's stream; the fastest is kept: its shape and cap, and the cycle
- * mode (HBM_CYCLES_AUTO when the persistent launch won, else
- * HBM_CYCLES_GRAPH).  The cycles are real cycles of every active slot
+ * mode (HBM_CYCLES_AUTO when the persistent launch won, HBM_CYCLES_FUSED when
+ * fused cycles did, else HBM_CYCLES_GRAPH).  The cycles are real cycles of every active slot
  * (HBM_TUNE_CANDIDATES (8 + trial_cycles) of them, counted against
  * max_cycles); results do not depend on the choice, so tuning during burn-in
  * changes no chain.  out_choice (nullable): [3] tiles per workgroup,
- * workgroups-per-CU cap (0: none), persistent (0/1); out_us (nullable):
+ * workgroups-per-CU cap (0: none), how cycles run (0: two-kernel graphs, 1:
+ * persistent launch, 2: fused graphs); out_us (nullable):
  * [HBM_TUNE_CANDIDATES] microseconds per cycle (NaN: not timed).
  * Synchronous. */
-#define HBM_TUNE_CANDIDATES 10
+#define HBM_TUNE_CANDIDATES 13
 HBM_API hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t out_choice[3],
                             double out_us[HBM_TUNE_CANDIDATES]);
 
-/* Per-launch duration of the sweep, persistent-cycle and marginal kernels:
- * when enabled, every launch of the sweep or marginal kernel carries a start
- * and a stop hipEvent that the runtime records from the dispatch itself
- * (hipExtLaunchKernel), every persistent launch is bracketed by events
- * recorded on the stream, and run_cycles issues plain launches where it
- * would replay graphs.  read returns the launches timed and their mean
- * duration in ms and resets the counters.  Synchronous read. */
+/* Per-launch duration of the sweep, fused-cycle, persistent-cycle and
+ * marginal kernels: when enabled, every launch of the sweep, fused or
+ * marginal kernel carries a start and a stop hipEvent that the runtime
+ * records from the dispatch itself (hipExtLaunchKernel), every persistent
+ * launch is bracketed by events recorded on the stream, and run_cycles
+ * issues plain launches where it would replay graphs (in mode
+ * HBM_CYCLES_FUSED, the fused sequence, timing its fused kernels only).
+ * read returns the launches timed and their mean duration in ms and resets
+ * the counters.  Synchronous read. */
 HBM_API hbm_status kernel_timing(hbm_ctx *ctx, int32_t enable);
 HBM_API hbm_status read_kernel_timing(hbm_ctx *ctx, int64_t *n_launches, double *mean_ms);
 

@@ -24,7 +24,7 @@ from .serve import TileAllocator
 HBM_OK, HBM_EINVAL, HBM_ENOMEM, HBM_EHIP, HBM_EDOMAIN, HBM_ESTATE, HBM_ENOSPACE = 0, -1, -2, -3, -4, -5, -6
 HBM_NORMAL_NORMAL_1D, HBM_GAMMA_LF_1D, HBM_GAMMA_LF_COLOR_3D, HBM_NORMAL_NORMAL_3D, HBM_BB1_LF = 1, 2, 3, 4, 5
 HBM_FP64, HBM_FP32 = 1, 2
-HBM_CYCLES_AUTO, HBM_CYCLES_GRAPH = 0, 1
+HBM_CYCLES_AUTO, HBM_CYCLES_GRAPH, HBM_CYCLES_FUSED = 0, 1, 2
 HBM_NOALLOC_SCRATCH_BYTES = 8 << 20     # the static device array of marginal_loglik_noalloc
 
 EXPORTED = ("init_chains", "init_batch", "create_pool", "load_datasets", "unload_dataset", "slot_info",
@@ -337,7 +337,7 @@ def set_occupancy(ctx, groups_per_cu: int):
     _check(lib().set_occupancy(ctx, groups_per_cu), ctx)
 
 
-TUNE_CANDIDATES = 10      # HBM_TUNE_CANDIDATES
+TUNE_CANDIDATES = 13      # HBM_TUNE_CANDIDATES
 TUNE_WARM = 8             # warm-up cycles per candidate
 
 
@@ -348,7 +348,8 @@ def autotune_cycles(trial_cycles: int) -> int:
 
 def tune_labels():
     """Names of the autotuner's candidates, in its order."""
-    return [f"tpw{t}_cap{c}" for c in (0, 4, 2) for t in (1, 2, 4)] + ["persistent"]
+    return ([f"tpw{t}_cap{c}" for c in (0, 4, 2) for t in (1, 2, 4)] + ["persistent"]
+            + [f"fused_tpw{t}" for t in (1, 2, 4)])
 
 
 def autotune(ctx, trial_cycles: int = 64):
@@ -357,7 +358,8 @@ def autotune(ctx, trial_cycles: int = 64):
     ch = np.zeros(3, dtype=np.int32)
     us = np.zeros(TUNE_CANDIDATES)
     _check(lib().autotune(ctx, trial_cycles, _ptr(ch), _ptr(us)), ctx)
-    return {"tiles_per_group": int(ch[0]), "groups_per_cu": int(ch[1]), "persistent": bool(ch[2])}, us
+    return {"tiles_per_group": int(ch[0]), "groups_per_cu": int(ch[1]), "persistent": int(ch[2]) == 1,
+            "fused": int(ch[2]) == 2}, us
 
 
 def kernel_timing(ctx, enable: bool):

@@ -22,6 +22,9 @@ HIPCC_FLAGS = [
     "-fvisibility=hidden",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-add fusion decided per source expression (never by how a
+    # function was inlined), so every launch shape computes the same bits
+    "-ffp-contract=on",
     "-Wall",
 ]
 

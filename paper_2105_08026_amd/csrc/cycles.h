@@ -40,7 +40,6 @@
 
 namespace hbm {
 
-constexpr int kKc = 16;              // per-sweep constants the models read (kc[0..15])
 constexpr int kXchCols = 2 + kMaxStats;   // most columns of lane sums (statistics path)
 constexpr int kMaxLanesPerGroup = 4;       // W >= 64
 
@@ -62,19 +61,6 @@ __device__ __forceinline__ uint64_t *xch_word(uint64_t *x, int buf, int col, int
     return x + ((static_cast<int64_t>(buf) * kXchCols + col) * 2 + half) * kBlock + lane;
 }
 
-// A value read in one lane made uniform (scalar registers).
-__device__ __forceinline__ float uniform_of(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ double uniform_of(double v)
-{
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<int>(b & 0xffffffffu));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32));
-    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
-}
-
 // B: tiles whose loads and steps are issued together.
 template <class M, int B, bool kStats>
 __global__ __launch_bounds__(kBlock) void cycles_kernel(CyclesArgs<typename M::T> a)
@@ -87,8 +73,8 @@ __global__ __launch_bounds__(kBlock) void cycles_kernel(CyclesArgs<typename M::T
     constexpr int kRed = kCols * B > NCOL ? kCols * B : NCOL;
     __shared__ CycleState c;
     __shared__ Precomp pc;
-    __shared__ double red[kRed][kWavesPerBlock];
-    __shared__ double zred[1][kWavesPerBlock];
+    __shared__ double red[kRed][kBlock];
+    __shared__ double zred[1][kBlock];
     __shared__ uint32_t nacc_w[B][kWavesPerBlock];
     __shared__ double lsum[kMaxLanesPerGroup][NCOL];     // this workgroup's lane sums (thread 0)
 

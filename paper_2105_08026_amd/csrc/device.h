@@ -230,8 +230,9 @@ __device__ __forceinline__ void ram_adapt(T *S, const T *U, T c)
 
 // ---------------------------------------------------------------------------
 // Deterministic reductions.  A wavefront sums with fixed DPP steps; a
-// workgroup adds its four wave sums in fixed order.  The result depends only
-// on the values and their lane positions, never on timing.
+// workgroup first adds, lane by lane, the values of its four wavefronts in a
+// fixed order.  The result depends only on the values and their lane
+// positions, never on timing.
 // ---------------------------------------------------------------------------
 // One DPP move of a double (both 32-bit halves) into the rows of kRowMask.
 // Lanes of other rows keep whatever their destination register held: callers
@@ -272,20 +273,25 @@ __device__ __forceinline__ double wave_sum(double v)
     return lane_f64(v, 63);
 }
 
-// Sums NV values over the workgroup; result valid in thread 0.
+// Sums NV values over the workgroup; result valid in thread 0.  Every
+// thread leaves its values in LDS; wavefront 0 alone adds, lane by lane, the
+// four values of lanes l, l + 64, l + 128, l + 192 as (w0 + w1) + (w2 + w3)
+// and reduces its 64 lane sums with wave_sum -- one wavefront's DPP steps per
+// value instead of four.  lds: [NV][256] doubles.
 template <int NV>
-__device__ __forceinline__ void block_sum(double *v, double (*lds)[kWavesPerBlock])
+__device__ __forceinline__ void block_sum(double *v, double (*lds)[kBlock])
 {
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const double s = wave_sum(v[q]);
-        if (lane == 0) lds[q][wave] = s;
-    }
+    for (int q = 0; q < NV; ++q) lds[q][threadIdx.x] = v[q];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {
+        const int l = threadIdx.x;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] = (lds[q][0] + lds[q][1]) + (lds[q][2] + lds[q][3]);
+        for (int q = 0; q < NV; ++q) {
+            const double s = (lds[q][l] + lds[q][l + kWave]) + (lds[q][l + 2 * kWave] + lds[q][l + 3 * kWave]);
+            const double r = wave_sum(s);
+            if (l == 0) v[q] = r;
+        }
     }
 }
 

@@ -70,6 +70,7 @@ struct Launch {
     // n full cycles as one persistent cooperative launch; *launched = false
     // (and nothing enqueued) when the context or device cannot take it
     hbm_status (*cycles)(CtxImpl *, int64_t n, bool *launched);
+    hbm_status (*fused)(CtxImpl *, int64_t len);  // len >= 2 fused cycles of a one-dataset context
 };
 
 // Host mirror of one slot.  Every field follows from the calls made, so the
@@ -106,6 +107,10 @@ struct CtxImpl {
     double *pout = nullptr;         // [n_slots][2] results of pop_loglik
     double *theta_in = nullptr;     // [n_slots][p] arguments of pop_loglik
     Precomp *side = nullptr;        // [n_slots] values the side workgroups leave for the epilogue
+    // the other buffers of a fused run: chain states, tile partials, side values
+    CycleState *cs_alt = nullptr;
+    double *partials_alt = nullptr;
+    Precomp *side_alt = nullptr;
     double *ref_t = nullptr, *ref_w = nullptr;       // [nq]
     double *qx = nullptr, *qw = nullptr, *qeps = nullptr;   // [n_slots][nq]
     CycleState *cs = nullptr;       // [n_slots]
@@ -376,10 +381,84 @@ struct Ops {
                                a);
     }
 
+    // len >= 2 full cycles of a one-dataset context with one launch per
+    // cycle after the first: the sweep kernel (its state, partials and side
+    // values in the primary buffers), len - 1 fused kernels, each taking the
+    // previous sweep's theta step and running the next sweep with the buffers
+    // alternating, then the last sweep's epilogue, which leaves the state in
+    // the primary buffer.
+    static hbm_status fused(CtxImpl *c, int64_t len)
+    {
+        if constexpr (M::NS > 0) {
+            if (c->stats_mode) return fused_as<true>(c, len);
+        }
+        return fused_as<false>(c, len);
+    }
+
+    template <bool kStats>
+    static hbm_status fused_as(CtxImpl *c, int64_t len)
+    {
+        const SweepArgs<T> a = sweep_args(c, nullptr);
+        const int tpw = c->tpw;
+        const dim3 grid(static_cast<unsigned>(1 + (c->n_tiles + tpw - 1) / tpw));
+        if (tpw == 4) launch_sweep<false, 4, true, kStats>(c, grid, a, nullptr, nullptr);
+        else if (tpw == 2) launch_sweep<false, 2, true, kStats>(c, grid, a, nullptr, nullptr);
+        else launch_sweep<false, 1, true, kStats>(c, grid, a, nullptr, nullptr);
+        LAUNCHCHK(c, "sweep_kernel");
+        CycleState *csb[2] = {c->cs, c->cs_alt};
+        double *pb[2] = {c->partials, c->partials_alt};
+        Precomp *sb[2] = {c->side, c->side_alt};
+        int cur = 0;
+        for (int64_t j = 1; j < len; ++j) {
+            FusedArgs<T> f;
+            f.sw = a;
+            f.sw.cs = csb[1 - cur];
+            f.sw.partials = pb[1 - cur];
+            f.sw.side = sb[1 - cur];
+            f.epi = epi_args(c);
+            f.epi.cs = f.epi.cs_out = csb[cur];
+            f.epi.partials = pb[cur];
+            f.epi.side = sb[cur];
+            const hbm_status st = tpw == 4   ? launch_fused<4, kStats>(c, grid, f)
+                                  : tpw == 2 ? launch_fused<2, kStats>(c, grid, f)
+                                             : launch_fused<1, kStats>(c, grid, f);
+            if (st != HBM_OK) return st;
+            LAUNCHCHK(c, "fused_kernel");
+            cur = 1 - cur;
+        }
+        EpiArgs e = epi_args(c);
+        e.cs = csb[cur];
+        e.cs_out = c->cs;
+        e.partials = pb[cur];
+        e.side = sb[cur];
+        hipLaunchKernelGGL((epilogue_kernel<M, true, true, kStats>), dim3(1), dim3(kBlock), 0, c->stream, e);
+        LAUNCHCHK(c, "epilogue_kernel");
+        return HBM_OK;
+    }
+
+    template <int TPW, bool kStats>
+    static hbm_status launch_fused(CtxImpl *c, dim3 grid, const FusedArgs<T> &f)
+    {
+        const size_t lds =
+            c->occ_cap > 0 ? occupancy_lds(c, reinterpret_cast<const void *>(&fused_kernel<M, TPW, kStats>)) : 0;
+        if (c->timing) {
+            // the runtime takes both timestamps from the dispatch itself
+            hipEvent_t e0 = take_event(c), e1 = take_event(c);
+            if (!e0 || !e1) return fail(c, HBM_ENOMEM, "hipEventCreate failed");
+            c->ev_pending.push_back(e0);
+            c->ev_pending.push_back(e1);
+            hipExtLaunchKernelGGL((fused_kernel<M, TPW, kStats>), grid, dim3(kBlock), lds, c->stream, e0, e1, 0, f);
+        } else {
+            hipLaunchKernelGGL((fused_kernel<M, TPW, kStats>), grid, dim3(kBlock), lds, c->stream, f);
+        }
+        return HBM_OK;
+    }
+
     static EpiArgs epi_args(CtxImpl *c)
     {
         EpiArgs e;
         e.cs = c->cs;
+        e.cs_out = c->cs;
         e.st = c->st;
         e.partials = c->partials;
         e.side = c->side;
@@ -580,7 +659,7 @@ struct Ops {
     static const Launch *table()
     {
         static const Launch t{&sweep, &theta, &set_theta, &poplik, &prepare, &check_init, &quadrature, &marginal,
-                              &cycles};
+                              &cycles, &fused};
         return &t;
     }
 };
@@ -689,7 +768,8 @@ void release(CtxImpl *c)
     for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pending) (void)hipEventDestroy(e);
     void *ptrs[] = {c->dd, c->partials, c->pout, c->theta_in, c->side, c->ref_t, c->ref_w, c->qx, c->qw, c->qeps,
-                    c->cs, c->st, c->theta_trace, c->tile_ds, c->which, c->marg_rule, c->marg_buf, c->xch};
+                    c->cs, c->st, c->theta_trace, c->tile_ds, c->which, c->marg_rule, c->marg_buf, c->xch,
+                    c->cs_alt, c->partials_alt, c->side_alt};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete static_cast<hbm_ctx *>(c);
@@ -923,7 +1003,11 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
                    sizeof(double) * c->p * static_cast<size_t>(pool->max_cycles) * ns)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->tile_ds), sizeof(int32_t) * c->n_tiles)) != HBM_OK ||
         (s = alloc(reinterpret_cast<void **>(&c->which), sizeof(int32_t) * ns)) != HBM_OK ||
-        (s = alloc(reinterpret_cast<void **>(&c->xch), kXchBytes)) != HBM_OK)
+        (s = alloc(reinterpret_cast<void **>(&c->xch), kXchBytes)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->cs_alt), sizeof(CycleState) * ns)) != HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->partials_alt), sizeof(double) * (2 + kMaxStats) * c->n_tiles)) !=
+            HBM_OK ||
+        (s = alloc(reinterpret_cast<void **>(&c->side_alt), sizeof(Precomp) * ns)) != HBM_OK)
         return bail(s);
     // every slot starts empty: zero statics (n = 0) and inactive states
     std::vector<Statics> hs(ns);
@@ -936,6 +1020,7 @@ hbm_status create_ctx(const hbm_pool_config *pool, const hbm_buffers *buffers, v
         (e = hipMemcpyAsync(c->tile_ds, c->h_tile_ds.data(), sizeof(int32_t) * c->n_tiles, hipMemcpyHostToDevice,
                             c->stream)) != hipSuccess ||
         (e = hipMemsetAsync(c->xch, 0, kXchBytes, c->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(c->cs_alt, 0, sizeof(CycleState) * ns, c->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
         hip_fail(c, e, "pool initialisation copies");
         return bail(HBM_EHIP);
@@ -1324,7 +1409,10 @@ hbm_status capture_cycles(CtxImpl *c, int64_t len, hipGraph_t *g_out, hipGraphEx
     c->stream = c->capture_stream;
     HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
     hbm_status st = HBM_OK;
-    for (int64_t j = 0; j < len && st == HBM_OK; ++j) st = c->ops->sweep(c, true, nullptr);
+    if (c->cycle_mode == HBM_CYCLES_FUSED && single(c) && len >= 2)
+        st = c->ops->fused(c, len);
+    else
+        for (int64_t j = 0; j < len && st == HBM_OK; ++j) st = c->ops->sweep(c, true, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
     c->stream = saved;
@@ -1388,6 +1476,13 @@ hbm_status issue_cycles(CtxImpl *c, int64_t n_cycles, bool use_graph)
         bool launched = false;
         hbm_status st = c->ops->cycles(c, n_cycles, &launched);
         if (st != HBM_OK || launched) return st;
+    }
+    if (use_graph && c->timing && c->cycle_mode == HBM_CYCLES_FUSED && single(c) && n_cycles >= 2) {
+        // fused cycles as plain launches, each fused kernel timed
+        hbm_status st = c->ops->fused(c, n_cycles);
+        if (st != HBM_OK) return st;
+        c->n_plain_cycles += n_cycles;
+        return HBM_OK;
     }
     if (use_graph && !c->timing) {
         hbm_status st = ensure_graphs(c, n_cycles);
@@ -1861,8 +1956,13 @@ hbm_status launch_counts(hbm_ctx *ctx, int64_t out[6])
 hbm_status set_cycle_mode(hbm_ctx *ctx, int32_t mode)
 {
     return with_ctx(ctx, [&](CtxImpl *c) -> hbm_status {
-        if (mode != HBM_CYCLES_AUTO && mode != HBM_CYCLES_GRAPH)
-            return fail(c, HBM_EINVAL, "mode must be HBM_CYCLES_AUTO or HBM_CYCLES_GRAPH");
+        if (mode != HBM_CYCLES_AUTO && mode != HBM_CYCLES_GRAPH && mode != HBM_CYCLES_FUSED)
+            return fail(c, HBM_EINVAL, "mode must be HBM_CYCLES_AUTO, HBM_CYCLES_GRAPH or HBM_CYCLES_FUSED");
+        // the captured graphs hold fused cycles or not
+        if ((mode == HBM_CYCLES_FUSED) != (c->cycle_mode == HBM_CYCLES_FUSED)) {
+            hbm_status st = drop_graph(c);
+            if (st != HBM_OK) return st;
+        }
         c->cycle_mode = mode;
         return HBM_OK;
     });
@@ -2199,25 +2299,31 @@ hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t out_choice[3], d
         }
         // candidates: the two-kernel cycle with tiles per workgroup {1, 2, 4}
         // under a cap of {none, 4, 2} workgroups per compute unit, then the
-        // persistent launch (one-dataset contexts in mode HBM_CYCLES_AUTO)
-        struct Cand { int32_t tpw, cap, persistent; };
+        // persistent launch (one-dataset contexts in mode HBM_CYCLES_AUTO),
+        // then fused cycles with tiles per workgroup {1, 2, 4} (one-dataset
+        // contexts).  how: 0 two-kernel graphs, 1 persistent, 2 fused graphs.
+        struct Cand { int32_t tpw, cap, how; };
         Cand cand[HBM_TUNE_CANDIDATES];
         int q = 0;
         for (int32_t cap : {0, 4, 2})
             for (int32_t tpw : {1, 2, 4}) cand[q++] = Cand{tpw, cap, 0};
         cand[q++] = Cand{c->tpw, c->occ_cap, 1};
+        for (int32_t tpw : {1, 2, 4}) cand[q++] = Cand{tpw, 0, 2};
         const int32_t mode = c->cycle_mode;
         const int32_t keep_tpw = c->tpw, keep_cap = c->occ_cap;
         double best = HUGE_VAL;
-        Cand pick{keep_tpw, keep_cap, mode == HBM_CYCLES_AUTO && single(c) ? 1 : 0};
+        Cand pick{keep_tpw, keep_cap,
+                  mode == HBM_CYCLES_AUTO && single(c) ? 1 : (mode == HBM_CYCLES_FUSED && single(c) ? 2 : 0)};
         hbm_status st = HBM_OK;
         for (int j = 0; j < HBM_TUNE_CANDIDATES && st == HBM_OK; ++j) {
             const Cand &cd = cand[j];
             if (out_us) out_us[j] = static_cast<double>(NAN);
             // every candidate runs its cycles (the trace counts them), timed or not
-            const bool usable = !cd.persistent || (mode == HBM_CYCLES_AUTO && single(c) && !c->stats_mode);
-            c->cycle_mode = cd.persistent ? HBM_CYCLES_AUTO : HBM_CYCLES_GRAPH;
-            if (!cd.persistent) {
+            const bool usable = cd.how == 0 || (cd.how == 1 && mode == HBM_CYCLES_AUTO && single(c) && !c->stats_mode) ||
+                                (cd.how == 2 && single(c));
+            const int32_t cm = cd.how == 1 ? HBM_CYCLES_AUTO : cd.how == 2 ? HBM_CYCLES_FUSED : HBM_CYCLES_GRAPH;
+            if ((st = set_cycle_mode(ctx, cm)) != HBM_OK) break;
+            if (cd.how != 1) {
                 if ((st = set_launch(ctx, cd.tpw)) != HBM_OK || (st = set_occupancy(ctx, cd.cap)) != HBM_OK) break;
                 if ((st = ensure_graphs(c, kTuneWarm)) != HBM_OK || (st = ensure_graphs(c, trial_cycles)) != HBM_OK)
                     break;
@@ -2234,7 +2340,7 @@ hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t out_choice[3], d
                 break;
             }
             // a persistent candidate counts only when the launch really happened
-            if (!usable || (cd.persistent && c->n_persistent_cycles - p0 != trial_cycles)) continue;
+            if (!usable || (cd.how == 1 && c->n_persistent_cycles - p0 != trial_cycles)) continue;
             const double us = 1e3 * ms / trial_cycles;
             if (out_us) out_us[j] = us;
             if (us < best) {
@@ -2244,18 +2350,23 @@ hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t out_choice[3], d
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        c->cycle_mode = mode;
-        if (st != HBM_OK) return st;
-        if (pick.persistent) {
-            if ((st = set_launch(ctx, keep_tpw)) != HBM_OK || (st = set_occupancy(ctx, keep_cap)) != HBM_OK) return st;
+        if (st != HBM_OK) {
+            c->cycle_mode = mode;
+            return st;
+        }
+        if (pick.how == 1) {
+            if ((st = set_cycle_mode(ctx, HBM_CYCLES_AUTO)) != HBM_OK || (st = set_launch(ctx, keep_tpw)) != HBM_OK ||
+                (st = set_occupancy(ctx, keep_cap)) != HBM_OK)
+                return st;
         } else {
-            if ((st = set_launch(ctx, pick.tpw)) != HBM_OK || (st = set_occupancy(ctx, pick.cap)) != HBM_OK) return st;
-            c->cycle_mode = HBM_CYCLES_GRAPH;
+            if ((st = set_cycle_mode(ctx, pick.how == 2 ? HBM_CYCLES_FUSED : HBM_CYCLES_GRAPH)) != HBM_OK ||
+                (st = set_launch(ctx, pick.tpw)) != HBM_OK || (st = set_occupancy(ctx, pick.cap)) != HBM_OK)
+                return st;
         }
         if (out_choice) {
             out_choice[0] = c->tpw;
             out_choice[1] = c->occ_cap;
-            out_choice[2] = pick.persistent;
+            out_choice[2] = pick.how;
         }
         return HBM_OK;
     });

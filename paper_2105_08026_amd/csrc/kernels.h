@@ -213,7 +213,7 @@ __device__ void theta_mh(CycleState &c, const Statics &s, double *theta_trace, d
 
 template <class M>
 __device__ __forceinline__ double block_log_z(const double *zc, const double *qx, const double *qw,
-                                              const double *qeps, int nq, double (*red)[kWavesPerBlock]);
+                                              const double *qeps, int nq, double (*red)[kBlock]);
 
 // The theta step from the sweep's sufficient statistics: K = s.substeps
 // Metropolis steps on theta given chi, K >= 1, every thread of the
@@ -243,7 +243,7 @@ __device__ __attribute__((noinline)) void aux_out_of_line(const double *th, doub
 template <class M>
 __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_trace, const Precomp &pc,
                                const double *qx, const double *qw, const double *qeps, int nq,
-                               double (*red)[kWavesPerBlock])
+                               double (*red)[kBlock])
 {
     constexpr int P = M::P, NB = (P + 3) / 4;
     constexpr int kAuxLane = kWave;               // first lane of the second wavefront
@@ -377,7 +377,7 @@ __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_tr
 // tid + 256, ...  Valid in thread 0.
 template <class M>
 __device__ __forceinline__ double block_log_z(const double *zc, const double *qx, const double *qw,
-                                              const double *qeps, int nq, double (*red)[kWavesPerBlock])
+                                              const double *qeps, int nq, double (*red)[kBlock])
 {
     double v[1] = {0.0};
     for (int j = threadIdx.x; j < nq; j += kBlock) v[0] += qw[j] * exp(M::zlog(zc, qx[j])) * qeps[j];
@@ -486,6 +486,42 @@ __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, i
     return accept;
 }
 
+// The values of the theta step that the objects do not decide, for the
+// proposal c.prop that the sweep k = c.k + 1 prepares (what a side workgroup
+// computes while the tiles run): the selection quadrature and per-theta
+// scalars of the proposal, the accept uniform, the next proposal's normals and
+// step size, and (off the epilogue's serial path) ln Z of the proposal and N
+// times the object-independent part of its log f change.  The whole
+// workgroup takes part; the result goes to out.
+template <class M>
+__device__ __forceinline__ void side_values(const CycleState &cs, const Statics &st, const double *qx, const double *qw,
+                            const double *qeps, int32_t nq, Precomp &sd, double (*zred)[kBlock], Precomp *out)
+{
+    const bool valid = cs.prop_valid != 0;
+    double judged[kMaxP];
+    for (int r = 0; r < M::P; ++r) judged[r] = cs.prop[r];
+    double zraw = 0.0;
+    if constexpr (M::kSelection) {
+        if (valid) {
+            double zc[4] = {cs.zc_prop[0], cs.zc_prop[1], cs.zc_prop[2], cs.zc_prop[3]};
+            zraw = block_log_z<M>(zc, qx, qw, qeps, nq, zred);
+        }
+    }
+    precompute<M>(sd, cs.k + 1, judged, valid, st);
+    if (threadIdx.x == 0) sd.zraw = zraw;
+    __syncthreads();
+    // the judged proposal's ln Z and constant log f change, off the
+    // epilogue's serial path (they need its aux scalars from wave 0)
+    if (threadIdx.x == 0) {
+        sd.logz_used = (valid && M::kSelection) ? zraw - M::logz_shift(sd.aux_used) : 0.0;
+        sd.dconst = valid ? static_cast<double>(st.n) * M::dlf_const(cs.theta, judged, cs.aux_cur, sd.aux_used) : 0.0;
+    }
+    __syncthreads();
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(&sd);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(out);
+    for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
+}
+
 // ---------------------------------------------------------------------------
 // The sweep.  Workgroups 0 .. n_ds-1 are side workgroups, one per dataset:
 // ln Z at its pending proposal and every FP64 value of its theta step that
@@ -505,7 +541,7 @@ template <class M, bool kTrace, int TPW, bool kSingle, bool kStats = false>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> a)
 {
     constexpr int kCols = kStats ? 1 + M::NS : 2;     // FP64 sums per tile besides the accepted count
-    __shared__ double red[kCols * TPW][kWavesPerBlock];
+    __shared__ double red[kCols * TPW][kBlock];
     __shared__ uint32_t nacc_w[TPW][kWavesPerBlock];
 
     const int n_side = kSingle ? 1 : a.n_ds;
@@ -513,36 +549,12 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
     if (kSingle) asm volatile("" ::"s"(a.chi), "s"(a.chol), "s"(a.acc), "s"(a.dd), "s"(a.n_total));
     if (static_cast<int>(blockIdx.x) < n_side) {
         const int ds = blockIdx.x;
-        CycleState *cs = a.cs + ds;
+        const CycleState *cs = a.cs + ds;
         if (!cs->active) return;
-        const Statics &st = a.st[ds];
         __shared__ Precomp sd;
-        __shared__ double zred[1][kWavesPerBlock];
-        const bool valid = cs->prop_valid != 0;
-        double judged[kMaxP];
-        for (int r = 0; r < M::P; ++r) judged[r] = cs->prop[r];
-        double zraw = 0.0;
-        if constexpr (M::kSelection) {
-            if (valid) {
-                double zc[4] = {cs->zc_prop[0], cs->zc_prop[1], cs->zc_prop[2], cs->zc_prop[3]};
-                const int64_t qo = static_cast<int64_t>(ds) * a.nq;
-                zraw = block_log_z<M>(zc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, zred);
-            }
-        }
-        precompute<M>(sd, cs->k + 1, judged, valid, st);
-        if (threadIdx.x == 0) sd.zraw = zraw;
-        __syncthreads();
-        // the judged proposal's ln Z and constant log f change, off the
-        // epilogue's serial path (they need its aux scalars from wave 0)
-        if (threadIdx.x == 0) {
-            sd.logz_used = (valid && M::kSelection) ? zraw - M::logz_shift(sd.aux_used) : 0.0;
-            sd.dconst = valid ? static_cast<double>(st.n) * M::dlf_const(cs->theta, judged, cs->aux_cur, sd.aux_used)
-                              : 0.0;
-        }
-        __syncthreads();
-        const uint64_t *src = reinterpret_cast<const uint64_t *>(&sd);
-        uint64_t *dst = reinterpret_cast<uint64_t *>(a.side + ds);
-        for (int j = threadIdx.x; j < static_cast<int>(sizeof(Precomp) / 8); j += kBlock) dst[j] = src[j];
+        __shared__ double zred[1][kBlock];
+        const int64_t qo = static_cast<int64_t>(ds) * a.nq;
+        side_values<M>(*cs, a.st[ds], a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, sd, zred, a.side + ds);
         return;
     }
 
@@ -648,7 +660,8 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<typename M::T> 
 }
 
 struct EpiArgs {
-    CycleState *cs;
+    CycleState *cs;            // the chain states the sweep ran with (sums pending)
+    CycleState *cs_out;        // where the epilogue leaves them (cs itself, or the other buffer of a fused run)
     const Statics *st;
     const double *partials;
     const Precomp *side;
@@ -659,18 +672,17 @@ struct EpiArgs {
     int32_t nq;
 };
 
-// Epilogue of a sweep, one workgroup per dataset: fixed-order reduction of
-// the dataset's tile partials, bookkeeping, then (kFull) the theta step,
-// then the proposal for the next sweep.
+// Epilogue of a sweep for dataset ds, by one workgroup, into its LDS copy c
+// of the chain state: fixed-order reduction of the dataset's tile partials,
+// bookkeeping, then (kFull) the theta step, then the proposal for the next
+// sweep.  Returns false (c staged unchanged) when the dataset is off.  The
+// theta trace row is written only with write_trace.
 template <class M, bool kFull, bool kSingle, bool kStats = false>
-__global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
+__device__ __forceinline__ bool epilogue_body(const EpiArgs &a, int ds, CycleState &c, Precomp &pc,
+                              double (*red)[kBlock], bool write_trace)
 {
     constexpr int NCOL = (kStats ? 1 + M::NS : 2) + 1;     // tile sums, then the accepted count
     constexpr int G = NCOL > 3 ? 4 : 8;                     // tiles whose loads are issued together
-    __shared__ CycleState c;
-    __shared__ Precomp pc;
-    __shared__ double red[NCOL][kWavesPerBlock];
-    const int ds = kSingle ? 0 : static_cast<int>(blockIdx.x);
     const Statics &st = a.st[ds];
     const int32_t ntt = a.n_tiles_total;
     const int32_t t0 = kSingle ? 0 : st.tile_start, nt = kSingle ? ntt : st.n_tiles;
@@ -724,23 +736,157 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
         if (static_cast<int>(threadIdx.x) < kPcWords) reinterpret_cast<uint64_t *>(&pc)[threadIdx.x] = pcw;
     }
     __syncthreads();
-    if (!c.active) return;               // uniform: read from LDS after the barrier
+    if (!c.active) return false;         // uniform: read from LDS after the barrier
     block_sum<NCOL>(v, red);
+    double *trace = write_trace ? a.theta_trace + ds * a.trace_stride * M::P : nullptr;
     if constexpr (kStats) {
         if (threadIdx.x == 0) finish_sweep<M, true>(c, st, v, pc);
         if constexpr (kFull) {
             __syncthreads();
             const int64_t qo = static_cast<int64_t>(ds) * a.nq;
-            theta_substeps<M>(c, st, a.theta_trace + ds * a.trace_stride * M::P, pc, a.qx + qo, a.qw + qo,
-                              a.qeps + qo, a.nq, red);
+            theta_substeps<M>(c, st, trace, pc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, red);
         }
         if (threadIdx.x == 0) prepare_next<M>(c, st, pc);
     } else if (threadIdx.x == 0) {
         finish_sweep<M>(c, st, v, pc);
-        if (kFull) theta_mh<M>(c, st, a.theta_trace + ds * a.trace_stride * M::P, pc.ln_u);
+        if (kFull) theta_mh<M>(c, st, trace, pc.ln_u);
         prepare_next<M>(c, st, pc);
     }
-    stage_out(a.cs + ds, c);
+    return true;
+}
+
+// Epilogue of a sweep, one workgroup per dataset (epilogue_body); the state
+// goes to cs_out (a dataset that is off is copied there unchanged when
+// cs_out is not cs).
+template <class M, bool kFull, bool kSingle, bool kStats = false>
+__global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
+{
+    __shared__ CycleState c;
+    __shared__ Precomp pc;
+    __shared__ double red[(kStats ? 1 + M::NS : 2) + 1][kBlock];
+    const int ds = kSingle ? 0 : static_cast<int>(blockIdx.x);
+    if (!epilogue_body<M, kFull, kSingle, kStats>(a, ds, c, pc, red, true) && a.cs_out == a.cs) return;
+    stage_out(a.cs_out + ds, c);
+}
+
+constexpr int kKc = 16;              // per-sweep constants the models read (kc[0..15])
+
+// A value read in one lane made uniform (scalar registers).
+__device__ __forceinline__ float uniform_of(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform_of(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<int>(b & 0xffffffffu));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// ---------------------------------------------------------------------------
+// One full cycle in one launch, for a context that holds one dataset: the
+// theta step of the previous sweep, then this sweep.  Every workgroup takes
+// the theta step itself -- the previous sweep's partials reduced in the
+// epilogue's fixed order, so every copy of the chain is bit for bit the
+// same -- and then, with the new state in its LDS, steps its tiles (the
+// tiles' object loads are issued first, so their latency overlaps the theta
+// step).  Workgroup 0 writes the chain state, the trace row and the side
+// values of the new proposal.  A fused run reads the previous sweep's state,
+// partials and side values from one set of buffers and writes this sweep's
+// to the other, so no workgroup reads what another writes in the same launch
+// and none waits for another; the kernel boundary orders consecutive cycles.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct FusedArgs {
+    SweepArgs<T> sw;           // this sweep: objects, and the buffers it writes (cs, partials, side)
+    EpiArgs epi;               // the previous sweep's state, partials and side values; the trace
+};
+
+template <class M, int TPW, bool kStats>
+__global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs<typename M::T> a)
+{
+    using T = typename M::T;
+    constexpr int D = M::D, NC = M::NC;
+    constexpr int kCols = kStats ? 1 + M::NS : 2;     // FP64 sums per tile besides the accepted count
+    constexpr int NCOL = kCols + 1;
+    constexpr int kRed = kCols * TPW > NCOL ? kCols * TPW : NCOL;
+    __shared__ CycleState c;
+    __shared__ Precomp pc;
+    __shared__ double red[kRed][kBlock];
+    __shared__ uint32_t nacc_w[TPW][kWavesPerBlock];
+    const SweepArgs<T> &sw = a.sw;
+    const bool side = blockIdx.x == 0;                 // uniform
+    const int64_t n = sw.n_total;
+    const int g0 = (static_cast<int>(blockIdx.x) - 1) * TPW;     // first tile of a tile workgroup
+    // this workgroup's objects first (positions past the end read the last one, unused)
+    T xs[TPW][D], Ss[TPW][NC];
+    uint32_t na[TPW];
+    typename M::Obj os[TPW];
+    if (!side) {
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
+            i = i < n ? i : n - 1;
+#pragma unroll
+            for (int j = 0; j < D; ++j) xs[u][j] = sw.chi[j * n + i];
+#pragma unroll
+            for (int e = 0; e < NC; ++e) Ss[u][e] = sw.chol[e * n + i];
+            na[u] = sw.acc[i];
+            os[u] = M::load(sw.dd, i, n);
+        }
+    }
+    // the previous sweep's theta step, in every workgroup
+    epilogue_body<M, true, true, kStats>(a.epi, 0, c, pc, red, side);
+    __syncthreads();
+    const Statics &st = sw.st[0];
+    if (side) {
+        // the chain state: every word but the flags, which the tiles may raise
+        // meanwhile, then this copy's flags; then the new proposal's side values
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&c);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(sw.cs);
+        constexpr int kWords = static_cast<int>(sizeof(CycleState) / 4);
+        constexpr int kFlagsWord = static_cast<int>(offsetof(CycleState, flags) / 4);
+        for (int q = threadIdx.x; q < kWords; q += kBlock)
+            if (q != kFlagsWord) dst[q] = src[q];
+        if (threadIdx.x == 0 && c.flags != 0) atomicOr(&sw.cs[0].flags, c.flags);
+        if (!c.active) return;                         // uniform: LDS after a barrier
+        __shared__ Precomp sd;
+        __shared__ double zred[1][kBlock];
+        side_values<M>(c, st, sw.qx, sw.qw, sw.qeps, sw.nq, sd, zred, sw.side);
+        return;
+    }
+    if (!c.active) return;
+    const TileView<T> tv{c.k + 1, st.obj_start, st.n, st.snap_cap, st.key0, st.key1, st.thin, c.active,
+                         st.snap_ring, static_cast<T>(c.eta_next), static_cast<T>(st.alpha_star)};
+    T kc[kKc];
+#pragma unroll
+    for (int q = 0; q < kKc; ++q) kc[q] = uniform_of(kc_of<T>(&c)[q]);
+    double v[kCols * TPW];
+    bool accepted[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int64_t i = static_cast<int64_t>(g0 + u) * kBlock + threadIdx.x;
+        accepted[u] = step_object<M, false, kStats>(sw, 0, tv, i, i, xs[u], Ss[u], na[u], os[u], v + kCols * u,
+                                                    g0 + u < sw.n_tiles_total && i < n, kc);
+    }
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const uint32_t nw = static_cast<uint32_t>(__popcll(__ballot(accepted[u])));
+        if ((threadIdx.x & (kWave - 1)) == 0) nacc_w[u][threadIdx.x / kWave] = nw;
+    }
+    block_sum<kCols * TPW>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int g = g0 + u;
+            if (g >= sw.n_tiles_total) continue;
+#pragma unroll
+            for (int q = 0; q < kCols; ++q) sw.partials[q * sw.n_tiles_total + g] = v[kCols * u + q];
+            sw.partials[kCols * sw.n_tiles_total + g] =
+                static_cast<double>((nacc_w[u][0] + nacc_w[u][1]) + (nacc_w[u][2] + nacc_w[u][3]));
+        }
+    }
 }
 
 // Theta step on its own, after a ram_sweep (plain cycle), one workgroup per dataset.
@@ -749,7 +895,7 @@ __global__ __launch_bounds__(kBlock) void theta_kernel(EpiArgs a)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
-    __shared__ double red[1][kWavesPerBlock];
+    __shared__ double red[1][kBlock];
     const int ds = blockIdx.x;
     if (!a.cs[ds].active) return;
     {
@@ -790,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void set_theta_kernel(CycleState *cs_all, c
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
-    __shared__ double red[1][kWavesPerBlock];
+    __shared__ double red[1][kBlock];
     const int ds = blockIdx.x;
     if (!which[ds]) return;
     CycleState *cs = cs_all + ds;
@@ -900,7 +1046,7 @@ template <class M>
 __global__ __launch_bounds__(kBlock) void poplik_kernel(PopArgs<typename M::T> a)
 {
     using T = typename M::T;
-    __shared__ double red[1][kWavesPerBlock];
+    __shared__ double red[1][kBlock];
     __shared__ T kc[32];
     if (static_cast<int>(blockIdx.x) < a.n_ds) {
         const int ds = blockIdx.x;
@@ -946,7 +1092,7 @@ __global__ __launch_bounds__(kBlock) void poplik_kernel(PopArgs<typename M::T> a
 
 __global__ __launch_bounds__(kBlock) void poplik_finish_kernel(const Statics *st, const double *partials, double *pout)
 {
-    __shared__ double red[1][kWavesPerBlock];
+    __shared__ double red[1][kBlock];
     const int ds = blockIdx.x;
     const Statics &s = st[ds];
     if (s.n == 0) return;

@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void marginal_kernel(MargArgs a)
     static_assert((2 * R::kCore) % kMargLanes == 0, "core rows must be whole");
     constexpr int kCoreRows = 2 * R::kCore / kMargLanes;
     constexpr int kBelow = R::kGraded + R::kTail, kBelowRows = (kBelow + kWave - 1) / kWave;
-    __shared__ double red[1][kWavesPerBlock];
+    __shared__ double red[1][kBlock];
     const Statics &s = *a.st;
     const int it = blockIdx.y;
     const typename G::Th t = *reinterpret_cast<const typename G::Th *>(a.th + static_cast<int64_t>(it) * kMargThWords);
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void marginal_finish_kernel(const double *t
                                                                  const double *qw, const double *qeps, int32_t nq,
                                                                  double *out)
 {
-    __shared__ double red[1][kWavesPerBlock];
+    __shared__ double red[1][kBlock];
     const int it = blockIdx.x;
     double lz = 0.0;
     if constexpr (M::kSelection) {

@@ -130,11 +130,14 @@ class _Prefetcher:
 
 def serve(jobs: List[Job], executor, make: Optional[Callable[[Job], object]] = None,
           clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-          prefetch: bool = True) -> dict:
+          prefetch: bool = True, progress: Optional[Callable[[int, int, float], None]] = None,
+          progress_every_s: float = 30.0) -> dict:
     """Runs the request loop until every job is done; returns the jobs and loop statistics.
 
     Jobs must be sorted by arrival time.  A job is visible to the loop once
     the clock passes its arrival; its latency is completion minus arrival.
+    progress (optional) is called with (jobs finished, jobs, seconds since
+    the start) at most every progress_every_s seconds.
     """
     make = make or executor.make
     for j in jobs:
@@ -150,8 +153,12 @@ def serve(jobs: List[Job], executor, make: Optional[Callable[[Job], object]] = N
     chunks = 0
     resident_sum = 0
     wait_gen = 0.0
+    last_report = 0.0
     while len(finished) < len(jobs):
         now = clock() - t0
+        if progress is not None and now - last_report >= progress_every_s:
+            progress(len(finished), len(jobs), now)
+            last_report = now
         while nxt < len(jobs) and jobs[nxt].arrival <= now:
             if src is not None:
                 tg = clock()

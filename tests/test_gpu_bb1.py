@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from conftest import batch_means
+from conftest import assert_moments_agree, moment_scores
 from lockstep import lockstep_step
 
 torch = pytest.importorskip("torch")
@@ -92,15 +92,10 @@ def test_bb1_free_run_posterior_moments(hbm):
     st = o.initial_state()
     to, _ = o.run(st, m)
     to = to[m // 5:]
-    for j in range(3):
-        mg, sg = batch_means(tg[:, j])
-        mo, so = batch_means(to[:, j])
-        z = abs(mg - mo) / math.hypot(sg, so)
-        vg, svg = batch_means((tg[:, j] - mg) ** 2)
-        vo, svo = batch_means((to[:, j] - mo) ** 2)
-        zv = abs(vg - vo) / math.hypot(svg, svo)
+    scores = moment_scores(tg, to)
+    for j, (z, zv, mg, sg, mo, so) in enumerate(scores):
         _say(f"  theta[{j}] gpu {mg:.5f}±{sg:.5f} oracle {mo:.5f}±{so:.5f} z={z:.2f}; variance z={zv:.2f}")
-        assert z < 2.0 and zv < 2.0
+    _say(f"  rms z over the means and variances {assert_moments_agree(scores):.2f}")
 
 
 def test_bb1_batch_matches_alone(hbm):

@@ -29,7 +29,7 @@ import pytest
 
 import oracle
 import synth
-from conftest import batch_means
+from conftest import MOMENT_BATCHES, batch_means
 
 torch = pytest.importorskip("torch")
 
@@ -192,8 +192,8 @@ def test_marginal_metropolis_matches_gibbs_posterior(hbm, name):
     tm = tm[m // 10:]
     _say(f"  marginal Metropolis acceptance {rate:.2f}")
     for j in range(wl.p):
-        mg, sg = batch_means(tg[:, j])
-        mm, sm = batch_means(tm[:, j])
+        mg, sg = batch_means(tg[:, j], MOMENT_BATCHES)
+        mm, sm = batch_means(tm[:, j], MOMENT_BATCHES)
         z = abs(mg - mm) / math.hypot(sg, sm)
         _say(f"  theta[{j}] gibbs {mg:.5f}±{sg:.5f} marginal {mm:.5f}±{sm:.5f} z={z:.2f}")
         assert z < 4.0

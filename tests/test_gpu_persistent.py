@@ -54,6 +54,8 @@ MODELS = {
     "lf3d_5000": lambda: synth.gamma_lf_3d(n=5000, seed=94, fth=FTH),
     "nn3d_777": lambda: synth.normal_normal_3d(n=777, seed=5),
     "bb1_4000": lambda: synth.bb1_lf(n=4000, seed=95, chunk=1_000_000),
+    # five tiles per lane of 3-D state are more than the LDS holds: the state stays in memory
+    "lf3d_300000": lambda: synth.gamma_lf_3d(n=300000, seed=99, fth=FTH),
 }
 
 

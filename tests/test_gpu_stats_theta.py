@@ -27,7 +27,7 @@ import pytest
 
 import oracle
 import synth
-from conftest import batch_means
+from conftest import MOMENT_BATCHES, batch_means
 from lockstep import lockstep_step
 
 torch = pytest.importorskip("torch")
@@ -128,8 +128,8 @@ def test_posterior_moments_match_the_generic_sampler(hbm):
     b.run_cycles(m)
     ta, tb = a.theta_trace()[m // 5:], b.theta_trace()[m // 5:]
     for j in range(wl.p):
-        ma, sa = batch_means(ta[:, j])
-        mb, sb = batch_means(tb[:, j])
+        ma, sa = batch_means(ta[:, j], MOMENT_BATCHES)
+        mb, sb = batch_means(tb[:, j], MOMENT_BATCHES)
         z = abs(ma - mb) / math.hypot(sa, sb)
         _say(f"  theta[{j}] generic {ma:.5f}±{sa:.5f} K=4 {mb:.5f}±{sb:.5f} z={z:.2f}")
         assert z < 4.0
