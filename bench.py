@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--sat-jobs", type=int, default=200, help="serving: jobs in the saturation run")
     ap.add_argument("--seq-steps", type=int, default=200,
-                    help="batch workload: cycles timed per dataset in the one-dataset-per-launch comparison")
+                    help="batch workload: cycles timed per dataset in the one-dataset-per-launch comparison "
+                         "(0 skips it)")
     ap.add_argument("--job-sweeps", type=int, default=2000, help="batch workload: sweeps that make one job")
     ap.add_argument("--n", type=int, default=None,
                     help="objects (default: 300,000; 1,000,000 for the 3-D catalog; 100,000 for BB1)")
@@ -323,8 +324,9 @@ def bench_batch(args, torch, synth, hbm):
     torch.cuda.empty_cache()
 
     # one dataset per launch sequence: the same datasets, each alone, back to back
+    # (skipped with --seq-steps 0)
     seq = 0.0
-    for wl in wls:
+    for wl in (wls if args.seq_steps > 0 else []):
         s = hbm.Sampler(wl, device="cuda:0", max_cycles=32 + args.seq_steps)
         s.run_cycles(32)
         torch.cuda.synchronize()
@@ -335,7 +337,7 @@ def bench_batch(args, torch, synth, hbm):
         s.close()
     t_cycle = wall / args.steps
     jobs_h = 256 * 3600.0 / (args.job_sweeps * t_cycle)
-    jobs_h_seq = 256 * 3600.0 / (args.job_sweeps * seq)
+    jobs_h_seq = 256 * 3600.0 / (args.job_sweeps * seq) if seq > 0 else None
     bpu = BYTES_PER_UPDATE["gamma_lf_1d"]
     achieved = bpu * n_tot / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
     traffic = measured_traffic("gamma_lf_batch256", n_tot)
@@ -361,8 +363,9 @@ def bench_batch(args, torch, synth, hbm):
         "config": {"workload": "gamma_lf_batch256", "n_datasets": 256, "n_objects_total": n_tot,
                    "job_sweeps": args.job_sweeps, "graph": use_graph,
                    "tiles_per_workgroup": pick["tiles_per_group"], "groups_per_cu_cap": pick["groups_per_cu"]},
-        "jobs_per_hour": jobs_h, "sequential_jobs_per_hour": jobs_h_seq, "batch_speedup": jobs_h / jobs_h_seq,
-        "sequential_ms_per_cycle_sum": 1e3 * seq,
+        "jobs_per_hour": jobs_h, "sequential_jobs_per_hour": jobs_h_seq,
+        "batch_speedup": jobs_h / jobs_h_seq if jobs_h_seq else None,
+        "sequential_ms_per_cycle_sum": 1e3 * seq if seq > 0 else None,
         "autotune_us_per_cycle": tune_table(hbm, us),
         "roofline": roof,
     }
