@@ -164,22 +164,25 @@ def planned_frac(name: str, n: int, kern_ms: float) -> dict:
 
 
 def side_c2(torch, synth, hbm, n: int = 1_000_000, cycles: int = 64):
-    """The 3-D colour catalog at N = 10^6, briefly: cycles per second (one
-    persistent launch; graph replays of the two-kernel cycle beside it) and
-    the sweep kernel's mean duration (HIP events on its stream, plain
-    launches) with its fraction of HBM peak."""
+    """The 3-D colour catalog at N = 10^6, briefly: cycles per second in the
+    issue mode the autotuner picks (two-kernel graphs, fused graphs or the
+    persistent launch), two-kernel graph replay beside it, and the sweep
+    kernel's mean duration (HIP events on its stream, plain launches) with
+    its fraction of HBM peak."""
     wl = synth.gamma_lf_3d(n=n)
     s = hbm.Sampler(wl, device="cuda:0", max_cycles=hbm.autotune_cycles(32) + 32 + 4 * cycles)
-    s.set_cycle_mode(hbm.HBM_CYCLES_GRAPH)
-    pick, tuned = s.autotune(32)                 # the two-kernel cycle's shape
-    s.set_cycle_mode(hbm.HBM_CYCLES_AUTO)
+    pick, tuned = s.autotune(32)
     s.run_cycles(32)
+    s.prepare_cycles(cycles)
     torch.cuda.synchronize()
+    lc0 = s.launch_counts()
     t0 = time.perf_counter()
     s.run_cycles(cycles)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    persistent = s.launch_counts()["persistent_cycles"] >= cycles
+    lc1 = s.launch_counts()
+    mode = ("persistent" if lc1["persistent_cycles"] > lc0["persistent_cycles"]
+            else "fused graphs" if pick.get("fused") else "two-kernel graphs")
     s.set_cycle_mode(hbm.HBM_CYCLES_GRAPH)
     s.prepare_cycles(cycles)
     torch.cuda.synchronize()
@@ -196,7 +199,7 @@ def side_c2(torch, synth, hbm, n: int = 1_000_000, cycles: int = 64):
     bpu = BYTES_PER_UPDATE[wl.name]
     gbs = bpu * n / (kern_ms * 1e-3) / 1e9
     return {"workload": wl.name, "n_objects": n, "cycles_timed": cycles, "us_per_cycle": 1e6 * wall / cycles,
-            "persistent_launch": persistent, "us_per_cycle_graph_replay": 1e6 * wall_graph / cycles,
+            "issue_mode": mode, "us_per_cycle_two_kernel_graph_replay": 1e6 * wall_graph / cycles,
             "updates_per_s": n * cycles / wall, "tiles_per_workgroup": pick["tiles_per_group"],
             "groups_per_cu_cap": pick["groups_per_cu"], "autotune_us_per_cycle": tune_table(hbm, tuned),
             "sweep_kernel_us": 1e3 * kern_ms, "launches_timed": n_launch, "bytes_per_update": bpu,
@@ -342,17 +345,17 @@ def bench_batch(args, torch, synth, hbm):
     achieved = bpu * n_tot / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else None
     traffic = measured_traffic("gamma_lf_batch256", n_tot)
     valu = valu_roof(traffic, kern_ms)
-    hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-           "traffic": (traffic["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9) if traffic else None,
-           "traffic_bytes_per_launch": traffic["bytes_per_launch"] if traffic else None,
-           "algorithmic_bytes_per_launch": bpu * n_tot, "bytes_per_update": bpu}
+    hbm_roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": (traffic["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9) if traffic else None,
+                "traffic_bytes_per_launch": traffic["bytes_per_launch"] if traffic else None,
+                "algorithmic_bytes_per_launch": bpu * n_tot, "bytes_per_update": bpu}
     if valu is not None:
         # the sweep issues VALU instructions at the SIMDs' rate: that is its roof
         roof = {"bound": "alu", "achieved": valu["achieved"], "peak": valu["peak"], "unit": valu["unit"],
-                "frac": valu["frac"], "traffic": hbm["traffic"], "valu": valu, "hbm": hbm}
+                "frac": valu["frac"], "traffic": hbm_roof["traffic"], "valu": valu, "hbm": hbm_roof}
     else:
-        roof = dict(hbm, traffic_source="no counter summary for the current kernel sources")
+        roof = dict(hbm_roof, traffic_source="no counter summary for the current kernel sources")
     roof.update({"kernel": "sweep_kernel<gamma_lf_1d, dataset table>", "launches_timed": n_launch,
                  "kernel_ms": kern_ms})
     out = {
