@@ -421,7 +421,11 @@ HBM_API hbm_status get_stats(hbm_ctx *ctx, int32_t slot, double out[8]);
 
 /* Launch shape of the sweep kernel: 256-object tiles per workgroup (1, 2 or
  * 4).  Every tile is still reduced on its own in a fixed order, so results
- * do not depend on the shape.  Drops the captured graph.  Synchronous. */
+ * do not depend on the shape.  The sweep kernel of the two-kernel cycle
+ * steps a workgroup's tiles with 256 threads, one object of each tile per
+ * thread; the fused cycle (HBM_CYCLES_FUSED) with 2 or 4 tiles runs
+ * 512- or 1024-thread workgroups, one object per thread (256 threads with
+ * theta sub-steps).  Drops the captured graph.  Synchronous. */
 HBM_API hbm_status set_launch(hbm_ctx *ctx, int32_t tiles_per_group);
 
 /* Occupancy of the sweep kernel: at most groups_per_cu of its 256-thread

@@ -278,14 +278,20 @@ __device__ __forceinline__ double wave_sum(double v)
 // four values of lanes l, l + 64, l + 128, l + 192 as (w0 + w1) + (w2 + w3)
 // and reduces its 64 lane sums with wave_sum -- one wavefront's DPP steps per
 // value instead of four.  lds: [NV][256] doubles.
+// The same reduction over the 256 threads of one slice of a larger
+// workgroup: threads with part set hold the values, lane is their position
+// in the slice (0..255, the slice's first wavefront reduces), lds its own
+// staging rows.  Every thread of the workgroup calls it (one barrier).
 template <int NV>
-__device__ __forceinline__ void block_sum(double *v, double (*lds)[kBlock])
+__device__ __forceinline__ void block_sum_at(double *v, double (*lds)[kBlock], int lane, bool part)
 {
+    if (part) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) lds[q][threadIdx.x] = v[q];
+        for (int q = 0; q < NV; ++q) lds[q][lane] = v[q];
+    }
     __syncthreads();
-    if (threadIdx.x < kWave) {
-        const int l = threadIdx.x;
+    if (part && lane < kWave) {
+        const int l = lane;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
             const double s = (lds[q][l] + lds[q][l + kWave]) + (lds[q][l + 2 * kWave] + lds[q][l + 3 * kWave]);
@@ -293,6 +299,12 @@ __device__ __forceinline__ void block_sum(double *v, double (*lds)[kBlock])
             if (l == 0) v[q] = r;
         }
     }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double *v, double (*lds)[kBlock])
+{
+    block_sum_at<NV>(v, lds, static_cast<int>(threadIdx.x), true);
 }
 
 // ---------------------------------------------------------------------------

@@ -230,11 +230,12 @@ int32_t marg_blocks(int64_t n)
 constexpr int kMargShapeNodes = 2 * MargRuleShape::kCore + MargRuleShape::kGraded + MargRuleShape::kTail;
 constexpr int kMargProductNodes = 2 * MargRuleProduct::kCore;
 
-// Dynamic LDS (unused by the kernel) that limits fn to c->occ_cap resident
-// workgroups per compute unit: the smallest multiple of 256 bytes at which
-// the occupancy calculator reports no more than the cap (the largest the
-// device allows, if even that leaves more).  Cached per kernel and cap.
-size_t occupancy_lds(CtxImpl *c, const void *fn)
+// Dynamic LDS (unused by the kernel) that limits fn, launched with threads
+// per workgroup, to c->occ_cap resident workgroups per compute unit: the
+// smallest multiple of 256 bytes at which the occupancy calculator reports
+// no more than the cap (the largest the device allows, if even that leaves
+// more).  Cached per kernel and cap.
+size_t occupancy_lds(CtxImpl *c, const void *fn, int threads = kBlock)
 {
     const auto key = std::make_pair(fn, c->occ_cap);
     for (const auto &e : c->occ_lds)
@@ -244,7 +245,7 @@ size_t occupancy_lds(CtxImpl *c, const void *fn)
         max_lds = 65536;
     auto fits = [&](size_t lds) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds) != hipSuccess) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds) != hipSuccess) {
             (void)hipGetLastError();
             return false;
         }
@@ -436,20 +437,27 @@ struct Ops {
         return HBM_OK;
     }
 
+    // TPW tiles per workgroup: one object per thread in TPW x 256 threads
+    // (fused_wide_kernel), or TPW objects per thread in 256 threads with
+    // theta sub-steps (fused_kernel, whose sub-steps use 256-thread reductions)
     template <int TPW, bool kStats>
     static hbm_status launch_fused(CtxImpl *c, dim3 grid, const FusedArgs<T> &f)
     {
-        const size_t lds =
-            c->occ_cap > 0 ? occupancy_lds(c, reinterpret_cast<const void *>(&fused_kernel<M, TPW, kStats>)) : 0;
+        constexpr bool kWide = TPW > 1 && !kStats;
+        constexpr int kThreads = kWide ? kBlock * TPW : kBlock;
+        void (*fn)(FusedArgs<T>);
+        if constexpr (kWide) fn = &fused_wide_kernel<M, TPW>;
+        else fn = &fused_kernel<M, TPW, kStats>;
+        const size_t lds = c->occ_cap > 0 ? occupancy_lds(c, reinterpret_cast<const void *>(fn), kThreads) : 0;
         if (c->timing) {
             // the runtime takes both timestamps from the dispatch itself
             hipEvent_t e0 = take_event(c), e1 = take_event(c);
             if (!e0 || !e1) return fail(c, HBM_ENOMEM, "hipEventCreate failed");
             c->ev_pending.push_back(e0);
             c->ev_pending.push_back(e1);
-            hipExtLaunchKernelGGL((fused_kernel<M, TPW, kStats>), grid, dim3(kBlock), lds, c->stream, e0, e1, 0, f);
+            hipExtLaunchKernelGGL(fn, grid, dim3(kThreads), lds, c->stream, e0, e1, 0, f);
         } else {
-            hipLaunchKernelGGL((fused_kernel<M, TPW, kStats>), grid, dim3(kBlock), lds, c->stream, f);
+            hipLaunchKernelGGL(fn, grid, dim3(kThreads), lds, c->stream, f);
         }
         return HBM_OK;
     }

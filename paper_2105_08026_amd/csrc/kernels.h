@@ -86,17 +86,15 @@ __device__ __forceinline__ void stage_out(CycleState *dst, const CycleState &src
 
 
 // k: the sweep whose theta step follows; judged: the proposal that sweep's
-// sums refer to (nullptr when there is none to judge).
+// sums refer to (nullptr when there is none to judge).  The draws (the next
+// proposal's normals, ln u, the next step size) depend on k alone
+// (precompute_draws), the rest on the judged proposal (precompute_judged);
+// each value is one lane's, whichever wavefront computes it.
 template <class M>
-__device__ __forceinline__ void precompute(Precomp &pc, int64_t k, const double *judged, bool judged_valid,
-                                           const Statics &s)
+__device__ __forceinline__ void precompute_draws(Precomp &pc, int64_t k, const Statics &s)
 {
     constexpr int NB = (M::P + 3) / 4;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    if (wave == 0 && lane == 0 && judged != nullptr) {
-        if (judged_valid) M::aux(judged, pc.aux_used);
-        else pc.aux_used[0] = pc.aux_used[1] = 0.0;
-    }
     if (wave == 1 && lane < NB) {
         const Block4 blk = philox(0u, static_cast<uint32_t>(k + 1), 1u, static_cast<uint32_t>(lane), s.key0, s.key1);
         double z4[4];
@@ -107,9 +105,27 @@ __device__ __forceinline__ void precompute(Precomp &pc, int64_t k, const double 
     if (wave == 2 && lane == 0) {
         const Block4 ub = philox(0u, static_cast<uint32_t>(k), 2u, 0u, s.key0, s.key1);
         pc.ln_u = log(uniform24<double>(ub, 4));
-        if (judged != nullptr) pc.lprior_used = judged_valid ? M::log_prior(judged) : -HUGE_VAL;
     }
     if (wave == 3 && lane == 0) pc.eta_next = pow(static_cast<double>(k + 2), -s.gamma);
+}
+
+template <class M>
+__device__ __forceinline__ void precompute_judged(Precomp &pc, const double *judged, bool judged_valid)
+{
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    if (wave == 0 && lane == 0) {
+        if (judged_valid) M::aux(judged, pc.aux_used);
+        else pc.aux_used[0] = pc.aux_used[1] = 0.0;
+    }
+    if (wave == 2 && lane == 0) pc.lprior_used = judged_valid ? M::log_prior(judged) : -HUGE_VAL;
+}
+
+template <class M>
+__device__ __forceinline__ void precompute(Precomp &pc, int64_t k, const double *judged, bool judged_valid,
+                                           const Statics &s)
+{
+    if (judged != nullptr) precompute_judged<M>(pc, judged, judged_valid);
+    precompute_draws<M>(pc, k, s);
 }
 
 // Draws the proposal theta' = theta + S_theta z for sweep k + 1 (c.k == k)
@@ -370,17 +386,31 @@ __device__ void theta_substeps(CycleState &c, const Statics &s, double *theta_tr
     }
 }
 
+// Node j's term of the selection quadrature, rounded on its own: the sums
+// below add it without a fused multiply-add, so whichever thread computes it
+// the total is the same.
+template <class M>
+__device__ __forceinline__ double quad_term(const double *zc, const double *qx, const double *qw,
+                                            const double *qeps, int j)
+{
+    const double t = (qw[j] * exp(M::zlog(zc, qx[j]))) * qeps[j];
+    return t;
+}
+
 // ln of the selection quadrature sum_j w_j g(x_j; theta) eps_j over the fixed
 // ln L rule, where g is the luminosity PDF in x = ln L without its
 // normaliser (the model's zlog; the normaliser is applied by the caller
-// through logz_shift); every lane of one workgroup takes nodes tid,
-// tid + 256, ...  Valid in thread 0.
+// through logz_shift); lane t of one 256-thread workgroup adds nodes t,
+// t + 256, ... in that order, then the block sum.  Valid in thread 0.
 template <class M>
 __device__ __forceinline__ double block_log_z(const double *zc, const double *qx, const double *qw,
                                               const double *qeps, int nq, double (*red)[kBlock])
 {
     double v[1] = {0.0};
-    for (int j = threadIdx.x; j < nq; j += kBlock) v[0] += qw[j] * exp(M::zlog(zc, qx[j])) * qeps[j];
+    for (int j = threadIdx.x; j < nq; j += kBlock) {
+        const double t = quad_term<M>(zc, qx, qw, qeps, j);
+        v[0] = v[0] + t;
+    }
     block_sum<1>(v, red);
     return log(v[0]);
 }
@@ -492,10 +522,12 @@ __device__ __forceinline__ bool step_object(const SweepArgs<typename M::T> &a, i
 // scalars of the proposal, the accept uniform, the next proposal's normals and
 // step size, and (off the epilogue's serial path) ln Z of the proposal and N
 // times the object-independent part of its log f change.  The whole
-// workgroup takes part; the result goes to out.
+// workgroup takes part; the result goes to out.  draws_done: the draws are
+// in sd already (precompute_draws for sweep c.k + 1).
 template <class M>
 __device__ __forceinline__ void side_values(const CycleState &cs, const Statics &st, const double *qx, const double *qw,
-                            const double *qeps, int32_t nq, Precomp &sd, double (*zred)[kBlock], Precomp *out)
+                            const double *qeps, int32_t nq, Precomp &sd, double (*zred)[kBlock], Precomp *out,
+                            bool draws_done = false)
 {
     const bool valid = cs.prop_valid != 0;
     double judged[kMaxP];
@@ -507,7 +539,8 @@ __device__ __forceinline__ void side_values(const CycleState &cs, const Statics 
             zraw = block_log_z<M>(zc, qx, qw, qeps, nq, zred);
         }
     }
-    precompute<M>(sd, cs.k + 1, judged, valid, st);
+    if (draws_done) precompute_judged<M>(sd, judged, valid);
+    else precompute<M>(sd, cs.k + 1, judged, valid, st);
     if (threadIdx.x == 0) sd.zraw = zraw;
     __syncthreads();
     // the judged proposal's ln Z and constant log f change, off the
@@ -676,11 +709,24 @@ struct EpiArgs {
 // of the chain state: fixed-order reduction of the dataset's tile partials,
 // bookkeeping, then (kFull) the theta step, then the proposal for the next
 // sweep.  Returns false (c staged unchanged) when the dataset is off.  The
-// theta trace row is written only with write_trace.
-template <class M, bool kFull, bool kSingle, bool kStats = false>
-__device__ __forceinline__ bool epilogue_body(const EpiArgs &a, int ds, CycleState &c, Precomp &pc,
-                              double (*red)[kBlock], bool write_trace)
+// theta trace row is written only with write_trace.  The dataset's constants
+// are staged into the LDS copy sst in the same round of loads as the state,
+// and the sequential theta chain reads them there: read from memory where
+// the chain first needs them, each would stall lane 0 for a memory round
+// trip (a scalar load after the kernel start's cache invalidation).
+// In a workgroup of NT > 256 threads the first 256 do the work and the
+// others pass the barriers.  While lane 0 runs the theta chain every other
+// thread calls during(k) with the sweep count k the state was staged with.
+struct NoChainHook {
+    __device__ void operator()(int64_t) const {}
+};
+
+template <class M, bool kFull, bool kSingle, bool kStats = false, int NT = kBlock, class Hook = NoChainHook>
+__device__ __forceinline__ bool epilogue_body(const EpiArgs &a, int ds, CycleState &c, Precomp &pc, Statics &sst,
+                              double (*red)[kBlock], bool write_trace, const Hook &during = Hook{})
 {
+    static_assert(NT == kBlock || !kStats, "theta sub-steps run in 256-thread workgroups");
+    const bool lane_ok = NT == kBlock || threadIdx.x < kBlock;
     constexpr int NCOL = (kStats ? 1 + M::NS : 2) + 1;     // tile sums, then the accepted count
     constexpr int G = NCOL > 3 ? 4 : 8;                     // tiles whose loads are issued together
     const Statics &st = a.st[ds];
@@ -691,17 +737,20 @@ __device__ __forceinline__ bool epilogue_body(const EpiArgs &a, int ds, CycleSta
     // The state and the side values are loaded first, into registers, so
     // their latency overlaps the partials' (loads complete in issue order).
     constexpr int kCsWords = static_cast<int>(sizeof(CycleState) / 8), kPcWords = static_cast<int>(sizeof(Precomp) / 8);
+    constexpr int kStWords = static_cast<int>(sizeof(Statics) / 8);
     constexpr int kCsPer = (kCsWords + kBlock - 1) / kBlock;
-    static_assert(kPcWords <= kBlock, "one side word per thread");
+    static_assert(kPcWords + kStWords <= kBlock, "one side or constants word per thread");
     uint64_t csw[kCsPer], pcw = 0;
     {
         const uint64_t *src = reinterpret_cast<const uint64_t *>(a.cs + ds);
 #pragma unroll
         for (int u = 0; u < kCsPer; ++u) {
             const int j = u * kBlock + static_cast<int>(threadIdx.x);
-            csw[u] = j < kCsWords ? src[j] : 0;
+            csw[u] = (lane_ok && j < kCsWords) ? src[j] : 0;
         }
-        if (static_cast<int>(threadIdx.x) < kPcWords) pcw = reinterpret_cast<const uint64_t *>(a.side + ds)[threadIdx.x];
+        const int t = static_cast<int>(threadIdx.x);
+        if (t < kPcWords) pcw = reinterpret_cast<const uint64_t *>(a.side + ds)[t];
+        else if (t < kPcWords + kStWords) pcw = reinterpret_cast<const uint64_t *>(a.st + ds)[t - kPcWords];
     }
     // tile partials of this dataset, structure of arrays [NCOL][n_tiles_total]:
     // lane t adds tiles t, t + 256, t + 512, ... in that order; the loads of
@@ -714,13 +763,13 @@ __device__ __forceinline__ bool epilogue_body(const EpiArgs &a, int ds, CycleSta
 #pragma unroll
         for (int m = 0; m < G; ++m) {
             const int t = base + m * kBlock + threadIdx.x;
-            const bool in = t < nt;
+            const bool in = lane_ok && t < nt;
 #pragma unroll
             for (int col = 0; col < NCOL; ++col) q[col][m] = in ? a.partials[col * ntt + t0 + t] : 0.0;
         }
 #pragma unroll
         for (int m = 0; m < G; ++m) {
-            if (base + m * kBlock + static_cast<int>(threadIdx.x) < nt) {
+            if (lane_ok && base + m * kBlock + static_cast<int>(threadIdx.x) < nt) {
 #pragma unroll
                 for (int col = 0; col < NCOL; ++col) v[col] += q[col][m];
             }
@@ -731,26 +780,36 @@ __device__ __forceinline__ bool epilogue_body(const EpiArgs &a, int ds, CycleSta
 #pragma unroll
         for (int u = 0; u < kCsPer; ++u) {
             const int j = u * kBlock + static_cast<int>(threadIdx.x);
-            if (j < kCsWords) dc[j] = csw[u];
+            if (lane_ok && j < kCsWords) dc[j] = csw[u];
         }
-        if (static_cast<int>(threadIdx.x) < kPcWords) reinterpret_cast<uint64_t *>(&pc)[threadIdx.x] = pcw;
+        const int t = static_cast<int>(threadIdx.x);
+        if (t < kPcWords) reinterpret_cast<uint64_t *>(&pc)[t] = pcw;
+        else if (t < kPcWords + kStWords) reinterpret_cast<uint64_t *>(&sst)[t - kPcWords] = pcw;
     }
     __syncthreads();
     if (!c.active) return false;         // uniform: read from LDS after the barrier
-    block_sum<NCOL>(v, red);
+    const int64_t k_staged = c.k;        // (lane 0 changes c.k only after the barrier below)
+    (void)k_staged;
+    block_sum_at<NCOL>(v, red, static_cast<int>(threadIdx.x), lane_ok);
     double *trace = write_trace ? a.theta_trace + ds * a.trace_stride * M::P : nullptr;
     if constexpr (kStats) {
-        if (threadIdx.x == 0) finish_sweep<M, true>(c, st, v, pc);
+        if (threadIdx.x == 0) finish_sweep<M, true>(c, sst, v, pc);
         if constexpr (kFull) {
             __syncthreads();
             const int64_t qo = static_cast<int64_t>(ds) * a.nq;
-            theta_substeps<M>(c, st, trace, pc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, red);
+            theta_substeps<M>(c, sst, trace, pc, a.qx + qo, a.qw + qo, a.qeps + qo, a.nq, red);
         }
-        if (threadIdx.x == 0) prepare_next<M>(c, st, pc);
+        if (threadIdx.x == 0) prepare_next<M>(c, sst, pc);
     } else if (threadIdx.x == 0) {
-        finish_sweep<M>(c, st, v, pc);
-        if (kFull) theta_mh<M>(c, st, trace, pc.ln_u);
-        prepare_next<M>(c, st, pc);
+        // the chain's wavefront first at the SIMD while other wavefronts
+        // sweep (a fused cycle) or other workgroups run
+        __builtin_amdgcn_s_setprio(3);
+        finish_sweep<M>(c, sst, v, pc);
+        if (kFull) theta_mh<M>(c, sst, trace, pc.ln_u);
+        prepare_next<M>(c, sst, pc);
+        __builtin_amdgcn_s_setprio(0);
+    } else {
+        during(k_staged);
     }
     return true;
 }
@@ -763,9 +822,10 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpiArgs a)
 {
     __shared__ CycleState c;
     __shared__ Precomp pc;
+    __shared__ Statics sst;
     __shared__ double red[(kStats ? 1 + M::NS : 2) + 1][kBlock];
     const int ds = kSingle ? 0 : static_cast<int>(blockIdx.x);
-    if (!epilogue_body<M, kFull, kSingle, kStats>(a, ds, c, pc, red, true) && a.cs_out == a.cs) return;
+    if (!epilogue_body<M, kFull, kSingle, kStats>(a, ds, c, pc, sst, red, true) && a.cs_out == a.cs) return;
     stage_out(a.cs_out + ds, c);
 }
 
@@ -813,8 +873,10 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs<typename M::T> 
     constexpr int kRed = kCols * TPW > NCOL ? kCols * TPW : NCOL;
     __shared__ CycleState c;
     __shared__ Precomp pc;
+    __shared__ Statics st;
     __shared__ double red[kRed][kBlock];
     __shared__ uint32_t nacc_w[TPW][kWavesPerBlock];
+    __shared__ Precomp sd;
     const SweepArgs<T> &sw = a.sw;
     const bool side = blockIdx.x == 0;                 // uniform
     const int64_t n = sw.n_total;
@@ -836,10 +898,14 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs<typename M::T> 
             os[u] = M::load(sw.dd, i, n);
         }
     }
-    // the previous sweep's theta step, in every workgroup
-    epilogue_body<M, true, true, kStats>(a.epi, 0, c, pc, red, side);
+    // the previous sweep's theta step, in every workgroup; the side
+    // workgroup's wavefronts 1-3 take the next side values' draws (for sweep
+    // staged count + 2) while lane 0 runs the chain
+    const auto during_chain = [&](int64_t k) {
+        if (side) precompute_draws<M>(sd, k + 2, st);
+    };
+    epilogue_body<M, true, true, kStats>(a.epi, 0, c, pc, st, red, side, during_chain);
     __syncthreads();
-    const Statics &st = sw.st[0];
     if (side) {
         // the chain state: every word but the flags, which the tiles may raise
         // meanwhile, then this copy's flags; then the new proposal's side values
@@ -851,9 +917,8 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs<typename M::T> 
             if (q != kFlagsWord) dst[q] = src[q];
         if (threadIdx.x == 0 && c.flags != 0) atomicOr(&sw.cs[0].flags, c.flags);
         if (!c.active) return;                         // uniform: LDS after a barrier
-        __shared__ Precomp sd;
         __shared__ double zred[1][kBlock];
-        side_values<M>(c, st, sw.qx, sw.qw, sw.qeps, sw.nq, sd, zred, sw.side);
+        side_values<M>(c, st, sw.qx, sw.qw, sw.qeps, sw.nq, sd, zred, sw.side, !kStats);
         return;
     }
     if (!c.active) return;
@@ -886,6 +951,149 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs<typename M::T> 
             sw.partials[kCols * sw.n_tiles_total + g] =
                 static_cast<double>((nacc_w[u][0] + nacc_w[u][1]) + (nacc_w[u][2] + nacc_w[u][3]));
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused cycle in workgroups of TPW x 256 threads, one object per thread:
+// the 256-thread slice u steps tile TPW (w - 1) + u.  A workgroup holds TPW
+// tiles without stepping several objects per thread, and the redundant
+// theta step -- its reads of every tile partial, and its serial chain on
+// lane 0 -- is taken once per TPW tiles.  The first 256 threads take it
+// exactly as fused_kernel does; the tile sums are the same block sums per
+// tile, so the chain is bit for bit the two-kernel cycle's.  The side
+// workgroup (0) uses its extra wavefronts for the selection quadrature of
+// the new proposal while wavefronts 0 and 2 evaluate the proposal's
+// per-theta scalars, and takes the draws that depend only on the sweep
+// count while lane 0 runs the chain.
+// ---------------------------------------------------------------------------
+// The side values of side_values() in a workgroup of NT = 256 m threads
+// (m >= 2), the draws already in sd: the judged proposal's scalars by
+// wavefronts 0 and 2 while the threads from 256 on evaluate the quadrature
+// terms, NT - 256 at a time into zt; the first 256 threads add them in
+// block_log_z's order (lane t: nodes t, t + 256, ...), so ln Z has the same
+// bits as there.
+template <class M, int NT>
+__device__ __forceinline__ void side_values_wide(const CycleState &cs, const Statics &st, const double *qx,
+                                                 const double *qw, const double *qeps, int32_t nq, Precomp &sd,
+                                                 double (*zred)[kBlock], double *zt, Precomp *out)
+{
+    static_assert(NT > kBlock && NT % kBlock == 0, "a workgroup of several 256-thread slices");
+    constexpr int NQT = NT - kBlock;
+    const int tid = static_cast<int>(threadIdx.x);
+    const bool valid = cs.prop_valid != 0;
+    double judged[kMaxP];
+    for (int r = 0; r < M::P; ++r) judged[r] = cs.prop[r];
+    precompute_judged<M>(sd, judged, valid);
+    double zraw = 0.0;
+    if constexpr (M::kSelection) {
+        if (valid) {                   // uniform
+            const double zc[4] = {cs.zc_prop[0], cs.zc_prop[1], cs.zc_prop[2], cs.zc_prop[3]};
+            double v[1] = {0.0};
+            for (int c0 = 0; c0 < nq; c0 += NQT) {
+                if (tid >= kBlock) {
+                    const int j = c0 + tid - kBlock;
+                    if (j < nq) zt[tid - kBlock] = quad_term<M>(zc, qx, qw, qeps, j);
+                }
+                __syncthreads();
+                if (tid < kBlock) {
+#pragma unroll
+                    for (int m = 0; m < NQT / kBlock; ++m) {
+                        const int j = c0 + m * kBlock + tid;
+                        if (j < nq) v[0] = v[0] + zt[m * kBlock + tid];
+                    }
+                }
+                __syncthreads();
+            }
+            block_sum_at<1>(v, zred, tid, tid < kBlock);
+            zraw = log(v[0]);
+        }
+    }
+    if (tid == 0) sd.zraw = zraw;
+    __syncthreads();
+    if (tid == 0) {
+        sd.logz_used = (valid && M::kSelection) ? zraw - M::logz_shift(sd.aux_used) : 0.0;
+        sd.dconst = valid ? static_cast<double>(st.n) * M::dlf_const(cs.theta, judged, cs.aux_cur, sd.aux_used) : 0.0;
+    }
+    __syncthreads();
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(&sd);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(out);
+    for (int j = tid; j < static_cast<int>(sizeof(Precomp) / 8); j += NT) dst[j] = src[j];
+}
+
+template <class M, int TPW>
+__global__ __launch_bounds__(kBlock * TPW) void fused_wide_kernel(FusedArgs<typename M::T> a)
+{
+    static_assert(TPW >= 2, "one tile per workgroup is fused_kernel");
+    using T = typename M::T;
+    constexpr int NT = kBlock * TPW;
+    constexpr int D = M::D, NC = M::NC;
+    constexpr int kCols = 2;                          // sum log f, sum of log f changes
+    constexpr int NCOL = kCols + 1;
+    __shared__ CycleState c;
+    __shared__ Precomp pc;
+    __shared__ Statics st;
+    __shared__ double red[NCOL][kBlock];
+    __shared__ double tred[TPW][kCols][kBlock];
+    __shared__ uint32_t nacc_w[TPW][kWavesPerBlock];
+    __shared__ Precomp sd;
+    __shared__ double zt[NT - kBlock];
+    const SweepArgs<T> &sw = a.sw;
+    const bool side = blockIdx.x == 0;                 // uniform
+    const int64_t n = sw.n_total;
+    const int u = static_cast<int>(threadIdx.x) / kBlock, lane = static_cast<int>(threadIdx.x) % kBlock;
+    const int g = (static_cast<int>(blockIdx.x) - 1) * TPW + u;     // this slice's tile
+    const int64_t i = static_cast<int64_t>(g) * kBlock + lane;
+    // this thread's object first (positions past the end read the last one, unused)
+    T xs[D], Ss[NC];
+    uint32_t na = 0;
+    typename M::Obj os{};
+    if (!side) {
+        const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int j = 0; j < D; ++j) xs[j] = sw.chi[j * n + ic];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) Ss[e] = sw.chol[e * n + ic];
+        na = sw.acc[ic];
+        os = M::load(sw.dd, ic, n);
+    }
+    // the previous sweep's theta step, in every workgroup; the side
+    // workgroup's wavefronts 1-3 take the next side values' draws (for sweep
+    // staged count + 2) while lane 0 runs the chain
+    const auto during_chain = [&](int64_t k) {
+        if (side) precompute_draws<M>(sd, k + 2, st);
+    };
+    epilogue_body<M, true, true, false, NT>(a.epi, 0, c, pc, st, red, side, during_chain);
+    __syncthreads();
+    if (side) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&c);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(sw.cs);
+        constexpr int kWords = static_cast<int>(sizeof(CycleState) / 4);
+        constexpr int kFlagsWord = static_cast<int>(offsetof(CycleState, flags) / 4);
+        for (int q = threadIdx.x; q < kWords; q += NT)
+            if (q != kFlagsWord) dst[q] = src[q];
+        if (threadIdx.x == 0 && c.flags != 0) atomicOr(&sw.cs[0].flags, c.flags);
+        if (!c.active) return;                         // uniform: LDS after a barrier
+        side_values_wide<M, NT>(c, st, sw.qx, sw.qw, sw.qeps, sw.nq, sd, red, zt, sw.side);
+        return;
+    }
+    if (!c.active) return;
+    const TileView<T> tv{c.k + 1, st.obj_start, st.n, st.snap_cap, st.key0, st.key1, st.thin, c.active,
+                         st.snap_ring, static_cast<T>(c.eta_next), static_cast<T>(st.alpha_star)};
+    T kc[kKc];
+#pragma unroll
+    for (int q = 0; q < kKc; ++q) kc[q] = uniform_of(kc_of<T>(&c)[q]);
+    double v[kCols];
+    const bool accepted = step_object<M, false, false>(sw, 0, tv, i, i, xs, Ss, na, os, v,
+                                                       g < sw.n_tiles_total && i < n, kc);
+    const uint32_t nw = static_cast<uint32_t>(__popcll(__ballot(accepted)));
+    if ((lane & (kWave - 1)) == 0) nacc_w[u][lane / kWave] = nw;
+    block_sum_at<kCols>(v, tred[u], lane, true);
+    if (lane == 0 && g < sw.n_tiles_total) {
+#pragma unroll
+        for (int q = 0; q < kCols; ++q) sw.partials[q * sw.n_tiles_total + g] = v[q];
+        sw.partials[kCols * sw.n_tiles_total + g] =
+            static_cast<double>((nacc_w[u][0] + nacc_w[u][1]) + (nacc_w[u][2] + nacc_w[u][3]));
     }
 }
 
