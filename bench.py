@@ -59,6 +59,8 @@ def parse():
                              "bb1_lf", "gamma_lf_batch256", "serving", "marginal_gamma_lf_1d", "marginal_bb1_lf",
                              "marginal_normal_normal_1d", "streaming_gamma_lf_1d"])
     ap.add_argument("--horizon", type=float, default=60.0, help="serving: seconds of Poisson arrivals")
+    ap.add_argument("--serve-fused-up-to", type=int, default=4,
+                    help="serving: fused cycles while at most this many jobs are resident (0: never)")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second")
     ap.add_argument("--sat-jobs", type=int, default=200, help="serving: jobs in the saturation run")
     ap.add_argument("--seq-steps", type=int, default=200,
@@ -397,7 +399,7 @@ def bench_serving(args, torch, synth, hbm):
         return [sv.Job(i, t, seed, n, sw) for i, (t, seed, n, sw) in enumerate(arr)]
 
     pool = hbm.Pool(hbm.HBM_GAMMA_LF_1D, capacity=1 << 22, n_slots=128, max_cycles=5000, device="cuda:0")
-    ex = sv.PoolExecutor(pool, make, chunk=32)
+    ex = sv.PoolExecutor(pool, make, chunk=32, fused_up_to=args.serve_fused_up_to)
     # warm-up: graph capture and first-touch of the pool
     sv.serve(jobs_of([(0.0, 1, 2000, 64), (0.0, 2, 50000, 96)]), ex, prefetch=False)
 
@@ -436,7 +438,8 @@ def bench_serving(args, torch, synth, hbm):
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded gamma-LF jobs, N log-uniform on [1e3, 3e5], budgets in {1000, 2000, 5000})",
         "config": {"workload": "serving", "rate_per_s": args.rate, "horizon_s": args.horizon,
-                   "pool_objects": 1 << 22, "pool_slots": 128, "chunk_cycles": 32},
+                   "pool_objects": 1 << 22, "pool_slots": 128, "chunk_cycles": 32,
+                   "fused_cycles_up_to_jobs": ex.fused_up_to},
         "poisson": {"jobs": len(live), "p50_s": res["p50_s"], "p99_s": res["p99_s"], "mean_s": res["mean_s"],
                     "jobs_per_hour": res["jobs_per_hour"], "mean_resident": res["mean_resident"],
                     "gpu_busy_frac": res["busy_s"] / res["wall_s"], "wait_for_inputs_s": res["wait_for_inputs_s"]},

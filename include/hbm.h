@@ -311,8 +311,8 @@ HBM_API hbm_status theta_step(hbm_ctx *ctx, int32_t *out_accepted);
  *   - otherwise with use_graph != 0: replays of captured hipGraphs,
  *     floor(n / 32) of a 32-cycle graph and one of a graph of the remaining
  *     n mod 32 cycles (captured on first need, again when the remainder
- *     changes; prepare_cycles captures ahead); in mode HBM_CYCLES_FUSED a
- *     one-dataset context's graphs hold fused cycles (set_cycle_mode).
+ *     changes; prepare_cycles captures ahead); in mode HBM_CYCLES_FUSED the
+ *     graphs hold fused cycles (set_cycle_mode).
  * A slot whose budget is reached stops at that cycle.  Asynchronous. */
 HBM_API hbm_status run_cycles(hbm_ctx *ctx, int64_t n_cycles, int32_t use_graph);
 
@@ -323,14 +323,15 @@ HBM_API hbm_status prepare_cycles(hbm_ctx *ctx, int64_t n_cycles);
 
 /* mode: HBM_CYCLES_AUTO (default) lets run_cycles use the persistent
  * launch where it can; HBM_CYCLES_GRAPH restricts it to graphs of the
- * two-kernel cycle; HBM_CYCLES_FUSED makes the graphs of a one-dataset
- * context (init_chains) hold fused cycles: after the first sweep kernel, one
- * launch per cycle in which every workgroup takes the previous sweep's theta
- * step itself (from that sweep's tile partials, in the epilogue's fixed
- * order) and then sweeps its tiles, buffers alternating between cycles, and
- * one epilogue at the end -- the same chain, bit for bit.  Contexts with
- * several slots keep the two-kernel graphs.  Changing to or from
- * HBM_CYCLES_FUSED drops the captured graphs.  Synchronous. */
+ * two-kernel cycle; HBM_CYCLES_FUSED makes the graphs hold fused cycles:
+ * after the first sweep kernel, one launch per cycle in which every
+ * workgroup takes the previous sweep's theta step itself (from that sweep's
+ * tile partials, in the epilogue's fixed order) and then sweeps its tiles,
+ * buffers alternating between cycles, and one epilogue at the end -- the
+ * same chains, bit for bit.  In a context with several slots each tile's
+ * workgroup takes its own dataset's theta step (one tile per workgroup,
+ * whatever set_launch chose).  Changing to or from HBM_CYCLES_FUSED drops
+ * the captured graphs.  Synchronous. */
 HBM_API hbm_status set_cycle_mode(hbm_ctx *ctx, int32_t mode);
 
 /* How run_cycles has issued cycles since the context was created:
@@ -441,7 +442,7 @@ HBM_API hbm_status set_occupancy(hbm_ctx *ctx, int32_t groups_per_cu);
  * cap of 2 workgroups per compute unit (6-8); then the persistent launch
  * (9; one-dataset contexts in mode HBM_CYCLES_AUTO, else not timed); then
  * graphs of fused cycles with tiles per workgroup 1, 2, 4 and no cap
- * (10-12; one-dataset contexts, else not timed).  Each
+ * (10-12; contexts with several slots time candidate 10 only).  Each
  * runs 8 warm-up cycles then trial_cycles cycles timed by hipEvents on the
  * context's stream; the fastest is kept: its shape and cap, and the cycle
  * mode (HBM_CYCLES_AUTO when the persistent launch won, HBM_CYCLES_FUSED when

@@ -70,7 +70,7 @@ struct Launch {
     // n full cycles as one persistent cooperative launch; *launched = false
     // (and nothing enqueued) when the context or device cannot take it
     hbm_status (*cycles)(CtxImpl *, int64_t n, bool *launched);
-    hbm_status (*fused)(CtxImpl *, int64_t len);  // len >= 2 fused cycles of a one-dataset context
+    hbm_status (*fused)(CtxImpl *, int64_t len);  // len >= 2 fused cycles
 };
 
 // Host mirror of one slot.  Every field follows from the calls made, so the
@@ -382,12 +382,13 @@ struct Ops {
                                a);
     }
 
-    // len >= 2 full cycles of a one-dataset context with one launch per
-    // cycle after the first: the sweep kernel (its state, partials and side
-    // values in the primary buffers), len - 1 fused kernels, each taking the
-    // previous sweep's theta step and running the next sweep with the buffers
-    // alternating, then the last sweep's epilogue, which leaves the state in
-    // the primary buffer.
+    // len >= 2 full cycles with one launch per cycle after the first: the
+    // sweep kernel (its state, partials and side values in the primary
+    // buffers), len - 1 fused kernels, each taking the previous sweep's theta
+    // step and running the next sweep with the buffers alternating, then the
+    // last sweep's epilogue, which leaves the state in the primary buffer.
+    // A context with several datasets runs one tile per workgroup
+    // (fused_pool_kernel) whatever its launch shape.
     static hbm_status fused(CtxImpl *c, int64_t len)
     {
         if constexpr (M::NS > 0) {
@@ -400,9 +401,12 @@ struct Ops {
     static hbm_status fused_as(CtxImpl *c, int64_t len)
     {
         const SweepArgs<T> a = sweep_args(c, nullptr);
-        const int tpw = c->tpw;
-        const dim3 grid(static_cast<unsigned>(1 + (c->n_tiles + tpw - 1) / tpw));
-        if (tpw == 4) launch_sweep<false, 4, true, kStats>(c, grid, a, nullptr, nullptr);
+        const bool one = single(c);
+        const int tpw = one ? c->tpw : 1;
+        const int32_t n_t = one ? c->n_tiles : c->ext_tiles;
+        const dim3 grid(static_cast<unsigned>(a.n_ds + (n_t + tpw - 1) / tpw));
+        if (!one) launch_sweep<false, 1, false, kStats>(c, grid, a, nullptr, nullptr);
+        else if (tpw == 4) launch_sweep<false, 4, true, kStats>(c, grid, a, nullptr, nullptr);
         else if (tpw == 2) launch_sweep<false, 2, true, kStats>(c, grid, a, nullptr, nullptr);
         else launch_sweep<false, 1, true, kStats>(c, grid, a, nullptr, nullptr);
         LAUNCHCHK(c, "sweep_kernel");
@@ -420,7 +424,8 @@ struct Ops {
             f.epi.cs = f.epi.cs_out = csb[cur];
             f.epi.partials = pb[cur];
             f.epi.side = sb[cur];
-            const hbm_status st = tpw == 4   ? launch_fused<4, kStats>(c, grid, f)
+            const hbm_status st = !one       ? launch_fused_pool<kStats>(c, grid, f)
+                                  : tpw == 4 ? launch_fused<4, kStats>(c, grid, f)
                                   : tpw == 2 ? launch_fused<2, kStats>(c, grid, f)
                                              : launch_fused<1, kStats>(c, grid, f);
             if (st != HBM_OK) return st;
@@ -432,8 +437,29 @@ struct Ops {
         e.cs_out = c->cs;
         e.partials = pb[cur];
         e.side = sb[cur];
-        hipLaunchKernelGGL((epilogue_kernel<M, true, true, kStats>), dim3(1), dim3(kBlock), 0, c->stream, e);
+        if (one)
+            hipLaunchKernelGGL((epilogue_kernel<M, true, true, kStats>), dim3(1), dim3(kBlock), 0, c->stream, e);
+        else
+            hipLaunchKernelGGL((epilogue_kernel<M, true, false, kStats>), dim3(c->ext_slots), dim3(kBlock), 0,
+                               c->stream, e);
         LAUNCHCHK(c, "epilogue_kernel");
+        return HBM_OK;
+    }
+
+    template <bool kStats>
+    static hbm_status launch_fused_pool(CtxImpl *c, dim3 grid, const FusedArgs<T> &f)
+    {
+        void (*fn)(FusedArgs<T>) = &fused_pool_kernel<M, kStats>;
+        const size_t lds = c->occ_cap > 0 ? occupancy_lds(c, reinterpret_cast<const void *>(fn)) : 0;
+        if (c->timing) {
+            hipEvent_t e0 = take_event(c), e1 = take_event(c);
+            if (!e0 || !e1) return fail(c, HBM_ENOMEM, "hipEventCreate failed");
+            c->ev_pending.push_back(e0);
+            c->ev_pending.push_back(e1);
+            hipExtLaunchKernelGGL(fn, grid, dim3(kBlock), lds, c->stream, e0, e1, 0, f);
+        } else {
+            hipLaunchKernelGGL(fn, grid, dim3(kBlock), lds, c->stream, f);
+        }
         return HBM_OK;
     }
 
@@ -1417,7 +1443,7 @@ hbm_status capture_cycles(CtxImpl *c, int64_t len, hipGraph_t *g_out, hipGraphEx
     c->stream = c->capture_stream;
     HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
     hbm_status st = HBM_OK;
-    if (c->cycle_mode == HBM_CYCLES_FUSED && single(c) && len >= 2)
+    if (c->cycle_mode == HBM_CYCLES_FUSED && len >= 2)
         st = c->ops->fused(c, len);
     else
         for (int64_t j = 0; j < len && st == HBM_OK; ++j) st = c->ops->sweep(c, true, nullptr);
@@ -1485,7 +1511,7 @@ hbm_status issue_cycles(CtxImpl *c, int64_t n_cycles, bool use_graph)
         hbm_status st = c->ops->cycles(c, n_cycles, &launched);
         if (st != HBM_OK || launched) return st;
     }
-    if (use_graph && c->timing && c->cycle_mode == HBM_CYCLES_FUSED && single(c) && n_cycles >= 2) {
+    if (use_graph && c->timing && c->cycle_mode == HBM_CYCLES_FUSED && n_cycles >= 2) {
         // fused cycles as plain launches, each fused kernel timed
         hbm_status st = c->ops->fused(c, n_cycles);
         if (st != HBM_OK) return st;
@@ -2308,8 +2334,9 @@ hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t out_choice[3], d
         // candidates: the two-kernel cycle with tiles per workgroup {1, 2, 4}
         // under a cap of {none, 4, 2} workgroups per compute unit, then the
         // persistent launch (one-dataset contexts in mode HBM_CYCLES_AUTO),
-        // then fused cycles with tiles per workgroup {1, 2, 4} (one-dataset
-        // contexts).  how: 0 two-kernel graphs, 1 persistent, 2 fused graphs.
+        // then fused cycles with tiles per workgroup {1, 2, 4} (one tile per
+        // workgroup for contexts with several datasets).  how: 0 two-kernel
+        // graphs, 1 persistent, 2 fused graphs.
         struct Cand { int32_t tpw, cap, how; };
         Cand cand[HBM_TUNE_CANDIDATES];
         int q = 0;
@@ -2321,14 +2348,14 @@ hbm_status autotune(hbm_ctx *ctx, int32_t trial_cycles, int32_t out_choice[3], d
         const int32_t keep_tpw = c->tpw, keep_cap = c->occ_cap;
         double best = HUGE_VAL;
         Cand pick{keep_tpw, keep_cap,
-                  mode == HBM_CYCLES_AUTO && single(c) ? 1 : (mode == HBM_CYCLES_FUSED && single(c) ? 2 : 0)};
+                  mode == HBM_CYCLES_AUTO && single(c) ? 1 : (mode == HBM_CYCLES_FUSED ? 2 : 0)};
         hbm_status st = HBM_OK;
         for (int j = 0; j < HBM_TUNE_CANDIDATES && st == HBM_OK; ++j) {
             const Cand &cd = cand[j];
             if (out_us) out_us[j] = static_cast<double>(NAN);
             // every candidate runs its cycles (the trace counts them), timed or not
             const bool usable = cd.how == 0 || (cd.how == 1 && mode == HBM_CYCLES_AUTO && single(c) && !c->stats_mode) ||
-                                (cd.how == 2 && single(c));
+                                (cd.how == 2 && (single(c) || cd.tpw == 1));
             const int32_t cm = cd.how == 1 ? HBM_CYCLES_AUTO : cd.how == 2 ? HBM_CYCLES_FUSED : HBM_CYCLES_GRAPH;
             if ((st = set_cycle_mode(ctx, cm)) != HBM_OK) break;
             if (cd.how != 1) {

@@ -1097,6 +1097,93 @@ __global__ __launch_bounds__(kBlock * TPW) void fused_wide_kernel(FusedArgs<type
     }
 }
 
+// ---------------------------------------------------------------------------
+// The fused cycle of a context with several datasets (a batch or a pool),
+// one tile per workgroup: workgroup ds < n_ds is dataset ds's side
+// workgroup (it takes the dataset's theta step, writes its state, trace row
+// and the new proposal's side values), every other workgroup a tile, which
+// takes the theta step of its own dataset -- the reduction of that
+// dataset's tile partials only -- and steps its objects.  A dataset that is
+// off keeps its state (copied to the other buffer) and its tiles do
+// nothing, as in the two-kernel cycle.
+// ---------------------------------------------------------------------------
+template <class M, bool kStats>
+__global__ __launch_bounds__(kBlock) void fused_pool_kernel(FusedArgs<typename M::T> a)
+{
+    using T = typename M::T;
+    constexpr int D = M::D, NC = M::NC;
+    constexpr int kCols = kStats ? 1 + M::NS : 2;     // FP64 sums per tile besides the accepted count
+    constexpr int NCOL = kCols + 1;
+    __shared__ CycleState c;
+    __shared__ Precomp pc;
+    __shared__ Statics st;
+    __shared__ double red[NCOL][kBlock];
+    __shared__ uint32_t nacc_w[kWavesPerBlock];
+    __shared__ Precomp sd;
+    const SweepArgs<T> &sw = a.sw;
+    const int n_side = sw.n_ds;
+    const bool side = static_cast<int>(blockIdx.x) < n_side;      // uniform
+    const int g = static_cast<int>(blockIdx.x) - n_side;          // tile of a tile workgroup
+    const int ds = side ? static_cast<int>(blockIdx.x) : (g < sw.n_tiles_total ? sw.tile_ds[g] : -1);
+    if (ds < 0) return;                                           // an unused tile
+    const int64_t n = sw.n_total;
+    const int64_t i = static_cast<int64_t>(g) * kBlock + threadIdx.x;
+    // the object first (tile workgroups; every position below n_total lies
+    // inside the caller's buffers)
+    T xs[D], Ss[NC];
+    uint32_t na = 0;
+    typename M::Obj os{};
+    if (!side) {
+        const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int j = 0; j < D; ++j) xs[j] = sw.chi[j * n + ic];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) Ss[e] = sw.chol[e * n + ic];
+        na = sw.acc[ic];
+        os = M::load(sw.dd, ic, n);
+    }
+    // the dataset's previous theta step; the side workgroup's wavefronts 1-3
+    // take the next side values' draws (sweep staged count + 2) meanwhile
+    const auto during_chain = [&](int64_t k) {
+        if (side) precompute_draws<M>(sd, k + 2, st);
+    };
+    epilogue_body<M, true, false, kStats>(a.epi, ds, c, pc, st, red, side, during_chain);
+    __syncthreads();
+    if (side) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&c);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(sw.cs + ds);
+        constexpr int kWords = static_cast<int>(sizeof(CycleState) / 4);
+        constexpr int kFlagsWord = static_cast<int>(offsetof(CycleState, flags) / 4);
+        for (int q = threadIdx.x; q < kWords; q += kBlock)
+            if (q != kFlagsWord) dst[q] = src[q];
+        if (threadIdx.x == 0 && c.flags != 0) atomicOr(&sw.cs[ds].flags, c.flags);
+        if (!c.active) return;                         // uniform: LDS after a barrier
+        __shared__ double zred[1][kBlock];
+        const int64_t qo = static_cast<int64_t>(ds) * sw.nq;
+        side_values<M>(c, st, sw.qx + qo, sw.qw + qo, sw.qeps + qo, sw.nq, sd, zred, sw.side + ds, !kStats);
+        return;
+    }
+    if (!c.active) return;
+    const TileView<T> tv{c.k + 1, st.obj_start, st.n, st.snap_cap, st.key0, st.key1, st.thin, c.active,
+                         st.snap_ring, static_cast<T>(c.eta_next), static_cast<T>(st.alpha_star)};
+    T kc[kKc];
+#pragma unroll
+    for (int q = 0; q < kKc; ++q) kc[q] = uniform_of(kc_of<T>(&c)[q]);
+    const int64_t il = i - st.obj_start;
+    double v[kCols];
+    const bool accepted =
+        step_object<M, false, kStats>(sw, ds, tv, il, i, xs, Ss, na, os, v, il >= 0 && il < st.n, kc);
+    const uint32_t nw = static_cast<uint32_t>(__popcll(__ballot(accepted)));
+    if ((threadIdx.x & (kWave - 1)) == 0) nacc_w[threadIdx.x / kWave] = nw;
+    block_sum<kCols>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < kCols; ++q) sw.partials[q * sw.n_tiles_total + g] = v[q];
+        sw.partials[kCols * sw.n_tiles_total + g] =
+            static_cast<double>((nacc_w[0] + nacc_w[1]) + (nacc_w[2] + nacc_w[3]));
+    }
+}
+
 // Theta step on its own, after a ram_sweep (plain cycle), one workgroup per dataset.
 template <class M, bool kStats = false>
 __global__ __launch_bounds__(kBlock) void theta_kernel(EpiArgs a)

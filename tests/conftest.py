@@ -38,6 +38,13 @@ def batch_means(x: np.ndarray, n_batches: int = None):
 # understate the error ~1.8-fold, while 30 batches of 800 draws do not.
 MOMENT_BATCHES = 30
 
+# Key of the oracle chains that free-run moment tests compare with a GPU
+# chain: a different Philox key from the workload's, so that the two chains
+# are independent (with the same key they would agree draw for draw until
+# rounding first flips a decision, and the combined standard error of their
+# difference would be too large).
+INDEPENDENT_SEED = 1000003
+
 
 def moment_scores(a: np.ndarray, b: np.ndarray, n_batches: int = MOMENT_BATCHES):
     """Per component of two chains [M][p]: the difference of their means and

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from conftest import assert_moments_agree, moment_scores
+from conftest import INDEPENDENT_SEED, assert_moments_agree, moment_scores
 from lockstep import lockstep_step
 
 torch = pytest.importorskip("torch")
@@ -88,7 +88,9 @@ def test_bb1_free_run_posterior_moments(hbm):
     s = hbm.Sampler(wl, max_cycles=m)
     s.run_cycles(m)
     tg = s.theta_trace()[m // 5:]
-    o = oracle.Oracle(wl)
+    # an independent oracle chain: its own Philox key, so the two chains'
+    # batch-means errors add as the combined standard error assumes
+    o = oracle.Oracle(wl, seed=INDEPENDENT_SEED)
     st = o.initial_state()
     to, _ = o.run(st, m)
     to = to[m // 5:]
