@@ -844,6 +844,23 @@ __device__ __forceinline__ double uniform_of(double v)
     return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 
+// The chain state c of a fused launch written to the other buffer by the
+// NT threads of a side workgroup: every word but the flags, which this
+// launch's tiles may raise meanwhile (atomicOr in step_object), then c's
+// flags OR-ed in (flags only accumulate, so the word ends as c's flags plus
+// any the tiles raise).
+template <int NT>
+__device__ __forceinline__ void publish_state(CycleState *dst, const CycleState &c)
+{
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&c);
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+    constexpr int kWords = static_cast<int>(sizeof(CycleState) / 4);
+    constexpr int kFlagsWord = static_cast<int>(offsetof(CycleState, flags) / 4);
+    for (int q = threadIdx.x; q < kWords; q += NT)
+        if (q != kFlagsWord) d[q] = src[q];
+    if (threadIdx.x == 0 && c.flags != 0) atomicOr(&dst->flags, c.flags);
+}
+
 // ---------------------------------------------------------------------------
 // One full cycle in one launch, for a context that holds one dataset: the
 // theta step of the previous sweep, then this sweep.  Every workgroup takes
@@ -907,15 +924,8 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(FusedArgs<typename M::T> 
     epilogue_body<M, true, true, kStats>(a.epi, 0, c, pc, st, red, side, during_chain);
     __syncthreads();
     if (side) {
-        // the chain state: every word but the flags, which the tiles may raise
-        // meanwhile, then this copy's flags; then the new proposal's side values
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(&c);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(sw.cs);
-        constexpr int kWords = static_cast<int>(sizeof(CycleState) / 4);
-        constexpr int kFlagsWord = static_cast<int>(offsetof(CycleState, flags) / 4);
-        for (int q = threadIdx.x; q < kWords; q += kBlock)
-            if (q != kFlagsWord) dst[q] = src[q];
-        if (threadIdx.x == 0 && c.flags != 0) atomicOr(&sw.cs[0].flags, c.flags);
+        // the chain state, then the new proposal's side values
+        publish_state<kBlock>(sw.cs, c);
         if (!c.active) return;                         // uniform: LDS after a barrier
         __shared__ double zred[1][kBlock];
         side_values<M>(c, st, sw.qx, sw.qw, sw.qeps, sw.nq, sd, zred, sw.side, !kStats);
@@ -1066,13 +1076,7 @@ __global__ __launch_bounds__(kBlock * TPW) void fused_wide_kernel(FusedArgs<type
     epilogue_body<M, true, true, false, NT>(a.epi, 0, c, pc, st, red, side, during_chain);
     __syncthreads();
     if (side) {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(&c);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(sw.cs);
-        constexpr int kWords = static_cast<int>(sizeof(CycleState) / 4);
-        constexpr int kFlagsWord = static_cast<int>(offsetof(CycleState, flags) / 4);
-        for (int q = threadIdx.x; q < kWords; q += NT)
-            if (q != kFlagsWord) dst[q] = src[q];
-        if (threadIdx.x == 0 && c.flags != 0) atomicOr(&sw.cs[0].flags, c.flags);
+        publish_state<NT>(sw.cs, c);
         if (!c.active) return;                         // uniform: LDS after a barrier
         side_values_wide<M, NT>(c, st, sw.qx, sw.qw, sw.qeps, sw.nq, sd, red, zt, sw.side);
         return;
@@ -1150,13 +1154,7 @@ __global__ __launch_bounds__(kBlock) void fused_pool_kernel(FusedArgs<typename M
     epilogue_body<M, true, false, kStats>(a.epi, ds, c, pc, st, red, side, during_chain);
     __syncthreads();
     if (side) {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(&c);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(sw.cs + ds);
-        constexpr int kWords = static_cast<int>(sizeof(CycleState) / 4);
-        constexpr int kFlagsWord = static_cast<int>(offsetof(CycleState, flags) / 4);
-        for (int q = threadIdx.x; q < kWords; q += kBlock)
-            if (q != kFlagsWord) dst[q] = src[q];
-        if (threadIdx.x == 0 && c.flags != 0) atomicOr(&sw.cs[ds].flags, c.flags);
+        publish_state<kBlock>(sw.cs + ds, c);
         if (!c.active) return;                         // uniform: LDS after a barrier
         __shared__ double zred[1][kBlock];
         const int64_t qo = static_cast<int64_t>(ds) * sw.nq;
