@@ -135,3 +135,65 @@ def test_slots_limit_concurrency():
                key=lambda x: (x[0], x[1]))
     live = np.cumsum([d for _, d in t])
     assert live.max() <= 2
+
+
+class _ModePool:
+    """Stands in for a Pool in PoolExecutor: records cycle-mode changes."""
+
+    def __init__(self):
+        self.tiles = np.full(64, -1)
+        self.max_cycles = 1000
+        self.device = "cpu"
+        self.modes = []
+        self.next_slot = 0
+
+    def set_cycle_mode(self, mode):
+        self.modes.append(mode)
+
+    def fits(self, n):
+        return True
+
+    def admit(self, wls, budgets, **kw):
+        self.next_slot += 1
+        return [self.next_slot - 1]
+
+    def run_cycles(self, n):
+        pass
+
+    def run_streamed(self, n, chunk, on_rows):
+        pass
+
+    def finished(self):
+        return []
+
+    def retire(self, slot):
+        return np.zeros((0, 2))
+
+
+def test_pool_executor_runs_fused_cycles_only_with_few_jobs(monkeypatch):
+    import torch
+    import paper_2105_08026_amd as hbm
+    from paper_2105_08026_amd.serve import PoolExecutor
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    pool = _ModePool()
+    ex = PoolExecutor(pool, make_workload=None, chunk=8, fused_up_to=2)
+    jobs = [Job(j, 0.0, j, 1000, 100) for j in range(3)]
+    ex.admit(jobs[0], None)
+    ex.run()
+    assert pool.modes == [hbm.HBM_CYCLES_FUSED]
+    ex.run()                                   # unchanged: no new mode
+    assert pool.modes == [hbm.HBM_CYCLES_FUSED]
+    ex.admit(jobs[1], None)
+    ex.admit(jobs[2], None)
+    ex.run()                                   # three resident: two-kernel cycles
+    assert pool.modes[-1] == hbm.HBM_CYCLES_GRAPH and len(pool.modes) == 2
+    ex.retire(1)
+    ex.retire(2)
+    ex.run()
+    assert pool.modes[-1] == hbm.HBM_CYCLES_FUSED and len(pool.modes) == 3
+    # a streamed executor keeps the two-kernel cycle
+    pool2 = _ModePool()
+    ex2 = PoolExecutor(pool2, make_workload=None, chunk=8, fused_up_to=4, on_rows=lambda *a: None)
+    ex2.admit(jobs[0], None)
+    ex2.run()
+    assert ex2.fused_up_to == 0 and pool2.modes == [hbm.HBM_CYCLES_GRAPH]
