@@ -99,3 +99,18 @@ def test_init_chains_rejects_bad_theta_modes_before_touching_the_device():
     bb = synth.bb1_lf(n=50, seed=2, chunk=100_000)
     st, msg, out = _reject(hbm, hbm.make_config(bb, max_cycles=10, theta_substeps=2), bb.theta0)
     assert st == hbm.HBM_EINVAL and "sufficient statistics" in msg and not out
+
+
+def test_init_chains_rejects_bad_sizes_before_touching_the_device():
+    """An empty catalog and one past the index range are refused with
+    HBM_EINVAL by the host checks alone."""
+    import paper_2105_08026_amd as hbm
+    import synth
+    if not os.path.exists(hbm.LIB_PATH):
+        pytest.skip("library not built")
+    lf = synth.gamma_lf_1d(n=300, seed=3, fth=389.75)
+    for n in (0, -5, 2 ** 31):
+        cfg = hbm.make_config(lf, max_cycles=10)
+        cfg.n_objects = n
+        st, msg, out = _reject(hbm, cfg, lf.theta0)
+        assert st == hbm.HBM_EINVAL and "n_objects" in msg and not out, (n, msg)

@@ -65,6 +65,7 @@ BATCHES = {
     "lf3d": lambda: [synth.gamma_lf_3d(n=n, seed=50 + j, fth=FTH) for j, n in enumerate((700, 2100, 300))],
     "nn3d": lambda: [synth.normal_normal_3d(n=n, seed=60 + j) for j, n in enumerate((500, 257))],
     "bb1": lambda: [synth.bb1_lf(n=n, seed=70 + j, chunk=1_000_000) for j, n in enumerate((900, 3000))],
+    "tiny": lambda: [synth.gamma_lf_1d(n=n, seed=90 + j, fth=FTH) for j, n in enumerate((1, 2, 257))],
 }
 
 

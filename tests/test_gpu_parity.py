@@ -303,3 +303,33 @@ def test_lf3d_free_run_posterior_moments(hbm):
     for j, (z, zv, mg, sg, mo, so) in enumerate(scores):
         _say(f"  theta[{j}] gpu {mg:.5f}±{sg:.5f} oracle {mo:.5f}±{so:.5f} z={z:.2f}; variance z={zv:.2f}")
     _say(f"  rms z over the means and variances {assert_moments_agree(scores):.2f}")
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_tiny_catalogs(hbm, n):
+    """Degenerate sizes: one and two objects (one partial tile, 255 or 254
+    idle lanes).  The normal-normal chain equals the oracle's; the LF chain
+    runs in lockstep with it; every issue mode gives the same chain."""
+    _say(f"tiny catalogs: N={n}")
+    wl = synth.normal_normal_1d(n=n, seed=62)
+    s = hbm.Sampler(wl, max_cycles=100)
+    s.run_cycles(100)
+    o = oracle.Oracle(wl)
+    to, _ = o.run(o.initial_state(), 100)
+    np.testing.assert_allclose(s.theta_trace(), to, rtol=1e-9, atol=1e-9)
+    lf = synth.gamma_lf_1d(n=n, seed=61, fth=389.75)
+    a = hbm.Sampler(lf, max_cycles=60)
+    ol = oracle.Oracle(lf)
+    for _ in range(10):
+        lockstep_step(a, ol, "f32")
+    runs = []
+    for mode in (hbm.HBM_CYCLES_GRAPH, hbm.HBM_CYCLES_FUSED, hbm.HBM_CYCLES_AUTO):
+        b = hbm.Sampler(lf, max_cycles=70)
+        b.set_cycle_mode(mode)
+        b.run_cycles(70)
+        runs.append((b.theta_trace(), b.state()))
+        b.close()
+    for tr, st in runs[1:]:
+        assert np.array_equal(tr, runs[0][0])
+        for x, y in zip(st, runs[0][1]):
+            assert np.array_equal(x, y)
