@@ -106,10 +106,11 @@ def test_fused_full_catalog(hbm):
     b.close()
 
 
-def test_fused_snapshots(hbm):
+@pytest.mark.parametrize("tpw", [1, 2])
+def test_fused_snapshots(hbm, tpw):
     wl = synth.gamma_lf_1d(n=2600, seed=96, fth=FTH)
-    _say("fused cycles with latent snapshots every 7 sweeps")
-    a = _fused(hbm, wl, 100, thin=7)
+    _say(f"fused cycles with latent snapshots every 7 sweeps, {tpw} tiles per workgroup")
+    a = _fused(hbm, wl, 100, tpw=tpw, thin=7)
     a.run_cycles(60)
     a.run_cycles(40)
     b = hbm.Sampler(wl, max_cycles=100, thin=7)
@@ -118,12 +119,13 @@ def test_fused_snapshots(hbm):
     assert np.array_equal(a.chi_snapshots(0, 14), b.chi_snapshots(0, 14))
 
 
+@pytest.mark.parametrize("tpw", [1, 2])
 @pytest.mark.parametrize("make", [lambda: synth.gamma_lf_1d(n=4000, seed=97, fth=FTH),
                                   lambda: synth.normal_normal_3d(n=900, seed=6)])
-def test_fused_theta_substeps(hbm, make):
+def test_fused_theta_substeps(hbm, make, tpw):
     wl = make()
-    _say(f"fused cycles, 4 theta steps per cycle from sufficient statistics: {wl.name} N={wl.n}")
-    a = _fused(hbm, wl, 80, theta_substeps=4)
+    _say(f"fused cycles, 4 theta steps per cycle from sufficient statistics: {wl.name} N={wl.n}, {tpw} tiles per workgroup")
+    a = _fused(hbm, wl, 80, tpw=tpw, theta_substeps=4)
     a.run_cycles(80)
     b = hbm.Sampler(wl, max_cycles=80, theta_substeps=4)
     b.run_cycles(80, use_graph=False)
