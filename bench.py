@@ -785,7 +785,12 @@ def main():
                 "traffic_bytes_per_launch": traffic["bytes_per_launch"] if traffic else None,
                 "algorithmic_bytes_per_launch": bpu * wl.n, "bytes_per_update": bpu,
                 "traffic_source": traffic["source"] if traffic else "no counter summary for the current kernel sources",
-                "kernel": f"fused_kernel<{wl.name}>", "kernel_ms": dom_ms, "launches_timed": n_launch_dom,
+                # the kernel the launch shape selects; the committed counters of the
+                # fused cycle were taken with two tiles per workgroup
+                "kernel": (f"fused_wide_kernel<{wl.name}, {pick['tiles_per_group']}>" if pick["tiles_per_group"] > 1
+                           else f"fused_kernel<{wl.name}>"),
+                "traffic_counted_with_tiles_per_workgroup": 2,
+                "kernel_ms": dom_ms, "launches_timed": n_launch_dom,
                 "valu": valu_roof(traffic, dom_ms), **planned_frac(wl.name, wl.n, dom_ms),
                 "sweep_kernel_two_kernel_cycle": sweep_roof}
     else:
