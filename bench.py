@@ -200,12 +200,19 @@ def side_c2(torch, synth, hbm, n: int = 1_000_000, cycles: int = 64):
     s.close()
     bpu = BYTES_PER_UPDATE[wl.name]
     gbs = bpu * n / (kern_ms * 1e-3) / 1e9
+    # counted HBM bytes from the committed counter summary of this sweep kernel
+    # (one tile per workgroup), over the same event-timed duration
+    traffic = measured_traffic(wl.name, n)
     return {"workload": wl.name, "n_objects": n, "cycles_timed": cycles, "us_per_cycle": 1e6 * wall / cycles,
             "issue_mode": mode, "us_per_cycle_two_kernel_graph_replay": 1e6 * wall_graph / cycles,
             "updates_per_s": n * cycles / wall, "tiles_per_workgroup": pick["tiles_per_group"],
             "groups_per_cu_cap": pick["groups_per_cu"], "autotune_us_per_cycle": tune_table(hbm, tuned),
             "sweep_kernel_us": 1e3 * kern_ms, "launches_timed": n_launch, "bytes_per_update": bpu,
-            "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS, **planned_frac(wl.name, n, kern_ms)}
+            "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "traffic_GBps": (traffic["bytes_per_launch"] / (kern_ms * 1e-3) / 1e9) if traffic else None,
+            "traffic_bytes_per_launch": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_source": traffic["source"] if traffic else "no counter summary for the current kernel sources",
+            **planned_frac(wl.name, n, kern_ms)}
 
 
 def accuracy_vs_oracle(wl, s, o):
